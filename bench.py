@@ -1,0 +1,265 @@
+"""Throughput of the MRPT voting-search query path on one MI355X.
+
+One step = one query call over the whole batch of the sift-like workload
+(n = 1,000,000 points, d = 128, 10,000 queries, T = 100 trees, depth 12,
+k = 10, v = 3): routing, voting and exact search in S, all in the library's
+HIP kernels, inputs resident in HBM.  Two arms on the same index: float32
+exact search (the headline value) and bfloat16 prefilter + float32 rerank +
+float64 recheck.  Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "queries/sec at recall@10=0.9 (1M×128, k=10); FP32 plain vs BF16+rerank"
+KERNEL_SRC = os.path.join(ROOT, "paper_1509_06957_amd", "csrc", "kernels_query.hip")
+STAGES = ("route", "vote", "search")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="sift_like")
+    p.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
+    p.add_argument("--recall-sample", type=int, default=500)
+    p.add_argument("--cpu-sample", type=int, default=10000)
+    return p.parse_args()
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(kernel, workload_key):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_key}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                vals[key.strip()] = val.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the query path is "
+              "query-parallel and would shard by splitting the batch across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1509_06957_amd import mrpt
+    from paper_1509_06957_amd import workloads as W
+
+    w = W.ALL[args.workload]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    X = W.data(w)
+    Q = W.queries(w)
+    log(f"workload {w.name}: generated in {time.perf_counter() - t0:.1f}s")
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = mrpt.Index(Xd, w.T, w.depth, w.a, w.index_seed)
+    build_s = time.perf_counter() - t0
+    log(f"index built in {build_s:.1f}s")
+    nq, k, v = w.nq, w.k, w.v
+
+    # |S| per query and the leaf sizes visited (for the algorithmic bytes)
+    s_count = torch.zeros(nq, dtype=torch.int32, device="cuda")
+    ix.query(Qd, k, v, s_count=s_count)
+    leaf = torch.empty((nq, w.T), dtype=torch.int32, device="cuda")
+    mrpt.mrpt_debug_leaves(ix.handle, Qd, leaf)
+    torch.cuda.synchronize()
+    S = s_count.cpu().numpy().astype(np.int64)
+    off = mrpt.mrpt_export_leaf_offsets(ix.handle)
+    sizes = np.diff(off)
+    leaf_entries = int(sizes[leaf.cpu().numpy()].sum())
+    sum_s = int(S.sum())
+    log(f"|S| mean {S.mean():.1f} p50 {np.percentile(S, 50):.0f} p99 {np.percentile(S, 99):.0f}")
+
+    nnz = int(ix.info.nnz)
+    nsplit = (1 << w.depth) - 1
+    bytes_route = nq * w.d * 4 + nq * w.T * 4 + (w.T * w.depth + 1) * 4 + nnz * 8 + w.T * nsplit * 4
+    bytes_vote = nq * w.T * 4 + nq * w.T * 8 + leaf_entries * 4 + sum_s * 4 + nq * 4
+    kp = 4 * k
+    rerank_rows = int(np.minimum(S, kp).sum())
+    bytes_search = {
+        "fp32": nq * 4 + sum_s * 4 + sum_s * w.d * 4 + nq * w.d * 4 + nq * k * 8,
+        "bf16": nq * 4 + sum_s * 4 + sum_s * (w.d * 2 + 4) + rerank_rows * w.d * 4 + nq * w.d * 4 + nq * k * 8,
+    }
+
+    def run_arm(precision, steps, warmup):
+        out = (torch.empty((nq, k), dtype=torch.int32, device="cuda"),
+               torch.empty((nq, k), dtype=torch.float32, device="cuda"))
+        opts = mrpt.mrpt_default_opts()
+        opts.precision = precision
+        for _ in range(warmup):
+            mrpt.mrpt_query_ex(ix.handle, Qd, k, v, out[0], out[1], opts)
+        events = []
+        arrays = []
+        for _ in range(steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            for e in ev:
+                e.record()                       # creates the HIP event
+            arr = (ctypes_void_array(4))(*[e.cuda_event for e in ev])
+            events.append(ev)
+            arrays.append(arr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            opts.stage_events = ctypes_cast_events(arrays[i])
+            mrpt.mrpt_query_ex(ix.handle, Qd, k, v, out[0], out[1], opts)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        stage_ms = np.array([[ev[j].elapsed_time(ev[j + 1]) for j in range(3)] for ev in events])
+        return elapsed, stage_ms.mean(axis=0), out
+
+    log(f"timing {args.steps} steps after {args.warmup} warmup (fp32)")
+    el32, st32, out32 = run_arm(mrpt.MRPT_FP32, args.steps, args.warmup)
+    log(f"fp32: {el32 / args.steps * 1e3:.3f} ms/step, stages(ms) {np.round(st32, 4).tolist()}")
+    el16, st16, out16 = run_arm(mrpt.MRPT_BF16_RERANK, args.steps, args.warmup)
+    log(f"bf16+rerank: {el16 / args.steps * 1e3:.3f} ms/step, stages(ms) {np.round(st16, 4).tolist()}")
+    gi32, gd32 = out32[0].cpu().numpy(), out32[1].cpu().numpy()
+    gi16, gd16 = out16[0].cpu().numpy(), out16[1].cpu().numpy()
+
+    # recall against float64 brute force and error against float64 on a sample
+    import oracle
+    rs = np.random.default_rng(0).choice(nq, size=min(args.recall_sample, nq), replace=False)
+    t0 = time.perf_counter()
+    bi, bd = oracle.bruteforce(X, Q[rs], k)
+    log(f"brute-force ground truth for {len(rs)} queries in {time.perf_counter() - t0:.1f}s")
+
+    def quality(gi, gd):
+        rec, err = [], 0.0
+        for j, q in enumerate(rs):
+            rec.append(len(set(gi[q].tolist()) & set(bi[j].tolist())) / k)
+            real = gi[q][gi[q] >= 0]
+            d64 = np.sqrt(((X[real].astype(np.float64) - Q[q].astype(np.float64)) ** 2).sum(1))
+            nz = d64 > 0
+            if nz.any():
+                err = max(err, float(np.max(np.abs(gd[q][:len(real)][nz] - d64[nz]) / d64[nz])))
+        return float(np.mean(rec)), err
+
+    rec32, err32 = quality(gi32, gd32)
+    rec16, err16 = quality(gi16, gd16)
+    log(f"recall@{k}: fp32 {rec32:.4f} bf16+rerank {rec16:.4f}; max rel err {err32:.2e} / {err16:.2e}")
+
+    def arm_record(elapsed, stage_ms, arm):
+        qps = nq * args.steps / elapsed
+        by = {"route": bytes_route, "vote": bytes_vote, "search": bytes_search[arm]}
+        stages = {}
+        for j, name in enumerate(STAGES):
+            gbs = by[name] / (stage_ms[j] * 1e-3) / 1e9
+            stages[name] = {"ms": round(float(stage_ms[j]), 5), "bytes": int(by[name]),
+                            "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        total_bytes = sum(by.values())
+        return qps, stages, total_bytes
+
+    qps32, stages32, tb32 = arm_record(el32, st32, "fp32")
+    qps16, stages16, tb16 = arm_record(el16, st16, "bf16")
+    dom = max(STAGES, key=lambda s: stages32[s]["ms"])
+    kernel_names = {"route": "route_kernel", "vote": "vote_kernel", "search": "dist_fp32_kernel"}
+    traffic = read_traffic(kernel_names[dom], args.workload)
+    roofline = {
+        "bound": "hbm", "kernel": kernel_names[dom],
+        "achieved": stages32[dom]["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(stages32[dom]["GBps"] / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "bytes_per_launch": stages32[dom]["bytes"], "launch_ms": stages32[dom]["ms"],
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nth = oracle.default_threads()
+        t0 = time.perf_counter()
+        orc = oracle.build_index(X, w.T, w.depth, w.a, w.index_seed, nthreads=nth)
+        log(f"oracle index built in {time.perf_counter() - t0:.1f}s on {nth} threads")
+        m = min(args.cpu_sample, nq)
+        t0 = time.perf_counter()
+        oracle.query(orc, Q[:m], k, v, nthreads=nth)
+        el = time.perf_counter() - t0
+        cpu = {"value": round(m / el, 1), "unit": "queries/s", "cores": nth, "kind": "oracle",
+               "sample": f"first {m} of the {nq} queries, oracle index of the same seed, "
+                         f"{el:.2f}s wall on {nth} host threads"}
+        log(f"oracle: {m / el:.1f} queries/s")
+
+    rec = {
+        "metric": METRIC,
+        "value": round(qps32, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el32 / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: n={w.n} d={w.d} nq={nq} T={w.T} depth={w.depth} "
+                               f"a=1/sqrt(d) k={k} v={v}",
+                   "n": w.n, "d": w.d, "nq": nq, "T": w.T, "depth": w.depth, "k": k, "v": v},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "recall_at_k": round(rec32, 4),
+        "max_rel_err_vs_fp64": err32,
+        "s_size": {"mean": round(float(S.mean()), 1), "p50": float(np.percentile(S, 50)),
+                   "p99": float(np.percentile(S, 99))},
+        "stages": stages32,
+        "path_hbm_frac": round(tb32 / (el32 / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "arms": {
+            "fp32": {"qps": round(qps32, 1), "ms_per_step": round(el32 / args.steps * 1e3, 4),
+                     "recall_at_k": round(rec32, 4), "max_rel_err_vs_fp64": err32, "stages": stages32},
+            "bf16_rerank": {"qps": round(qps16, 1), "ms_per_step": round(el16 / args.steps * 1e3, 4),
+                            "recall_at_k": round(rec16, 4), "max_rel_err_vs_fp64": err16,
+                            "stages": stages16,
+                            "path_hbm_frac": round(tb16 / (el16 / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+                            "identical_to_fp32": bool(np.array_equal(gi32, gi16) and np.array_equal(gd32, gd16))},
+        },
+        "build_s": round(build_s, 2),
+        "recall_sample": len(rs),
+    }
+    ix.close()
+    print(json.dumps(rec), flush=True)
+
+
+def ctypes_void_array(n):
+    import ctypes
+    return ctypes.c_void_p * n
+
+
+def ctypes_cast_events(arr):
+    import ctypes
+    return ctypes.cast(arr, ctypes.c_void_p)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * mrpt.h -- C ABI of the MI355X (gfx950) query path of multiple random
+ * projection trees with voting search ("Fast k-NN Search", Hyvonen et al.,
+ * arXiv:1509.06957).
+ *
+ * The problem (paper Sec. I-A): X holds n points of R^d; for a query q the
+ * answer is the k points of X closest to q in Euclidean distance.  The index
+ * (Sec. II, Alg. 1-2) is T random projection trees of depth `depth`, each
+ * using one sparse Gaussian vector per level (Sec. II-B, II-C) and median
+ * splits.  A query (Sec. III, Alg. 3-4) is routed to one leaf per tree, every
+ * point gets one vote per tree whose leaf it shares with q, the points with
+ * at least v votes form the candidate set S, and the k nearest members of S
+ * are returned.
+ *
+ * Conventions shared by every entry point:
+ *   - All calls return an mrpt_status and never throw.  On error the output
+ *     buffers are left untouched and mrpt_last_error() (thread-local) names
+ *     the problem.
+ *   - "device" pointers are HIP device memory of the current device (e.g. a
+ *     torch CUDA tensor's data_ptr()); "host" pointers are ordinary memory.
+ *   - Matrices are row-major float32: X is n x d, Q is nq x d.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Query calls are
+ *     asynchronous on that stream: they read Q and write the outputs in stream
+ *     order and return before the work completes.
+ *   - An index is immutable after mrpt_build.  It owns a workspace for query
+ *     temporaries; calls on one index made from several host threads are
+ *     serialised by the library, and calls on different streams are ordered
+ *     through an event, so they are safe but do not overlap on the GPU.
+ *
+ * Limits (MRPT_EINVAL beyond them): 1 <= d <= 65535, 1 <= n < 2^31,
+ * 2^depth <= n, depth <= 24, 1 <= T <= 255, 0 < a <= 1, 1 <= k <= min(n, 1024),
+ * 1 <= v <= T.
+ */
+#ifndef MRPT_H
+#define MRPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrpt_index mrpt_index;
+
+typedef enum {
+    MRPT_OK = 0,
+    MRPT_EINVAL = -1,      /* bad argument (sizes, limits, null pointer) */
+    MRPT_ENOMEM = -2,      /* device or host allocation failed */
+    MRPT_EDEVICE = -3,     /* a HIP runtime call or kernel launch failed */
+    MRPT_ENONFINITE = -4,  /* NaN or Inf in the data (build) or, when asked, in Q */
+    MRPT_EINTERNAL = -5    /* an internal consistency check failed */
+} mrpt_status;
+
+typedef enum {
+    MRPT_FP32 = 0,         /* exact search in S with float32 distances */
+    MRPT_BF16_RERANK = 1   /* bfloat16 prefilter over S, float32 rerank of the best
+                              rerank_factor*k, float64 recheck at the k-th boundary */
+} mrpt_precision;
+
+typedef struct {
+    int32_t precision;     /* mrpt_precision; default MRPT_FP32 */
+    int32_t rerank_factor; /* BF16 arm: keep the best rerank_factor*k of the prefilter
+                              (default 4; rerank_factor*k <= 512) */
+    float recheck_rel;     /* BF16 arm: candidates whose float32 distance is within
+                              recheck_rel (relative) of the k-th are re-ranked in
+                              float64 (default 1e-6) */
+    int32_t check_finite;  /* 1: scan Q for NaN/Inf first and return MRPT_ENONFINITE
+                              (this synchronises the stream); 0: no check, and a
+                              non-finite query row yields unspecified but in-range
+                              results */
+    int32_t* s_count;      /* optional device int32[nq]: receives |S| per query */
+    void* const* stage_events; /* optional host array of 4 hipEvent_t, recorded on `stream`
+                              before the routing kernel, after it, after the vote kernel
+                              and after the exact-search kernel (of the first sub-batch
+                              when a large batch is processed in several) */
+} mrpt_query_opts;
+
+typedef struct {
+    int64_t n;
+    int32_t d, T, depth;
+    float a;
+    uint64_t seed;
+    int64_t nnz;           /* nonzeros of the T*depth projection vectors */
+    int32_t max_leaf;      /* ceil(n / 2^depth) */
+    int32_t id_chunk;      /* ids per vote-counting pass of the query kernels */
+    int64_t device_bytes;  /* device memory held by the index (without workspace) */
+} mrpt_index_desc;
+
+/* Build the index (paper Alg. 1 grow_trees, Alg. 2 grow_tree; Sec. II-B sparse
+ * vectors with density a; Sec. II-C one vector per level).
+ *   data  : device, n x d float32, finite.  Copied; the caller keeps ownership.
+ *   seed  : the projection vectors are a pure function of (seed, tree, level,
+ *           feature), so tree t is the same for every T > t.
+ *   out   : receives the new index (release with mrpt_free).
+ * Synchronous: the device is synchronised before returning.  Errors:
+ * MRPT_EINVAL, MRPT_ENONFINITE, MRPT_ENOMEM, MRPT_EDEVICE. */
+mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32_t depth,
+                       float a, uint64_t seed, mrpt_index** out);
+
+/* Approximate k-NN of nq queries (paper Alg. 4 approximate_knn with Alg. 3
+ * tree_query), float32 exact search in S.
+ *   Q        : device, nq x d float32.
+ *   out_idx  : device int32[nq*k]; row q holds the ids of the k nearest members
+ *              of S_q ordered by (distance, id); -1 pads rows with |S_q| < k.
+ *   out_dist : device float32[nq*k]; Euclidean distances (not squared); +inf pads.
+ * nq = 0 is a no-op.  Asynchronous on `stream`. */
+mrpt_status mrpt_query(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v,
+                       int32_t* out_idx, float* out_dist, void* stream);
+
+/* mrpt_query with options (precision arm, rerank factor, finite check, |S|
+ * export).  opts = NULL means the defaults, i.e. mrpt_query. */
+mrpt_status mrpt_query_ex(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v,
+                          int32_t* out_idx, float* out_dist, const mrpt_query_opts* opts,
+                          void* stream);
+
+/* Default options (MRPT_FP32, rerank_factor 4, recheck_rel 1e-6, no check, no
+ * |S| export, no stage events). */
+void mrpt_default_opts(mrpt_query_opts* opts);
+
+/* Release an index and all device memory it owns (NULL is ignored).  The
+ * device is synchronised first. */
+void mrpt_free(mrpt_index* ix);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* mrpt_last_error(void);
+
+/* Sizes and parameters of a built index. */
+mrpt_status mrpt_index_info(const mrpt_index* ix, mrpt_index_desc* out);
+
+/* Debug export of the projection vectors (Sec. II-B), one CSR row per (tree,
+ * level) in order tree*depth + level, features ascending.
+ *   rowptr : host int32[T*depth + 1];  col : host int32[nnz];  val : host float[nnz]. */
+mrpt_status mrpt_export_projection(const mrpt_index* ix, int32_t* rowptr, int32_t* col, float* val);
+
+/* Debug export of tree t (Alg. 2): splits host float[2^depth - 1] in heap
+ * order (children of node i are 2i+1 and 2i+2), perm host int32[n] = the
+ * point ids leaf after leaf (left to right), ascending inside each leaf.
+ * Either pointer may be NULL. */
+mrpt_status mrpt_export_tree(const mrpt_index* ix, int32_t t, float* splits, int32_t* perm);
+
+/* Debug export of the leaf offsets: host int64[2^depth + 1]; leaf L of every
+ * tree is perm[off[L] .. off[L+1]). */
+mrpt_status mrpt_export_leaf_offsets(const mrpt_index* ix, int64_t* off);
+
+/* Debug: the leaf of every query in every tree (Alg. 3), computed by the same
+ * kernel the query path runs.  leaf: device int32[nq*T].  Asynchronous. */
+mrpt_status mrpt_debug_leaves(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf,
+                              void* stream);
+
+/* Debug: the candidate sets S_q = {x : F(x; q) >= v} (Sec. III-A) computed by
+ * the query path's vote kernel.
+ *   s_count : device int32[nq]       |S_q|
+ *   s_ids   : device int32[nq*cap]   members of S_q, in no particular order
+ *   s_votes : device uint8[nq*cap]   F(x; q) of each listed member (may be NULL)
+ *   cap     : row stride of s_ids/s_votes; must be >= min(n, floor(T*max_leaf/v))
+ * Asynchronous. */
+mrpt_status mrpt_debug_votes(const mrpt_index* ix, const float* Q, int64_t nq, int32_t v,
+                             int32_t* s_count, int32_t* s_ids, uint8_t* s_votes, int64_t cap,
+                             void* stream);
+
+/* Upper bound used for the per-query candidate buffer: min(n, floor(T*max_leaf/v)). */
+int64_t mrpt_candidate_cap(const mrpt_index* ix, int32_t v);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRPT_H */

@@ -1,0 +1,412 @@
+// C ABI of libmrpt: argument checks, index lifetime, workspace, and the
+// order of kernel launches of one query call (Alg. 4: route every query in
+// every tree, vote, exact search in S).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "mrpt_internal.h"
+
+namespace mrpt {
+
+namespace {
+thread_local std::string g_error;
+// workspace bound per query call (larger batches run in several sub-batches);
+// MRPT_WORKSPACE_LIMIT (bytes) overrides it
+size_t workspace_limit() {
+    const char* env = std::getenv("MRPT_WORKSPACE_LIMIT");
+    if (env && *env) {
+        const long long v = std::atoll(env);
+        if (v > 0) return (size_t)v;
+    }
+    return size_t(4) << 30;
+}
+
+template <class T>
+hipError_t dev_alloc(T** p, size_t count, int64_t* tally) {
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e == hipSuccess && tally) *tally += (int64_t)(count * sizeof(T));
+    return e;
+}
+
+void dev_release(mrpt_index* ix) {
+    void* ptrs[] = {ix->X, ix->Xb, ix->xnorm, ix->rowptr, ix->col, ix->val, ix->splits, ix->perm, ix->off,
+                    ix->ws.base};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (ix->ws.done) (void)hipEventDestroy(ix->ws.done);
+}
+
+bool is_device_pointer(const void* p) {
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof(attr));
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+mrpt_status check_index(const mrpt_index* ix) {
+    if (!ix) return fail(MRPT_EINVAL, "index is NULL");
+    return MRPT_OK;
+}
+
+mrpt_status check_query_args(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v,
+                             const void* out_idx, const void* out_dist) {
+    MRPT_TRY(check_index(ix));
+    if (nq < 0) return fail(MRPT_EINVAL, "nq = %lld < 0", (long long)nq);
+    if (k < 1 || k > kMaxK || (int64_t)k > ix->n)
+        return fail(MRPT_EINVAL, "k = %d outside [1, min(n, %d)]", k, kMaxK);
+    if (v < 1 || v > ix->T) return fail(MRPT_EINVAL, "v = %d outside [1, T = %d]", v, ix->T);
+    if (nq > 0 && (!Q || !out_idx || !out_dist)) return fail(MRPT_EINVAL, "NULL query or output pointer");
+    return MRPT_OK;
+}
+
+// workspace for nb queries at candidate cap `cap` (caller holds ix->mu)
+mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
+    const size_t leaf_b = ((size_t)nb * ix->T * sizeof(int32_t) + 255) & ~size_t(255);
+    const size_t ids_b = ((size_t)nb * (size_t)cap * sizeof(int32_t) + 255) & ~size_t(255);
+    const size_t cnt_b = ((size_t)nb * sizeof(int32_t) + 255) & ~size_t(255);
+    const size_t need = leaf_b + ids_b + cnt_b + 256;
+    if (!ix->ws.done) MRPT_HIP_TRY(hipEventCreateWithFlags(&ix->ws.done, hipEventDisableTiming));
+    if (need > ix->ws.bytes) {
+        MRPT_HIP_TRY(hipEventSynchronize(ix->ws.done));
+        if (ix->ws.base) MRPT_HIP_TRY(hipFree(ix->ws.base));
+        ix->ws.base = nullptr;
+        ix->ws.bytes = 0;
+        if (hipMalloc(&ix->ws.base, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MRPT_ENOMEM, "workspace of %zu bytes", need);
+        }
+        ix->ws.bytes = need;
+    }
+    char* b = (char*)ix->ws.base;
+    ix->ws.leaf = (int32_t*)b;
+    ix->ws.s_ids = (int32_t*)(b + leaf_b);
+    ix->ws.s_count = (int32_t*)(b + leaf_b + ids_b);
+    ix->ws.flag = (int32_t*)(b + leaf_b + ids_b + cnt_b);
+    return MRPT_OK;
+}
+
+int64_t candidate_cap(const mrpt_index* ix, int32_t v) {
+    const int64_t bound = (int64_t)ix->T * ix->max_leaf / v;
+    return std::max<int64_t>(1, std::min<int64_t>(ix->n, bound));
+}
+
+int64_t batch_size(const mrpt_index* ix, int64_t nq, int64_t cap) {
+    const int64_t per_q = (int64_t)(ix->T + cap + 1) * (int64_t)sizeof(int32_t);
+    const int64_t nb = std::max<int64_t>(1, (int64_t)workspace_limit() / per_q);
+    return std::min(nq, nb);
+}
+
+mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_t k, int32_t v, int32_t* out_idx,
+                       float* out_dist, const mrpt_query_opts* opts, void* stream) {
+    clear_error();
+    MRPT_TRY(check_query_args(cix, Q, nq, k, v, out_idx, out_dist));
+    mrpt_query_opts o;
+    mrpt_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.precision != MRPT_FP32 && o.precision != MRPT_BF16_RERANK)
+        return fail(MRPT_EINVAL, "unknown precision %d", o.precision);
+    if (o.precision == MRPT_BF16_RERANK) {
+        if (o.rerank_factor < 1 || (int64_t)o.rerank_factor * k > kMaxRerank)
+            return fail(MRPT_EINVAL, "rerank_factor*k = %lld outside [1, %d]",
+                        (long long)o.rerank_factor * k, kMaxRerank);
+        if (!(o.recheck_rel >= 0.0f) || !std::isfinite(o.recheck_rel))
+            return fail(MRPT_EINVAL, "recheck_rel must be finite and >= 0");
+        if (cix->d % 8 != 0 || cix->d > 1024)
+            return fail(MRPT_EINVAL, "the bfloat16 arm needs d %% 8 == 0 and d <= 1024 (d = %d)", cix->d);
+    }
+    if (nq == 0) return MRPT_OK;
+    mrpt_index* ix = const_cast<mrpt_index*>(cix);
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(ix->mu);
+    MRPT_HIP_TRY(hipSetDevice(ix->device));
+    const int64_t cap = candidate_cap(ix, v);
+    const int64_t nb = batch_size(ix, nq, cap);
+    MRPT_TRY(ensure_workspace(ix, nb, cap));
+    MRPT_HIP_TRY(hipStreamWaitEvent(s, ix->ws.done, 0));
+    if (o.check_finite) {
+        MRPT_HIP_TRY(hipMemsetAsync(ix->ws.flag, 0, sizeof(int32_t), s));
+        MRPT_HIP_TRY(launch_check_finite(Q, nq * (int64_t)ix->d, ix->ws.flag, s));
+        int32_t h = 0;
+        MRPT_HIP_TRY(hipMemcpyAsync(&h, ix->ws.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MRPT_HIP_TRY(hipStreamSynchronize(s));
+        if (h) return fail(MRPT_ENONFINITE, "query matrix holds NaN or Inf");
+    }
+    auto mark = [&](int64_t q0, int i) -> hipError_t {
+        if (!o.stage_events || q0 != 0 || !o.stage_events[i]) return hipSuccess;
+        return hipEventRecord((hipEvent_t)o.stage_events[i], s);
+    };
+    for (int64_t q0 = 0; q0 < nq; q0 += nb) {
+        const int64_t m = std::min(nb, nq - q0);
+        const float* Qb = Q + q0 * ix->d;
+        MRPT_HIP_TRY(mark(q0, 0));
+        MRPT_HIP_TRY(launch_route(ix, Qb, m, ix->ws.leaf, s));
+        MRPT_HIP_TRY(mark(q0, 1));
+        MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, m, v, ix->ws.s_ids, cap, ix->ws.s_count, s));
+        MRPT_HIP_TRY(mark(q0, 2));
+        if (o.precision == MRPT_FP32)
+            MRPT_HIP_TRY(launch_dist_fp32(ix, Qb, m, ix->ws.s_ids, cap, ix->ws.s_count, k, out_idx + q0 * k,
+                                          out_dist + q0 * k, s));
+        else
+            MRPT_HIP_TRY(launch_dist_bf16(ix, Qb, m, ix->ws.s_ids, cap, ix->ws.s_count, k, o.rerank_factor,
+                                          o.recheck_rel, out_idx + q0 * k, out_dist + q0 * k, s));
+        MRPT_HIP_TRY(mark(q0, 3));
+        if (o.s_count) MRPT_HIP_TRY(launch_copy_counts(ix->ws.s_count, m, o.s_count + q0, s));
+    }
+    MRPT_HIP_TRY(hipEventRecord(ix->ws.done, s));
+    return MRPT_OK;
+}
+
+}  // namespace
+
+mrpt_status fail(mrpt_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+void clear_error() { g_error.clear(); }
+
+}  // namespace mrpt
+
+using namespace mrpt;
+
+extern "C" {
+
+const char* mrpt_last_error(void) { return g_error.c_str(); }
+
+void mrpt_default_opts(mrpt_query_opts* o) {
+    if (!o) return;
+    o->precision = MRPT_FP32;
+    o->rerank_factor = 4;
+    o->recheck_rel = 1e-6f;
+    o->check_finite = 0;
+    o->s_count = nullptr;
+    o->stage_events = nullptr;
+}
+
+mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32_t depth, float a, uint64_t seed,
+                       mrpt_index** out) {
+    clear_error();
+    if (!out) return fail(MRPT_EINVAL, "out is NULL");
+    if (!data) return fail(MRPT_EINVAL, "data is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(MRPT_EINVAL, "n = %lld outside [1, 2^31)", (long long)n);
+    if (d < 1 || d > 65535) return fail(MRPT_EINVAL, "d = %d outside [1, 65535]", d);
+    if (T < 1 || T > kMaxT) return fail(MRPT_EINVAL, "T = %d outside [1, %d]", T, kMaxT);
+    if (depth < 0 || depth > kMaxDepth) return fail(MRPT_EINVAL, "depth = %d outside [0, %d]", depth, kMaxDepth);
+    if ((int64_t(1) << depth) > n) return fail(MRPT_EINVAL, "2^depth = %lld exceeds n = %lld",
+                                              (long long)(int64_t(1) << depth), (long long)n);
+    if (!(a > 0.0f && a <= 1.0f)) return fail(MRPT_EINVAL, "a = %g outside (0, 1]", (double)a);
+    if (!is_device_pointer(data)) return fail(MRPT_EINVAL, "data must be device memory");
+
+    std::unique_ptr<mrpt_index> ix;
+    try {
+        ix.reset(new mrpt_index());
+    } catch (const std::bad_alloc&) {
+        return fail(MRPT_ENOMEM, "host allocation of the index");
+    }
+    ix->n = n; ix->d = d; ix->T = T; ix->depth = depth; ix->a = a; ix->seed = seed;
+    ix->nleaf = 1 << depth;
+    ix->max_leaf = (int32_t)((n + ix->nleaf - 1) / ix->nleaf);
+    {
+        const int64_t padded = (n + 15) / 16 * 16;
+        ix->id_chunk = (int32_t)std::min<int64_t>(padded, kVoteChunk);
+    }
+    MRPT_HIP_TRY(hipGetDevice(&ix->device));
+
+    struct Guard {
+        mrpt_index* p;
+        ~Guard() { if (p) dev_release(p); }
+    } guard{ix.get()};
+
+    const size_t nd = (size_t)n * (size_t)d;
+    auto oom = [&](hipError_t e, const char* what) -> mrpt_status {
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? MRPT_ENOMEM : MRPT_EDEVICE, "allocating %s: %s", what,
+                    hipGetErrorString(e));
+    };
+    hipError_t e;
+    if ((e = dev_alloc(&ix->X, nd, &ix->device_bytes)) != hipSuccess) return oom(e, "data copy");
+    MRPT_HIP_TRY(hipMemcpy(ix->X, data, nd * sizeof(float), hipMemcpyDeviceToDevice));
+    {
+        int32_t* flag = nullptr;
+        MRPT_HIP_TRY(hipMalloc((void**)&flag, sizeof(int32_t)));
+        hipError_t e1 = hipMemset(flag, 0, sizeof(int32_t));
+        if (e1 == hipSuccess) e1 = launch_check_finite(ix->X, (int64_t)nd, flag, nullptr);
+        int32_t h = 0;
+        if (e1 == hipSuccess) e1 = hipMemcpy(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost);
+        (void)hipFree(flag);
+        MRPT_HIP_TRY(e1);
+        if (h) return fail(MRPT_ENONFINITE, "data holds NaN or Inf");
+    }
+
+    std::vector<float> hX;
+    try {
+        hX.resize(nd);
+    } catch (const std::bad_alloc&) {
+        return fail(MRPT_ENOMEM, "host copy of the data (%zu bytes)", nd * sizeof(float));
+    }
+    MRPT_HIP_TRY(hipMemcpy(hX.data(), ix->X, nd * sizeof(float), hipMemcpyDeviceToHost));
+
+    generate_projection(d, T, depth, a, seed, ix->h_rowptr, ix->h_col, ix->h_val);
+    HostTrees trees;
+    grow_trees_host(hX.data(), n, d, T, depth, ix->h_rowptr, ix->h_col, ix->h_val, trees);
+    ix->h_off = trees.off;
+    hX.clear();
+    hX.shrink_to_fit();
+
+    const size_t nnz = ix->h_col.size();
+    const size_t nsplit = ((size_t)1 << depth) - 1;
+    if ((e = dev_alloc(&ix->rowptr, ix->h_rowptr.size(), &ix->device_bytes)) != hipSuccess) return oom(e, "rowptr");
+    if ((e = dev_alloc(&ix->col, std::max<size_t>(nnz, 1), &ix->device_bytes)) != hipSuccess) return oom(e, "col");
+    if ((e = dev_alloc(&ix->val, std::max<size_t>(nnz, 1), &ix->device_bytes)) != hipSuccess) return oom(e, "val");
+    if ((e = dev_alloc(&ix->splits, std::max<size_t>((size_t)T * nsplit, 1), &ix->device_bytes)) != hipSuccess)
+        return oom(e, "splits");
+    if ((e = dev_alloc(&ix->perm, (size_t)T * (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "perm");
+    if ((e = dev_alloc(&ix->off, (size_t)ix->nleaf + 1, &ix->device_bytes)) != hipSuccess) return oom(e, "offsets");
+    if ((e = dev_alloc(&ix->Xb, nd, &ix->device_bytes)) != hipSuccess) return oom(e, "bfloat16 data");
+    if ((e = dev_alloc(&ix->xnorm, (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "norms");
+
+    MRPT_HIP_TRY(hipMemcpy(ix->rowptr, ix->h_rowptr.data(), ix->h_rowptr.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
+    if (nnz) {
+        MRPT_HIP_TRY(hipMemcpy(ix->col, ix->h_col.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        MRPT_HIP_TRY(hipMemcpy(ix->val, ix->h_val.data(), nnz * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (nsplit)
+        MRPT_HIP_TRY(hipMemcpy(ix->splits, trees.splits.data(), (size_t)T * nsplit * sizeof(float),
+                               hipMemcpyHostToDevice));
+    MRPT_HIP_TRY(hipMemcpy(ix->perm, trees.perm.data(), (size_t)T * n * sizeof(int32_t), hipMemcpyHostToDevice));
+    std::vector<int32_t> off32(ix->h_off.begin(), ix->h_off.end());
+    MRPT_HIP_TRY(hipMemcpy(ix->off, off32.data(), off32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MRPT_HIP_TRY(launch_quantize_bf16(ix->X, n, d, ix->Xb, ix->xnorm, nullptr));
+    MRPT_HIP_TRY(hipDeviceSynchronize());
+
+    guard.p = nullptr;
+    *out = ix.release();
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_query(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v, int32_t* out_idx,
+                       float* out_dist, void* stream) {
+    return query_impl(ix, Q, nq, k, v, out_idx, out_dist, nullptr, stream);
+}
+
+mrpt_status mrpt_query_ex(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v, int32_t* out_idx,
+                          float* out_dist, const mrpt_query_opts* opts, void* stream) {
+    return query_impl(ix, Q, nq, k, v, out_idx, out_dist, opts, stream);
+}
+
+void mrpt_free(mrpt_index* ix) {
+    if (!ix) return;
+    (void)hipSetDevice(ix->device);
+    (void)hipDeviceSynchronize();
+    dev_release(ix);
+    delete ix;
+}
+
+mrpt_status mrpt_index_info(const mrpt_index* ix, mrpt_index_desc* out) {
+    clear_error();
+    MRPT_TRY(check_index(ix));
+    if (!out) return fail(MRPT_EINVAL, "out is NULL");
+    out->n = ix->n; out->d = ix->d; out->T = ix->T; out->depth = ix->depth;
+    out->a = ix->a; out->seed = ix->seed;
+    out->nnz = (int64_t)ix->h_col.size();
+    out->max_leaf = ix->max_leaf;
+    out->id_chunk = ix->id_chunk;
+    out->device_bytes = ix->device_bytes;
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_export_projection(const mrpt_index* ix, int32_t* rowptr, int32_t* col, float* val) {
+    clear_error();
+    MRPT_TRY(check_index(ix));
+    if (!rowptr || (!ix->h_col.empty() && (!col || !val))) return fail(MRPT_EINVAL, "NULL output pointer");
+    std::memcpy(rowptr, ix->h_rowptr.data(), ix->h_rowptr.size() * sizeof(int32_t));
+    if (!ix->h_col.empty()) {
+        std::memcpy(col, ix->h_col.data(), ix->h_col.size() * sizeof(int32_t));
+        std::memcpy(val, ix->h_val.data(), ix->h_val.size() * sizeof(float));
+    }
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_export_tree(const mrpt_index* ix, int32_t t, float* splits, int32_t* perm) {
+    clear_error();
+    MRPT_TRY(check_index(ix));
+    if (t < 0 || t >= ix->T) return fail(MRPT_EINVAL, "tree %d outside [0, %d)", t, ix->T);
+    MRPT_HIP_TRY(hipSetDevice(ix->device));
+    const size_t nsplit = ((size_t)1 << ix->depth) - 1;
+    if (splits && nsplit)
+        MRPT_HIP_TRY(hipMemcpy(splits, ix->splits + (size_t)t * nsplit, nsplit * sizeof(float),
+                               hipMemcpyDeviceToHost));
+    if (perm)
+        MRPT_HIP_TRY(hipMemcpy(perm, ix->perm + (size_t)t * ix->n, (size_t)ix->n * sizeof(int32_t),
+                               hipMemcpyDeviceToHost));
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_export_leaf_offsets(const mrpt_index* ix, int64_t* off) {
+    clear_error();
+    MRPT_TRY(check_index(ix));
+    if (!off) return fail(MRPT_EINVAL, "off is NULL");
+    std::memcpy(off, ix->h_off.data(), ix->h_off.size() * sizeof(int64_t));
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_debug_leaves(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, void* stream) {
+    clear_error();
+    MRPT_TRY(check_index(ix));
+    if (nq < 0) return fail(MRPT_EINVAL, "nq < 0");
+    if (nq > 0 && (!Q || !leaf)) return fail(MRPT_EINVAL, "NULL pointer");
+    if (nq == 0) return MRPT_OK;
+    MRPT_HIP_TRY(hipSetDevice(ix->device));
+    MRPT_HIP_TRY(launch_route(ix, Q, nq, leaf, (hipStream_t)stream));
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_debug_votes(const mrpt_index* cix, const float* Q, int64_t nq, int32_t v, int32_t* s_count,
+                             int32_t* s_ids, uint8_t* s_votes, int64_t cap, void* stream) {
+    clear_error();
+    MRPT_TRY(check_index(cix));
+    if (nq < 0) return fail(MRPT_EINVAL, "nq < 0");
+    if (v < 1 || v > cix->T) return fail(MRPT_EINVAL, "v = %d outside [1, T]", v);
+    if (nq > 0 && (!Q || !s_count || !s_ids)) return fail(MRPT_EINVAL, "NULL pointer");
+    if (cap < candidate_cap(cix, v))
+        return fail(MRPT_EINVAL, "cap = %lld below the candidate bound %lld", (long long)cap,
+                    (long long)candidate_cap(cix, v));
+    if (nq == 0) return MRPT_OK;
+    mrpt_index* ix = const_cast<mrpt_index*>(cix);
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(ix->mu);
+    MRPT_HIP_TRY(hipSetDevice(ix->device));
+    MRPT_TRY(ensure_workspace(ix, nq, 1));
+    MRPT_HIP_TRY(hipStreamWaitEvent(s, ix->ws.done, 0));
+    MRPT_HIP_TRY(launch_route(ix, Q, nq, ix->ws.leaf, s));
+    MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, nq, v, s_ids, cap, s_count, s));
+    if (s_votes) MRPT_HIP_TRY(launch_vote_counts(ix, ix->ws.leaf, nq, s_ids, cap, s_count, s_votes, s));
+    MRPT_HIP_TRY(hipEventRecord(ix->ws.done, s));
+    return MRPT_OK;
+}
+
+int64_t mrpt_candidate_cap(const mrpt_index* ix, int32_t v) {
+    if (!ix || v < 1) return 0;
+    return candidate_cap(ix, v);
+}
+
+}  // extern "C"

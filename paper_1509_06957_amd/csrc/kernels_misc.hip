@@ -1,0 +1,69 @@
+// Build-time and utility kernels: finiteness scan, bfloat16 copy of the data
+// with float32 squared norms (inputs of the bfloat16 prefilter).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mrpt_internal.h"
+
+namespace mrpt {
+namespace {
+
+__global__ void check_finite_kernel(const float* __restrict__ A, int64_t count, int32_t* __restrict__ flag) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = __builtin_bit_cast(uint32_t, A[i]);
+        bad |= ((b & 0x7f800000u) == 0x7f800000u) ? 1 : 0;
+    }
+    if (__ballot(bad != 0) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+// round-to-nearest-even float32 -> bfloat16 (finite inputs)
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+    uint32_t b = __builtin_bit_cast(uint32_t, x);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+// one wave per row: lanes over columns
+__global__ __launch_bounds__(256) void quantize_bf16_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                            uint16_t* __restrict__ Xb,
+                                                            float* __restrict__ xnorm) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < n; row += waves) {
+        const float* xr = X + row * d;
+        uint16_t* br = Xb + row * d;
+        float acc = 0.0f;
+        for (int i = lane; i < d; i += 64) {
+            const uint16_t h = to_bf16(xr[i]);
+            br[i] = h;
+            const float f = __builtin_bit_cast(float, (uint32_t)h << 16);
+            acc = __builtin_fmaf(f, f, acc);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) xnorm[row] = acc;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, count, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, float* xnorm, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(quantize_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, Xb, xnorm);
+    return hipGetLastError();
+}
+
+}  // namespace mrpt

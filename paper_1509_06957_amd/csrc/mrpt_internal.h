@@ -1,0 +1,125 @@
+// Internal declarations of libmrpt (the GPU library).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mrpt.h"
+
+namespace mrpt {
+
+// ---------------------------------------------------------------- errors
+mrpt_status fail(mrpt_status st, const char* fmt, ...);
+void clear_error();
+
+#define MRPT_HIP_TRY(expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::mrpt::fail(MRPT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define MRPT_TRY(expr)                        \
+    do {                                      \
+        mrpt_status s_ = (expr);              \
+        if (s_ != MRPT_OK) return s_;         \
+    } while (0)
+
+// ---------------------------------------------------------------- limits
+constexpr int kMaxT = 255;          // 8-bit vote counters
+constexpr int kMaxDepth = 24;
+constexpr int kMaxK = 1024;
+constexpr int kMaxRerank = 512;     // rerank_factor * k
+constexpr int kVoteChunk = 65536;   // ids per LDS counting pass (bytes of LDS)
+
+// ---------------------------------------------------------------- index
+struct DeviceBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace {
+    int32_t* leaf = nullptr;     // nb x T
+    int32_t* s_ids = nullptr;    // nb x cap
+    int32_t* s_count = nullptr;  // nb
+    int32_t* flag = nullptr;     // 1 int
+    void* base = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;   // recorded after the last kernel that used it
+};
+
+}  // namespace mrpt
+
+struct mrpt_index {
+    int64_t n = 0;
+    int32_t d = 0, T = 0, depth = 0;
+    float a = 0.f;
+    uint64_t seed = 0;
+    int32_t nleaf = 1;           // 2^depth
+    int32_t max_leaf = 0;        // ceil(n / 2^depth)
+    int32_t id_chunk = 0;        // ids per vote pass (<= kVoteChunk, multiple of 16)
+    int device = 0;
+
+    // host copy of the projection CSR (for export)
+    std::vector<int32_t> h_rowptr;
+    std::vector<int32_t> h_col;
+    std::vector<float> h_val;
+    std::vector<int64_t> h_off;
+
+    // device arrays
+    float* X = nullptr;          // n x d
+    uint16_t* Xb = nullptr;      // n x d bfloat16 bits (round to nearest even)
+    float* xnorm = nullptr;      // n: squared norm of the bfloat16 row, float32
+    int32_t* rowptr = nullptr;   // T*depth + 1
+    int32_t* col = nullptr;      // nnz
+    float* val = nullptr;        // nnz
+    float* splits = nullptr;     // T x (2^depth - 1)
+    int32_t* perm = nullptr;     // T x n
+    int32_t* off = nullptr;      // 2^depth + 1
+    int64_t device_bytes = 0;
+
+    std::mutex mu;               // guards ws
+    mrpt::Workspace ws;
+};
+
+namespace mrpt {
+
+// host-side index construction (host_build.cpp)
+struct HostTrees {
+    std::vector<float> splits;   // T x (2^depth - 1)
+    std::vector<int32_t> perm;   // T x n
+    std::vector<int64_t> off;    // 2^depth + 1
+};
+void generate_projection(int32_t d, int32_t T, int32_t depth, float a, uint64_t seed,
+                         std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
+                         std::vector<float>& val);
+void leaf_offsets(int64_t n, int32_t depth, std::vector<int64_t>& off);
+void grow_trees_host(const float* X, int64_t n, int32_t d, int32_t T, int32_t depth,
+                     const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,
+                     const std::vector<float>& val, HostTrees& out);
+
+// kernel launchers (kernels_query.hip / kernels_misc.hip); all asynchronous
+hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf,
+                        hipStream_t s);
+hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v,
+                       int32_t* s_ids, int64_t cap, int32_t* s_count, hipStream_t s);
+hipError_t launch_vote_counts(const mrpt_index* ix, const int32_t* leaf, int64_t nq,
+                              const int32_t* s_ids, int64_t cap, const int32_t* s_count,
+                              uint8_t* s_votes, hipStream_t s);
+hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, int64_t nq,
+                            const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k,
+                            int32_t* out_idx, float* out_dist, hipStream_t s);
+hipError_t launch_dist_bf16(const mrpt_index* ix, const float* Q, int64_t nq,
+                            const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k,
+                            int32_t rerank, float recheck_rel, int32_t* out_idx, float* out_dist,
+                            hipStream_t s);
+hipError_t launch_copy_counts(const int32_t* src, int64_t nq, int32_t* dst, hipStream_t s);
+hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hipStream_t s);
+hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, float* xnorm,
+                                hipStream_t s);
+
+}  // namespace mrpt

@@ -1,0 +1,220 @@
+"""Thin ctypes binding of libmrpt (include/mrpt.h), same names as the C ABI.
+
+Only argument marshalling happens here: every step of the search runs in the
+library's HIP kernels.  Device arrays are torch CUDA tensors (torch is used for
+device memory and streams only).  There is no CPU fallback: if libmrpt.so is
+missing or no GPU is present, calls raise.
+"""
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmrpt.so")
+
+MRPT_OK, MRPT_EINVAL, MRPT_ENOMEM, MRPT_EDEVICE, MRPT_ENONFINITE, MRPT_EINTERNAL = 0, -1, -2, -3, -4, -5
+MRPT_FP32, MRPT_BF16_RERANK = 0, 1
+_STATUS = {0: "MRPT_OK", -1: "MRPT_EINVAL", -2: "MRPT_ENOMEM", -3: "MRPT_EDEVICE", -4: "MRPT_ENONFINITE",
+           -5: "MRPT_EINTERNAL"}
+
+
+class MrptError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class mrpt_query_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rerank_factor", ctypes.c_int32),
+                ("recheck_rel", ctypes.c_float), ("check_finite", ctypes.c_int32),
+                ("s_count", ctypes.c_void_p), ("stage_events", ctypes.c_void_p)]
+
+
+class mrpt_index_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("T", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("a", ctypes.c_float), ("seed", ctypes.c_uint64), ("nnz", ctypes.c_int64),
+                ("max_leaf", ctypes.c_int32), ("id_chunk", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+EXPORTED = [
+    "mrpt_build", "mrpt_query", "mrpt_query_ex", "mrpt_default_opts", "mrpt_free", "mrpt_last_error",
+    "mrpt_index_info", "mrpt_export_projection", "mrpt_export_tree", "mrpt_export_leaf_offsets",
+    "mrpt_debug_leaves", "mrpt_debug_votes", "mrpt_candidate_cap",
+]
+
+
+def load(path: str = LIB_PATH):
+    """Load libmrpt.so and declare its signatures (no GPU needed to load)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch first: its HIP runtime (same soname) must be the one libmrpt binds to
+    import torch  # noqa: F401
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_1509_06957_amd/build.py (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, f32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64
+    lib.mrpt_build.argtypes = [vp, i64, i32, i32, i32, f32, u64, ctypes.POINTER(vp)]
+    lib.mrpt_query.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp]
+    lib.mrpt_query_ex.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.POINTER(mrpt_query_opts), vp]
+    lib.mrpt_default_opts.argtypes = [ctypes.POINTER(mrpt_query_opts)]
+    lib.mrpt_default_opts.restype = None
+    lib.mrpt_free.argtypes = [vp]
+    lib.mrpt_free.restype = None
+    lib.mrpt_last_error.restype = ctypes.c_char_p
+    lib.mrpt_index_info.argtypes = [vp, ctypes.POINTER(mrpt_index_desc)]
+    lib.mrpt_export_projection.argtypes = [vp, vp, vp, vp]
+    lib.mrpt_export_tree.argtypes = [vp, i32, vp, vp]
+    lib.mrpt_export_leaf_offsets.argtypes = [vp, vp]
+    lib.mrpt_debug_leaves.argtypes = [vp, vp, i64, vp, vp]
+    lib.mrpt_debug_votes.argtypes = [vp, vp, i64, i32, vp, vp, vp, i64, vp]
+    lib.mrpt_candidate_cap.argtypes = [vp, i32]
+    lib.mrpt_candidate_cap.restype = i64
+    for name in EXPORTED:
+        if name not in ("mrpt_default_opts", "mrpt_free", "mrpt_last_error", "mrpt_candidate_cap"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def mrpt_last_error() -> str:
+    return load().mrpt_last_error().decode()
+
+
+def _check(status: int):
+    if status != MRPT_OK:
+        raise MrptError(status, mrpt_last_error())
+
+
+def _dev(t, dtype_name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError(f"expected torch.{dtype_name}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def mrpt_build(data, T: int, depth: int, a: float, seed: int) -> ctypes.c_void_p:
+    """Build an index over data (n x d float32 CUDA tensor); returns the handle."""
+    n, d = data.shape
+    h = ctypes.c_void_p()
+    _check(load().mrpt_build(_dev(data, "float32"), n, d, T, depth, a, seed & (2**64 - 1), ctypes.byref(h)))
+    return h
+
+
+def mrpt_default_opts() -> mrpt_query_opts:
+    o = mrpt_query_opts()
+    load().mrpt_default_opts(ctypes.byref(o))
+    return o
+
+
+def mrpt_query(ix, Q, k: int, v: int, out_idx, out_dist, stream=None):
+    nq = Q.shape[0]
+    _check(load().mrpt_query(ix, _dev(Q, "float32"), nq, k, v, _dev(out_idx, "int32"),
+                             _dev(out_dist, "float32"), _stream(stream)))
+
+
+def mrpt_query_ex(ix, Q, k: int, v: int, out_idx, out_dist, opts: Optional[mrpt_query_opts] = None, stream=None):
+    nq = Q.shape[0]
+    _check(load().mrpt_query_ex(ix, _dev(Q, "float32"), nq, k, v, _dev(out_idx, "int32"),
+                                _dev(out_dist, "float32"), None if opts is None else ctypes.byref(opts),
+                                _stream(stream)))
+
+
+def mrpt_free(ix):
+    if ix:
+        load().mrpt_free(ix)
+
+
+def mrpt_index_info(ix) -> mrpt_index_desc:
+    out = mrpt_index_desc()
+    _check(load().mrpt_index_info(ix, ctypes.byref(out)))
+    return out
+
+
+def mrpt_export_projection(ix):
+    """(rowptr, col, val) numpy arrays of the CSR of the projection vectors."""
+    info = mrpt_index_info(ix)
+    rows = info.T * info.depth
+    rowptr = np.zeros(rows + 1, np.int32)
+    col = np.zeros(max(info.nnz, 1), np.int32)
+    val = np.zeros(max(info.nnz, 1), np.float32)
+    _check(load().mrpt_export_projection(ix, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data))
+    return rowptr, col[:info.nnz], val[:info.nnz]
+
+
+def mrpt_export_tree(ix, t: int):
+    """(splits, perm) numpy arrays of tree t."""
+    info = mrpt_index_info(ix)
+    splits = np.zeros(max((1 << info.depth) - 1, 1), np.float32)
+    perm = np.zeros(info.n, np.int32)
+    _check(load().mrpt_export_tree(ix, t, splits.ctypes.data, perm.ctypes.data))
+    return splits[:(1 << info.depth) - 1], perm
+
+
+def mrpt_export_leaf_offsets(ix):
+    info = mrpt_index_info(ix)
+    off = np.zeros((1 << info.depth) + 1, np.int64)
+    _check(load().mrpt_export_leaf_offsets(ix, off.ctypes.data))
+    return off
+
+
+def mrpt_debug_leaves(ix, Q, leaf, stream=None):
+    _check(load().mrpt_debug_leaves(ix, _dev(Q, "float32"), Q.shape[0], _dev(leaf, "int32"), _stream(stream)))
+
+
+def mrpt_debug_votes(ix, Q, v: int, s_count, s_ids, s_votes, cap: int, stream=None):
+    _check(load().mrpt_debug_votes(ix, _dev(Q, "float32"), Q.shape[0], v, _dev(s_count, "int32"),
+                                   _dev(s_ids, "int32"), None if s_votes is None else _dev(s_votes, "uint8"),
+                                   cap, _stream(stream)))
+
+
+def mrpt_candidate_cap(ix, v: int) -> int:
+    return int(load().mrpt_candidate_cap(ix, v))
+
+
+class Index:
+    """Owning wrapper of an index handle (frees it on close / garbage collection)."""
+
+    def __init__(self, data, T: int, depth: int, a: float, seed: int):
+        self.handle = mrpt_build(data, T, depth, a, seed)
+        self.info = mrpt_index_info(self.handle)
+
+    def query(self, Q, k: int, v: int, precision: int = MRPT_FP32, rerank_factor: int = 4,
+              recheck_rel: float = 1e-6, s_count=None, out=None, stream=None):
+        import torch
+        nq = Q.shape[0]
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int32, device=Q.device),
+                   torch.empty((nq, k), dtype=torch.float32, device=Q.device))
+        o = mrpt_default_opts()
+        o.precision = precision
+        o.rerank_factor = rerank_factor
+        o.recheck_rel = recheck_rel
+        o.s_count = None if s_count is None else s_count.data_ptr()
+        mrpt_query_ex(self.handle, Q, k, v, out[0], out[1], o, stream)
+        return out
+
+    def close(self):
+        if self.handle:
+            mrpt_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

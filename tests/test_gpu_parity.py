@@ -1,0 +1,274 @@
+"""GPU parity of every step of the query path against the oracle, through the
+C ABI: projection vectors, trees, leaves, candidate sets with vote counts,
+and the k nearest neighbours (float32 arm and bfloat16+rerank arm).
+
+Sizes: the mixture-128 (n=10k, d=128) and mnist-like (n=60k, d=784)
+workloads at their full sizes, plus small shapes that hit ragged tiles, the
+generic kernels and the degenerate cases of the method.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_06957_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_helpers import build, check_knn, dev, leaves, query, recall, votes  # noqa: E402
+from paper_1509_06957_amd import mrpt  # noqa: E402
+
+
+def _print_case(name):
+    print(f"[case] {name}", flush=True)
+
+
+class Case:
+    def __init__(self, w: W.Workload, nq=None):
+        w = w if nq is None else w.scaled(nq=nq)
+        self.w = w
+        self.X = W.data(w)
+        self.Q = W.queries(w)
+        self.orc = oracle.build_index(self.X, w.T, w.depth, w.a, w.index_seed)
+        self.gpu = build(self.X, w.T, w.depth, w.a, w.index_seed)
+        self.Qd = dev(self.Q)
+
+
+@pytest.fixture(scope="module", params=["mixture128", "mnist_like"])
+def case(request):
+    _print_case(request.param)
+    c = Case(W.ALL[request.param])
+    yield c
+    c.gpu.close()
+
+
+def test_projection_bit_exact(case):
+    rowptr, col, val = mrpt.mrpt_export_projection(case.gpu.handle)
+    R = np.zeros_like(case.orc.R)
+    for r in range(R.shape[0]):
+        R[r, col[rowptr[r]:rowptr[r + 1]]] = val[rowptr[r]:rowptr[r + 1]]
+        assert np.all(np.diff(col[rowptr[r]:rowptr[r + 1]]) > 0)
+    assert np.array_equal(R.view(np.uint32), case.orc.R.view(np.uint32))
+
+
+def test_trees_bit_exact(case):
+    off = mrpt.mrpt_export_leaf_offsets(case.gpu.handle)
+    assert np.array_equal(off, case.orc.off)
+    for t in range(case.w.T):
+        splits, perm = mrpt.mrpt_export_tree(case.gpu.handle, t)
+        assert np.array_equal(splits.view(np.uint32), case.orc.splits[t].view(np.uint32)), f"tree {t} splits"
+        assert np.array_equal(perm, case.orc.perm[t]), f"tree {t} perm"
+
+
+def test_leaves_bit_exact(case):
+    assert np.array_equal(leaves(case.gpu, case.Qd), oracle.route(case.orc, case.Q))
+
+
+def test_votes_bit_exact(case):
+    w = case.w
+    for v in sorted({1, w.v, w.T}):
+        ref = oracle.query(case.orc, case.Q, w.k, v, want_sets=True)
+        ids, cnt = votes(case.gpu, case.Qd, v)
+        for q in range(len(case.Q)):
+            assert np.array_equal(ids[q], ref["s_ids"][q]), f"v={v} query {q} S"
+            assert np.array_equal(cnt[q], ref["s_votes"][q]), f"v={v} query {q} F"
+
+
+def test_knn_fp32(case):
+    w = case.w
+    ref = oracle.query(case.orc, case.Q, w.k, w.v, want_sets=True)
+    gi, gd, sc = query(case.gpu, case.Qd, w.k, w.v)
+    assert np.array_equal(sc, ref["s_count"])
+    exact = w.kind in ("mnist_like", "sift_like")
+    check_knn(case.X, case.Q, gi, gd, ref["idx"], ref["dist"], exact_ids=exact,
+              S=[set(s.tolist()) for s in ref["s_ids"]])
+    bi, _ = oracle.bruteforce(case.X, case.Q, w.k)
+    print(f"[recall] {w.name} fp32 gpu {recall(gi, bi):.4f} oracle {recall(ref['idx'], bi):.4f}", flush=True)
+
+
+def test_knn_bf16_rerank(case):
+    w = case.w
+    ref = oracle.query(case.orc, case.Q, w.k, w.v)
+    gi, gd, _ = query(case.gpu, case.Qd, w.k, w.v, precision=mrpt.MRPT_BF16_RERANK)
+    fi, fd, _ = query(case.gpu, case.Qd, w.k, w.v)
+    bi, _ = oracle.bruteforce(case.X, case.Q, w.k)
+    r_b, r_f = recall(gi, bi), recall(fi, bi)
+    print(f"[recall] {w.name} bf16+rerank {r_b:.4f} fp32 {r_f:.4f}", flush=True)
+    if w.kind == "mnist_like":
+        # integers <= 255 are exact in bfloat16 and every sum stays below 2^24
+        assert np.array_equal(gi, fi) and np.array_equal(gd, fd)
+    # returned distances are float32/float64 recomputations: always within tolerance
+    for q in range(len(case.Q)):
+        real = gi[q][gi[q] >= 0]
+        d64 = np.sqrt(((case.X[real].astype(np.float64) - case.Q[q].astype(np.float64)) ** 2).sum(1))
+        assert np.all(np.abs(gd[q][:len(real)] - d64) <= 1e-5 * d64 + 1e-6)
+        assert np.all(np.diff(gd[q][:len(real)]) >= -1e-6 * gd[q][len(real) - 1])
+    assert r_b >= r_f - 0.02
+
+
+def test_repeat_is_deterministic(case):
+    w = case.w
+    a = query(case.gpu, case.Qd, w.k, w.v)
+    b = query(case.gpu, case.Qd, w.k, w.v)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+# ---------------------------------------------------------------- edge cases
+
+def _small(n, d, T, depth, seed=0, integer=False, nq=37):
+    rng = np.random.default_rng(seed)
+    if integer:
+        X = rng.integers(0, 4, size=(n, d)).astype(np.float32)
+        Q = rng.integers(0, 4, size=(nq, d)).astype(np.float32)
+    else:
+        X = rng.standard_normal((n, d)).astype(np.float32)
+        Q = rng.standard_normal((nq, d)).astype(np.float32)
+    return X, Q
+
+
+def _full_compare(X, Q, T, depth, a, seed, k, v, exact_ids=False, precision=None):
+    orc = oracle.build_index(X, T, depth, a, seed)
+    g = build(X, T, depth, a, seed)
+    Qd = dev(Q)
+    assert np.array_equal(leaves(g, Qd), oracle.route(orc, Q))
+    ref = oracle.query(orc, Q, k, v, want_sets=True)
+    ids, cnt = votes(g, Qd, v)
+    for q in range(len(Q)):
+        assert np.array_equal(ids[q], ref["s_ids"][q])
+        assert np.array_equal(cnt[q], ref["s_votes"][q])
+    kw = {} if precision is None else {"precision": precision}
+    gi, gd, sc = query(g, Qd, k, v, **kw)
+    assert np.array_equal(sc, ref["s_count"])
+    check_knn(X, Q, gi, gd, ref["idx"], ref["dist"], exact_ids=exact_ids,
+              S=[set(s.tolist()) for s in ref["s_ids"]])
+    g.close()
+    return gi, gd, ref
+
+
+@pytest.mark.parametrize("nq", [1, 63, 64, 65, 130])
+def test_ragged_query_tiles(nq):
+    _print_case(f"ragged nq={nq}")
+    X, Q = _small(3000, 32, 6, 5, seed=nq, nq=nq)
+    _full_compare(X, Q, 6, 5, 0.2, 11, 10, 2)
+
+
+@pytest.mark.parametrize("d", [1, 3, 4, 13, 36, 64, 200, 520])
+def test_dimensions_generic_and_vector_kernels(d):
+    _print_case(f"dim d={d}")
+    X, Q = _small(1500, d, 5, 4, seed=d)
+    a = min(1.0, 1 / np.sqrt(d) * 2)
+    _full_compare(X, Q, 5, 4, a, 3, 7, 1)
+
+
+def test_depth_zero_is_bruteforce():
+    _print_case("depth 0")
+    X, Q = _small(2000, 24, 3, 0, seed=5)
+    gi, gd, ref = _full_compare(X, Q, 3, 0, 0.3, 1, 10, 1)
+    bi, bd = oracle.bruteforce(X, Q, 10)
+    check_knn(X, Q, gi, gd, bi, bd, exact_ids=False)
+
+
+def test_single_tree_and_all_votes():
+    _print_case("T=1 and v=T")
+    X, Q = _small(4000, 16, 1, 6, seed=6)
+    _full_compare(X, Q, 1, 6, 0.5, 2, 5, 1)
+    X, Q = _small(4000, 16, 9, 4, seed=7)
+    _full_compare(X, Q, 9, 4, 0.5, 2, 5, 9)
+
+
+def test_short_candidate_sets_padded():
+    _print_case("padding")
+    X, Q = _small(512, 8, 3, 6, seed=8)   # leaves of 8, v = 3 keeps few
+    gi, gd, ref = _full_compare(X, Q, 3, 6, 0.5, 4, 12, 3)
+    assert np.any(gi == -1)
+
+
+def test_integer_ties_exact():
+    _print_case("integer ties")
+    X, Q = _small(5000, 12, 7, 6, seed=9, integer=True)
+    _full_compare(X, Q, 7, 6, 0.4, 5, 10, 2, exact_ids=True)
+
+
+@pytest.mark.parametrize("k", [1, 64, 65, 100, 300])
+def test_large_k(k):
+    _print_case(f"k={k}")
+    X, Q = _small(6000, 20, 6, 3, seed=k)
+    _full_compare(X, Q, 6, 3, 0.3, 6, k, 1)
+
+
+def test_bf16_generic_shapes():
+    _print_case("bf16 shapes")
+    for d in (8, 96, 256, 960):
+        X, Q = _small(1200, d, 4, 3, seed=d, integer=True)
+        gi_b, gd_b, ref = _full_compare(X, Q, 4, 3, min(1.0, 2 / np.sqrt(d)), 1, 10, 1, exact_ids=True,
+                                        precision=mrpt.MRPT_BF16_RERANK)
+
+
+def test_streams_and_nq_zero():
+    _print_case("stream")
+    X, Q = _small(2000, 32, 4, 4, seed=10)
+    g = build(X, 4, 4, 0.3, 1)
+    Qd = dev(Q)
+    ref = query(g, Qd, 5, 1)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        idx = torch.empty((len(Q), 5), dtype=torch.int32, device="cuda")
+        dist = torch.empty((len(Q), 5), dtype=torch.float32, device="cuda")
+        mrpt.mrpt_query(g.handle, Qd, 5, 1, idx, dist, stream=s)
+    s.synchronize()
+    assert np.array_equal(idx.cpu().numpy(), ref[0])
+    empty = torch.empty((0, 32), dtype=torch.float32, device="cuda")
+    mrpt.mrpt_query(g.handle, empty, 5, 1, idx[:0], dist[:0])
+    g.close()
+
+
+def test_error_paths():
+    _print_case("errors")
+    X, Q = _small(1000, 8, 2, 3, seed=11)
+    Xd, Qd = dev(X), dev(Q)
+    with pytest.raises(mrpt.MrptError) as e:
+        mrpt.mrpt_build(Xd, 2, 11, 0.5, 1)          # 2^11 > n
+    assert e.value.status == mrpt.MRPT_EINVAL
+    for T, a in ((0, 0.5), (256, 0.5), (2, 0.0), (2, 1.5)):
+        with pytest.raises(mrpt.MrptError):
+            mrpt.mrpt_build(Xd, T, 3, a, 1)
+    bad = X.copy()
+    bad[5, 3] = np.nan
+    with pytest.raises(mrpt.MrptError) as e:
+        mrpt.mrpt_build(dev(bad), 2, 3, 0.5, 1)
+    assert e.value.status == mrpt.MRPT_ENONFINITE
+    h = ctypes_build_host_pointer(X)
+    assert h == mrpt.MRPT_EINVAL
+    g = build(X, 2, 3, 0.5, 1)
+    idx = torch.empty((len(Q), 5), dtype=torch.int32, device="cuda")
+    dist = torch.empty((len(Q), 5), dtype=torch.float32, device="cuda")
+    for k, v in ((0, 1), (5, 0), (5, 3), (1025, 1)):
+        with pytest.raises(mrpt.MrptError) as e:
+            mrpt.mrpt_query(g.handle, Qd, k, v, idx, dist)
+        assert e.value.status == mrpt.MRPT_EINVAL
+    Qn = Q.copy()
+    Qn[2, 1] = np.inf
+    o = mrpt.mrpt_default_opts()
+    o.check_finite = 1
+    with pytest.raises(mrpt.MrptError) as e:
+        mrpt.mrpt_query_ex(g.handle, dev(Qn), 5, 1, idx, dist, o)
+    assert e.value.status == mrpt.MRPT_ENONFINITE
+    o.check_finite = 0
+    o.precision = mrpt.MRPT_BF16_RERANK
+    o.rerank_factor = 200
+    with pytest.raises(mrpt.MrptError):
+        mrpt.mrpt_query_ex(g.handle, Qd, 5, 1, idx, dist, o)
+    # a failed call leaves the outputs untouched and a later call works
+    mrpt.mrpt_query(g.handle, Qd, 5, 1, idx, dist)
+    torch.cuda.synchronize()
+    g.close()
+
+
+def ctypes_build_host_pointer(X):
+    import ctypes
+    lib = mrpt.load()
+    h = ctypes.c_void_p()
+    Xc = np.ascontiguousarray(X)
+    return lib.mrpt_build(ctypes.c_void_p(Xc.ctypes.data), Xc.shape[0], Xc.shape[1], 2, 3, 0.5, 1,
+                          ctypes.byref(h))
