@@ -21,7 +21,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "queries/sec at recall@10=0.9 (1M×128, k=10); FP32 plain vs BF16+rerank"
-KERNEL_SRC = os.path.join(ROOT, "paper_1509_06957_amd", "csrc", "kernels_query.hip")
+CSRC = os.path.join(ROOT, "paper_1509_06957_amd", "csrc")
+KERNEL_FILE = {"route_kernel": "kernels_route.hip", "vote_kernel": "kernels_vote.hip",
+               "dist_fp32_kernel": "kernels_search.hip", "dist_bf16_kernel": "kernels_search.hip"}
 STAGES = ("route", "vote", "search")
 
 
@@ -41,9 +43,12 @@ def parse():
     return p.parse_args()
 
 
-def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_source_hash(kernel):
+    h = hashlib.sha256()
+    for name in (KERNEL_FILE[kernel], "device_common.h"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(kernel, workload_key):
@@ -58,7 +63,7 @@ def read_traffic(kernel, workload_key):
             if ":" in line and not line.startswith("#"):
                 key, val = line.split(":", 1)
                 vals[key.strip()] = val.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])

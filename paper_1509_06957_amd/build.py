@@ -7,7 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrpt.so")
-SOURCES = ["abi.cpp", "host_build.cpp", "kernels_query.hip", "kernels_misc.hip"]
+SOURCES = ["abi.cpp", "host_build.cpp", "kernels_route.hip", "kernels_vote.hip", "kernels_search.hip",
+           "kernels_misc.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

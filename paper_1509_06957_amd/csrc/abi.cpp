@@ -224,10 +224,7 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
     ix->n = n; ix->d = d; ix->T = T; ix->depth = depth; ix->a = a; ix->seed = seed;
     ix->nleaf = 1 << depth;
     ix->max_leaf = (int32_t)((n + ix->nleaf - 1) / ix->nleaf);
-    {
-        const int64_t padded = (n + 15) / 16 * 16;
-        ix->id_chunk = (int32_t)std::min<int64_t>(padded, kVoteChunk);
-    }
+    ix->id_chunk = (int32_t)std::min<int64_t>(n, 77 * 1024 * 8);
     MRPT_HIP_TRY(hipGetDevice(&ix->device));
 
     struct Guard {
@@ -265,6 +262,9 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
     MRPT_HIP_TRY(hipMemcpy(hX.data(), ix->X, nd * sizeof(float), hipMemcpyDeviceToHost));
 
     generate_projection(d, T, depth, a, seed, ix->h_rowptr, ix->h_col, ix->h_val);
+    for (int32_t t = 0; t < T; ++t)
+        ix->max_tree_nnz = std::max(ix->max_tree_nnz, ix->h_rowptr[(size_t)(t + 1) * depth] -
+                                                        ix->h_rowptr[(size_t)t * depth]);
     HostTrees trees;
     grow_trees_host(hX.data(), n, d, T, depth, ix->h_rowptr, ix->h_col, ix->h_val, trees);
     ix->h_off = trees.off;

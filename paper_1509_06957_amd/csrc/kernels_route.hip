@@ -1,0 +1,183 @@
+// Routing kernel: the sparse projection of a query tile onto the depth
+// vectors of a tree (Sec. II-C: one vector per tree level, so a query's
+// T*depth projections form one sparse product) fused with the descent of
+// Alg. 3: at level j the query goes left when its projection is <= the node's
+// split (Sec. III), right otherwise.
+//
+// Layout of one workgroup: one wave per tree (trees_per_block trees), lanes =
+// 64 queries of a tile; the workgroup walks `tiles` consecutive query tiles so
+// the staged tables are reused.  LDS holds the split tables of its trees
+// (heap order), their CSR rows, and the current query tile transposed
+// ([feature][query], row stride 65 to spread the banks).  Every projection is
+// a float32 fused multiply-add chain in ascending feature order from +0.
+#include "device_common.h"
+#include "mrpt_internal.h"
+
+namespace mrpt {
+namespace {
+
+using namespace dev;
+
+constexpr int kQStride = 65;
+
+template <int MAXL>
+__global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q, int64_t nq, int32_t d,
+                                                    const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const float* __restrict__ val,
+                                                    const float* __restrict__ splits, int32_t T,
+                                                    int32_t depth, int32_t trees_per_block, int32_t tiles,
+                                                    int32_t fb_size, int32_t splits_in_lds, int32_t csr_cap,
+                                                    int32_t* __restrict__ leaf) {
+    extern __shared__ float route_smem[];
+    const int nsplit = (1 << depth) - 1;
+    float* qt = route_smem;                                   // [fb_size][65]
+    float* sp = qt + fb_size * kQStride;                      // [trees_per_block][nsplit] (if staged)
+    float* cv = sp + (splits_in_lds ? trees_per_block * nsplit : 0);  // [trees_per_block][csr_cap]
+    int32_t* cc = reinterpret_cast<int32_t*>(cv + trees_per_block * csr_cap);
+    const int lane = lane_id();
+    const int w = uniform((int)(threadIdx.x >> 6));
+    const int t = uniform((int)blockIdx.y * trees_per_block + w);
+    const bool tree_ok = t < T;
+    const int nthreads = (int)blockDim.x;
+    const int t_first = (int)blockIdx.y * trees_per_block;
+
+    // stage split tables and CSR rows of this block's trees
+    if (splits_in_lds) {
+        for (int i = (int)threadIdx.x; i < trees_per_block * nsplit; i += nthreads) {
+            const int tw = i / nsplit;
+            const int tt = t_first + tw;
+            sp[i] = tt < T ? splits[(int64_t)tt * nsplit + (i - tw * nsplit)] : 0.0f;
+        }
+    }
+    const int row0 = tree_ok ? uniform(rowptr[(int64_t)t * depth]) : 0;
+    const int row_end = tree_ok ? uniform(rowptr[(int64_t)(t + 1) * depth]) : 0;
+    if (csr_cap > 0) {
+        for (int i = (int)threadIdx.x; i < trees_per_block * csr_cap; i += nthreads) {
+            const int tw = i / csr_cap, e = i - tw * csr_cap;
+            const int tt = t_first + tw;
+            float vv = 0.0f;
+            int32_t c = 0;
+            if (tt < T) {
+                const int b = rowptr[(int64_t)tt * depth];
+                if (b + e < rowptr[(int64_t)(tt + 1) * depth]) {
+                    vv = val[b + e];
+                    c = col[b + e];
+                }
+            }
+            cv[i] = vv;
+            cc[i] = c;
+        }
+    }
+    const float* my_val = csr_cap > 0 ? cv + w * csr_cap - row0 : val;  // indexed by global entry
+    const int32_t* my_col = csr_cap > 0 ? cc + w * csr_cap - row0 : col;
+
+    int rp[MAXL + 1];
+#pragma unroll
+    for (int j = 0; j <= MAXL; ++j) rp[j] = (j <= depth && tree_ok) ? uniform(rowptr[(int64_t)t * depth + j]) : 0;
+    (void)row_end;
+
+    for (int tile = 0; tile < tiles; ++tile) {
+        const int64_t q0 = ((int64_t)blockIdx.x * tiles + tile) * kWave;
+        if (q0 >= nq) break;
+        float acc[MAXL];
+        int ptr[MAXL];
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) {
+            acc[j] = 0.0f;
+            ptr[j] = rp[j];
+        }
+        for (int fb = 0; fb < d; fb += fb_size) {
+            __syncthreads();
+            const int fcount = d - fb < fb_size ? d - fb : fb_size;
+            for (int i = (int)threadIdx.x; i < kWave * fcount; i += nthreads) {
+                const int qq = i / fcount, f = i - qq * fcount;
+                const int64_t gq = q0 + qq;
+                qt[f * kQStride + qq] = gq < nq ? Q[gq * d + fb + f] : 0.0f;
+            }
+            __syncthreads();
+            const int fe = fb + fcount;
+#pragma unroll
+            for (int j = 0; j < MAXL; ++j) {
+                if (j < depth) {
+                    int p = ptr[j];
+                    const int e = rp[j + 1];
+                    float a = acc[j];
+                    while (p < e) {
+                        const int c = my_col[p];
+                        if (c >= fe) break;
+                        a = __builtin_fmaf(qt[(c - fb) * kQStride + lane], my_val[p], a);
+                        ++p;
+                    }
+                    acc[j] = a;
+                    ptr[j] = p;
+                }
+            }
+        }
+        const int64_t q = q0 + lane;
+        if (tree_ok && q < nq) {
+            int node = 0;
+#pragma unroll
+            for (int j = 0; j < MAXL; ++j) {
+                if (j < depth) {
+                    const float s = splits_in_lds ? sp[w * nsplit + node] : splits[(int64_t)t * nsplit + node];
+                    node = (acc[j] <= s) ? 2 * node + 1 : 2 * node + 2;
+                }
+            }
+            leaf[q * T + t] = node - nsplit;
+        }
+    }
+}
+
+}  // namespace
+
+int lds_per_block_limit() {
+    static int limit = -1;
+    if (limit < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        limit = v;
+    }
+    return limit;
+}
+
+hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    const int depth = ix->depth;
+    const int nsplit = (1 << depth) - 1;
+    const int limit = std::min(lds_per_block_limit(), 80 * 1024);   // two workgroups per CU
+    const int d = ix->d;
+    int tpb = std::min(4, ix->T);
+    int fb = std::min(d, 128);
+    int csr_cap = ix->max_tree_nnz;
+    int splits_in_lds = 1;
+    auto bytes = [&](int tp, int f, int sl, int cc) {
+        return (size_t)f * kQStride * 4 + (sl ? (size_t)tp * nsplit * 4 : 0) + (size_t)tp * cc * 8;
+    };
+    while (tpb > 1 && bytes(tpb, fb, 1, csr_cap) > (size_t)limit) --tpb;
+    if (bytes(tpb, fb, 1, csr_cap) > (size_t)limit) splits_in_lds = 0;
+    if (bytes(tpb, fb, splits_in_lds, csr_cap) > (size_t)limit) csr_cap = 0;
+    while (fb > 8 && bytes(tpb, fb, splits_in_lds, csr_cap) > (size_t)limit) fb /= 2;
+    const size_t lds = bytes(tpb, fb, splits_in_lds, csr_cap);
+    const int64_t ntiles = (nq + kWave - 1) / kWave;
+    const int tiles = ntiles >= 4 * 256 ? 4 : (ntiles >= 2 * 256 ? 2 : 1);
+    dim3 grid((unsigned)((ntiles + tiles - 1) / tiles), (unsigned)((ix->T + tpb - 1) / tpb));
+    dim3 block(kWave * tpb);
+#define MRPT_ROUTE(ML)                                                                                  \
+    do {                                                                                                \
+        (void)hipFuncSetAttribute((const void*)route_kernel<ML>,                                        \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+        hipLaunchKernelGGL(route_kernel<ML>, grid, block, lds, s, Q, nq, d, ix->rowptr, ix->col, ix->val, \
+                           ix->splits, ix->T, depth, tpb, tiles, fb, splits_in_lds, csr_cap, leaf);     \
+    } while (0)
+    if (depth <= 8) MRPT_ROUTE(8);
+    else if (depth <= 12) MRPT_ROUTE(12);
+    else if (depth <= 16) MRPT_ROUTE(16);
+    else MRPT_ROUTE(24);
+#undef MRPT_ROUTE
+    return hipGetLastError();
+}
+
+}  // namespace mrpt

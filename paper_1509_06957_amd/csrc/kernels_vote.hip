@@ -1,0 +1,246 @@
+// Vote kernel (Sec. III-A, Alg. 4): for one query, F(x; q) counts the trees
+// whose leaf holds both x and q, and x joins S when its count reaches v.
+//
+// One workgroup per query.  Each wave owns trees w, w+NW, ...; their leaf
+// lists (ascending ids, contiguous in the tree's permutation) are loaded as
+// 64-id windows into registers once.  Counting runs in passes over id ranges
+// that fit a packed LDS counter array of B bits per id, where B is the
+// smallest width that can hold v (1 bit for v = 1, 2 bits for v <= 3, ...):
+// a counter saturates at v, so a point is appended to S exactly once, by the
+// thread whose update moves its counter from v-1 to v, as in Alg. 4.  After
+// a pass only the words that were touched are reset, so the array is cleared
+// in full once per query.  Windows that do not fit the register budget are
+// re-read from memory in every pass (and then the array is cleared in full).
+#include "device_common.h"
+#include "mrpt_internal.h"
+
+namespace mrpt {
+namespace {
+
+using namespace dev;
+
+constexpr int kVoteWaves = 16;
+constexpr int kVoteBlock = kVoteWaves * kWave;
+constexpr int kVoteSlots = 32;
+
+// one occurrence of id (rel = id - first id of the pass); true when this
+// occurrence is the v-th
+template <int B>
+__device__ __forceinline__ bool count_id(uint32_t* cnt, uint32_t rel, int v) {
+    constexpr uint32_t per = 32u / B;
+    const uint32_t word = rel / per;
+    const uint32_t sh = (rel % per) * B;
+    if constexpr (B == 1) {
+        const uint32_t bit = 1u << sh;
+        if (cnt[word] & bit) return false;
+        return (atomicOr(&cnt[word], bit) & bit) == 0u;
+    } else if constexpr (B == 8) {
+        if ((int)((cnt[word] >> sh) & 0xffu) >= v) return false;
+        const uint32_t old = atomicAdd(&cnt[word], 1u << sh);
+        return (int)((old >> sh) & 0xffu) + 1 == v;
+    } else {
+        constexpr uint32_t mask = (1u << B) - 1u;
+        uint32_t old = cnt[word];
+        while (true) {
+            const int c = (int)((old >> sh) & mask);
+            if (c >= v) return false;
+            const uint32_t prev = atomicCAS(&cnt[word], old, old + (1u << sh));
+            if (prev == old) return c + 1 == v;
+            old = prev;
+        }
+    }
+}
+
+// wave-aggregated append of the ids whose `elect` is set
+__device__ __forceinline__ void append(bool elect, int32_t id, int* nsel, int32_t* out, int64_t cap) {
+    const uint64_t m = __ballot(elect);
+    if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(nsel, __popcll(m));
+        base = __shfl(base, leader);
+        if (elect) {
+            const int64_t p = (int64_t)base + __popcll(m & __lanemask_lt());
+            if (p < cap) out[p] = id;
+        }
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restrict__ leaf,
+                                                          const int32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ off, int64_t n,
+                                                          int32_t T, int32_t v, int32_t chunk,
+                                                          int32_t* __restrict__ s_ids, int64_t cap,
+                                                          int32_t* __restrict__ s_count) {
+    extern __shared__ uint32_t vote_cnt[];   // chunk * B / 32 words
+    __shared__ int64_t tbase[kMaxT];
+    __shared__ int32_t tlen[kMaxT];
+    __shared__ int nsel;
+    __shared__ int spill;
+    constexpr int per = 32 / B;
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id();
+    const int w = uniform(tid >> 6);
+    const int64_t q = blockIdx.x;
+    const int words = chunk / per;
+
+    if (tid < T) {
+        const int L = leaf[q * T + tid];
+        const int b = off[L];
+        tbase[tid] = (int64_t)tid * n + b;
+        tlen[tid] = off[L + 1] - b;
+    }
+    if (tid == 0) { nsel = 0; spill = 0; }
+    for (int i = tid; i < (words >> 2); i += kVoteBlock)
+        reinterpret_cast<uint4*>(vote_cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+
+    // register windows: slot s holds window (tree jj, 64-id block uu) of this wave
+    int32_t ids[kVoteSlots];
+    int jj = w, uu = 0;
+#pragma unroll
+    for (int s = 0; s < kVoteSlots; ++s) {
+        ids[s] = -1;
+        if (jj < T) {
+            const int len = uniform(tlen[jj]);
+            const int e = uu * kWave + lane;
+            if (e < len) ids[s] = perm[tbase[jj] + e];
+            ++uu;
+            if (uu * kWave >= len) { uu = 0; jj += kVoteWaves; }
+        }
+    }
+    const int spill_j = jj, spill_u = uu;   // first window that did not fit
+    if (lane == 0 && spill_j < T) spill = 1;
+    __syncthreads();
+    const bool full_clear = spill != 0;
+
+    int32_t* out = s_ids + q * cap;
+    for (int64_t lo = 0; lo < n; lo += chunk) {
+        const int64_t hi = lo + chunk < n ? lo + chunk : n;
+#pragma unroll
+        for (int s = 0; s < kVoteSlots; ++s) {
+            const int32_t id = ids[s];
+            const bool in = id >= lo && id < hi;
+            bool elect = false;
+            if (in) elect = count_id<B>(vote_cnt, (uint32_t)(id - lo), v);
+            append(elect, id, &nsel, out, cap);
+        }
+        for (int j2 = spill_j, u2 = spill_u; j2 < T;) {
+            int32_t sid[8];                 // 8 windows in flight
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                sid[b] = -1;
+                if (j2 < T) {
+                    const int len = uniform(tlen[j2]);
+                    const int e = u2 * kWave + lane;
+                    if (e < len) sid[b] = perm[tbase[j2] + e];
+                    ++u2;
+                    if (u2 * kWave >= len) { u2 = 0; j2 += kVoteWaves; }
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool in = sid[b] >= lo && sid[b] < hi;
+                bool elect = false;
+                if (in) elect = count_id<B>(vote_cnt, (uint32_t)(sid[b] - lo), v);
+                append(elect, sid[b], &nsel, out, cap);
+            }
+        }
+        if (hi >= n) break;
+        __syncthreads();
+        if (full_clear) {
+            for (int i = tid; i < (words >> 2); i += kVoteBlock)
+                reinterpret_cast<uint4*>(vote_cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+#pragma unroll
+            for (int s = 0; s < kVoteSlots; ++s) {
+                const int32_t id = ids[s];
+                if (id >= lo && id < hi) vote_cnt[(uint32_t)(id - lo) / per] = 0u;
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (tid == 0) s_count[q] = nsel < cap ? nsel : (int32_t)cap;
+}
+
+// debug: F(x; q) of every listed candidate, by binary search of x in each of
+// the query's T leaf lists (independent of the counting kernel)
+__global__ __launch_bounds__(256) void vote_counts_kernel(const int32_t* __restrict__ leaf,
+                                                          const int32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ off, int64_t n,
+                                                          int32_t T, const int32_t* __restrict__ s_ids,
+                                                          int64_t cap, const int32_t* __restrict__ s_count,
+                                                          uint8_t* __restrict__ s_votes) {
+    const int64_t q = blockIdx.x;
+    const int ns = s_count[q];
+    for (int i = (int)threadIdx.x; i < ns; i += (int)blockDim.x) {
+        const int32_t x = s_ids[q * cap + i];
+        int F = 0;
+        for (int t = 0; t < T; ++t) {
+            const int L = leaf[q * T + t];
+            const int32_t* lst = perm + (int64_t)t * n;
+            int lo = off[L], hi = off[L + 1];
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (lst[mid] < x) lo = mid + 1; else hi = mid;
+            }
+            F += (lo < off[L + 1] && lst[lo] == x) ? 1 : 0;
+        }
+        s_votes[q * cap + i] = (uint8_t)F;
+    }
+}
+
+__global__ void copy_counts_kernel(const int32_t* __restrict__ src, int64_t nq, int32_t* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nq) dst[i] = src[i];
+}
+
+template <int B>
+hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
+                         int64_t cap, int32_t* s_count, hipStream_t s) {
+    constexpr int per = 32 / B;
+    constexpr size_t kStatic = kMaxT * 8 + kMaxT * 4 + 16;
+    // 16 waves of ~85 VGPRs hold a CU: the workgroup may take all of its LDS
+    const size_t budget = (size_t)std::min(lds_per_block_limit(), 160 * 1024) - kStatic;
+    // ids per pass: a multiple of 4 words' worth of ids, at most what the budget holds
+    int64_t chunk = (int64_t)(budget / 16) * 4 * per;
+    const int64_t padded = (ix->n + 4 * per - 1) / (4 * per) * (4 * per);
+    if (chunk > padded) chunk = padded;
+    // same number of passes, smaller array
+    const int64_t passes = (ix->n + chunk - 1) / chunk;
+    chunk = ((ix->n + passes - 1) / passes + 4 * per - 1) / (4 * per) * (4 * per);
+    const size_t lds = (size_t)(chunk / per) * 4;
+    (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)nq), dim3(kVoteBlock), lds, s, leaf, ix->perm, ix->off, ix->n,
+                       ix->T, v, (int32_t)chunk, s_ids, cap, s_count);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
+                       int64_t cap, int32_t* s_count, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    if (v == 1) return launch_vote_b<1>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+    if (v <= 3) return launch_vote_b<2>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+    if (v <= 15) return launch_vote_b<4>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+    return launch_vote_b<8>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+}
+
+hipError_t launch_vote_counts(const mrpt_index* ix, const int32_t* leaf, int64_t nq, const int32_t* s_ids,
+                              int64_t cap, const int32_t* s_count, uint8_t* s_votes, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(vote_counts_kernel, dim3((unsigned)nq), dim3(256), 0, s, leaf, ix->perm, ix->off, ix->n,
+                       ix->T, s_ids, cap, s_count, s_votes);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_counts(const int32_t* src, int64_t nq, int32_t* dst, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_counts_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, src, nq, dst);
+    return hipGetLastError();
+}
+
+}  // namespace mrpt

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -34,7 +35,6 @@ constexpr int kMaxT = 255;          // 8-bit vote counters
 constexpr int kMaxDepth = 24;
 constexpr int kMaxK = 1024;
 constexpr int kMaxRerank = 512;     // rerank_factor * k
-constexpr int kVoteChunk = 65536;   // ids per LDS counting pass (bytes of LDS)
 
 // ---------------------------------------------------------------- index
 struct DeviceBuf {
@@ -61,7 +61,8 @@ struct mrpt_index {
     uint64_t seed = 0;
     int32_t nleaf = 1;           // 2^depth
     int32_t max_leaf = 0;        // ceil(n / 2^depth)
-    int32_t id_chunk = 0;        // ids per vote pass (<= kVoteChunk, multiple of 16)
+    int32_t id_chunk = 0;        // ids per vote pass at v = 1 (reported by mrpt_index_info)
+    int32_t max_tree_nnz = 0;    // largest number of projection nonzeros of one tree
     int device = 0;
 
     // host copy of the projection CSR (for export)
@@ -102,7 +103,7 @@ void grow_trees_host(const float* X, int64_t n, int32_t d, int32_t T, int32_t de
                      const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,
                      const std::vector<float>& val, HostTrees& out);
 
-// kernel launchers (kernels_query.hip / kernels_misc.hip); all asynchronous
+// kernel launchers (kernels_route/vote/search/misc.hip); all asynchronous
 hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf,
                         hipStream_t s);
 hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v,
