@@ -20,7 +20,7 @@ using namespace dev;
 
 constexpr int kQStride = 65;
 
-template <int MAXL>
+template <int MAXL, bool CSR_LDS, bool SPLITS_LDS>
 __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q, int64_t nq, int32_t d,
                                                     const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ col,
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q,
     const int t_first = (int)blockIdx.y * trees_per_block;
 
     // stage split tables and CSR rows of this block's trees
-    if (splits_in_lds) {
+    if constexpr (SPLITS_LDS) {
         for (int i = (int)threadIdx.x; i < trees_per_block * nsplit; i += nthreads) {
             const int tw = i / nsplit;
             const int tt = t_first + tw;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q,
     }
     const int row0 = tree_ok ? uniform(rowptr[(int64_t)t * depth]) : 0;
     const int row_end = tree_ok ? uniform(rowptr[(int64_t)(t + 1) * depth]) : 0;
-    if (csr_cap > 0) {
+    if constexpr (CSR_LDS) {
         for (int i = (int)threadIdx.x; i < trees_per_block * csr_cap; i += nthreads) {
             const int tw = i / csr_cap, e = i - tw * csr_cap;
             const int tt = t_first + tw;
@@ -69,8 +69,9 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q,
             cc[i] = c;
         }
     }
-    const float* my_val = csr_cap > 0 ? cv + w * csr_cap - row0 : val;  // indexed by global entry
-    const int32_t* my_col = csr_cap > 0 ? cc + w * csr_cap - row0 : col;
+    // entry p of this tree (row0 <= p < row_end) sits at LDS index p - row0 + w*csr_cap;
+    // the index is formed in integers so the LDS address never leaves the array
+    const int lds_shift = w * csr_cap - row0;
 
     int rp[MAXL + 1];
 #pragma unroll
@@ -103,11 +104,20 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q,
                     int p = ptr[j];
                     const int e = rp[j + 1];
                     float a = acc[j];
-                    while (p < e) {
-                        const int c = my_col[p];
-                        if (c >= fe) break;
-                        a = __builtin_fmaf(qt[(c - fb) * kQStride + lane], my_val[p], a);
-                        ++p;
+                    if constexpr (CSR_LDS) {
+                        while (p < e) {
+                            const int c = cc[p + lds_shift];
+                            if (c >= fe) break;
+                            a = __builtin_fmaf(qt[(c - fb) * kQStride + lane], cv[p + lds_shift], a);
+                            ++p;
+                        }
+                    } else {
+                        while (p < e) {
+                            const int c = col[p];
+                            if (c >= fe) break;
+                            a = __builtin_fmaf(qt[(c - fb) * kQStride + lane], val[p], a);
+                            ++p;
+                        }
                     }
                     acc[j] = a;
                     ptr[j] = p;
@@ -120,7 +130,9 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q,
 #pragma unroll
             for (int j = 0; j < MAXL; ++j) {
                 if (j < depth) {
-                    const float s = splits_in_lds ? sp[w * nsplit + node] : splits[(int64_t)t * nsplit + node];
+                    float s;
+                    if constexpr (SPLITS_LDS) s = sp[w * nsplit + node];
+                    else s = splits[(int64_t)t * nsplit + node];
                     node = (acc[j] <= s) ? 2 * node + 1 : 2 * node + 2;
                 }
             }
@@ -165,18 +177,27 @@ hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_
     const int tiles = ntiles >= 4 * 256 ? 4 : (ntiles >= 2 * 256 ? 2 : 1);
     dim3 grid((unsigned)((ntiles + tiles - 1) / tiles), (unsigned)((ix->T + tpb - 1) / tpb));
     dim3 block(kWave * tpb);
-#define MRPT_ROUTE(ML)                                                                                  \
+#define MRPT_ROUTE_K(ML, CL, SL)                                                                        \
     do {                                                                                                \
-        (void)hipFuncSetAttribute((const void*)route_kernel<ML>,                                        \
+        (void)hipFuncSetAttribute((const void*)route_kernel<ML, CL, SL>,                                \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-        hipLaunchKernelGGL(route_kernel<ML>, grid, block, lds, s, Q, nq, d, ix->rowptr, ix->col, ix->val, \
-                           ix->splits, ix->T, depth, tpb, tiles, fb, splits_in_lds, csr_cap, leaf);     \
+        hipLaunchKernelGGL((route_kernel<ML, CL, SL>), grid, block, lds, s, Q, nq, d, ix->rowptr, ix->col, \
+                           ix->val, ix->splits, ix->T, depth, tpb, tiles, fb, splits_in_lds, csr_cap,    \
+                           leaf);                                                                       \
+    } while (0)
+#define MRPT_ROUTE(ML)                                          \
+    do {                                                        \
+        if (csr_cap > 0 && splits_in_lds) MRPT_ROUTE_K(ML, true, true); \
+        else if (csr_cap > 0) MRPT_ROUTE_K(ML, true, false);    \
+        else if (splits_in_lds) MRPT_ROUTE_K(ML, false, true);  \
+        else MRPT_ROUTE_K(ML, false, false);                    \
     } while (0)
     if (depth <= 8) MRPT_ROUTE(8);
     else if (depth <= 12) MRPT_ROUTE(12);
     else if (depth <= 16) MRPT_ROUTE(16);
     else MRPT_ROUTE(24);
 #undef MRPT_ROUTE
+#undef MRPT_ROUTE_K
     return hipGetLastError();
 }
 
