@@ -265,6 +265,8 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
     for (int32_t t = 0; t < T; ++t)
         ix->max_tree_nnz = std::max(ix->max_tree_nnz, ix->h_rowptr[(size_t)(t + 1) * depth] -
                                                         ix->h_rowptr[(size_t)t * depth]);
+    for (size_t r = 0; r + 1 < ix->h_rowptr.size(); ++r)
+        ix->max_row_nnz = std::max(ix->max_row_nnz, ix->h_rowptr[r + 1] - ix->h_rowptr[r]);
     HostTrees trees;
     grow_trees_host(hX.data(), n, d, T, depth, ix->h_rowptr, ix->h_col, ix->h_val, trees);
     ix->h_off = trees.off;

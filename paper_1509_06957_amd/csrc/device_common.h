@@ -22,6 +22,14 @@ __device__ __forceinline__ float read_lane_f(float x, int lane) {
 }
 __device__ __forceinline__ int read_lane_i(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
 
+// workgroup barrier that orders LDS accesses only: outstanding global loads
+// stay in flight across it (a full __syncthreads waits for them)
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // strict order on (distance, id): the order in which k-NN results are ranked
 __device__ __forceinline__ bool key_less(float da, int32_t ia, float db, int32_t ib) {
     return da < db || (da == db && ia < ib);

@@ -141,6 +141,105 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q,
     }
 }
 
+// Fast form, used when every projection vector has at most 64 nonzeros: the
+// wave's tree keeps row j of its CSR in registers (lane e holds entry e of
+// the row) and all depth levels advance together, step k adding the k-th
+// nonzero of every row, so the depth fused multiply-add chains overlap; each
+// chain still runs in ascending feature order.  The query tile sits in LDS
+// whole ([feature][query]) when it fits (QLDS), else each lane reads its own
+// query row from memory.
+template <int MAXL, bool QLDS, bool SPLITS_LDS>
+__global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict__ Q, int64_t nq, int32_t d,
+                                                         const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const float* __restrict__ val,
+                                                         const float* __restrict__ splits, int32_t T,
+                                                         int32_t depth, int32_t trees_per_block, int32_t tiles,
+                                                         int32_t* __restrict__ leaf) {
+    extern __shared__ float route_smem[];
+    const int nsplit = (1 << depth) - 1;
+    float* qt = route_smem;                                   // [d][65] when QLDS
+    float* sp = qt + (QLDS ? d * kQStride : 0);               // [trees_per_block][nsplit]
+    const int lane = lane_id();
+    const int w = uniform((int)(threadIdx.x >> 6));
+    const int t = uniform((int)blockIdx.y * trees_per_block + w);
+    const bool tree_ok = t < T;
+    const int nthreads = (int)blockDim.x;
+    const int t_first = (int)blockIdx.y * trees_per_block;
+
+    if constexpr (SPLITS_LDS) {
+        for (int i = (int)threadIdx.x; i < trees_per_block * nsplit; i += nthreads) {
+            const int tw = i / nsplit;
+            const int tt = t_first + tw;
+            sp[i] = tt < T ? splits[(int64_t)tt * nsplit + (i - tw * nsplit)] : 0.0f;
+        }
+    }
+    int len[MAXL];
+    int colr[MAXL];
+    float valr[MAXL];
+    int maxlen = 0;
+#pragma unroll
+    for (int j = 0; j < MAXL; ++j) {
+        len[j] = 0;
+        colr[j] = 0;
+        valr[j] = 0.0f;
+        if (j < depth && tree_ok) {
+            const int b = uniform(rowptr[(int64_t)t * depth + j]);
+            len[j] = uniform(rowptr[(int64_t)t * depth + j + 1]) - b;
+            if (lane < len[j]) {
+                colr[j] = col[b + lane];
+                valr[j] = val[b + lane];
+            }
+            maxlen = len[j] > maxlen ? len[j] : maxlen;
+        }
+    }
+
+    for (int tile = 0; tile < tiles; ++tile) {
+        const int64_t q0 = ((int64_t)blockIdx.x * tiles + tile) * kWave;
+        if (q0 >= nq) break;
+        const int64_t q = q0 + lane;
+        if constexpr (QLDS) {
+            __syncthreads();
+            for (int i = (int)threadIdx.x; i < kWave * d; i += nthreads) {
+                const int qq = i / d, f = i - qq * d;
+                const int64_t gq = q0 + qq;
+                qt[f * kQStride + qq] = gq < nq ? Q[gq * d + f] : 0.0f;
+            }
+        }
+        __syncthreads();
+        const float* qrow = Q + (q < nq ? q : nq - 1) * d;
+        float acc[MAXL];
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) acc[j] = 0.0f;
+        for (int k = 0; k < maxlen; ++k) {
+#pragma unroll
+            for (int j = 0; j < MAXL; ++j) {
+                if (j < depth && k < len[j]) {
+                    const int c = read_lane_i(colr[j], k);
+                    const float v = read_lane_f(valr[j], k);
+                    float x;
+                    if constexpr (QLDS) x = qt[c * kQStride + lane];
+                    else x = qrow[c];
+                    acc[j] = __builtin_fmaf(x, v, acc[j]);
+                }
+            }
+        }
+        if (tree_ok && q < nq) {
+            int node = 0;
+#pragma unroll
+            for (int j = 0; j < MAXL; ++j) {
+                if (j < depth) {
+                    float s;
+                    if constexpr (SPLITS_LDS) s = sp[w * nsplit + node];
+                    else s = splits[(int64_t)t * nsplit + node];
+                    node = (acc[j] <= s) ? 2 * node + 1 : 2 * node + 2;
+                }
+            }
+            leaf[q * T + t] = node - nsplit;
+        }
+    }
+}
+
 }  // namespace
 
 int lds_per_block_limit() {
@@ -155,8 +254,52 @@ int lds_per_block_limit() {
     return limit;
 }
 
+namespace {
+
+hipError_t launch_route_fast(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s) {
+    const int depth = ix->depth;
+    const int nsplit = (1 << depth) - 1;
+    const int d = ix->d;
+    const size_t limit = (size_t)std::min(lds_per_block_limit(), 160 * 1024);
+    const size_t q_bytes = (size_t)d * kQStride * 4;
+    const bool qlds = q_bytes <= 96 * 1024;
+    int tpb = std::min(4, ix->T);
+    const size_t base = qlds ? q_bytes : 0;
+    while (tpb > 1 && base + (size_t)tpb * nsplit * 4 > limit) --tpb;
+    const bool spl = base + (size_t)tpb * nsplit * 4 <= limit;
+    const size_t lds = base + (spl ? (size_t)tpb * nsplit * 4 : 0);
+    const int64_t ntiles = (nq + kWave - 1) / kWave;
+    const int tiles = ntiles >= 4 * 256 ? 4 : (ntiles >= 2 * 256 ? 2 : 1);
+    dim3 grid((unsigned)((ntiles + tiles - 1) / tiles), (unsigned)((ix->T + tpb - 1) / tpb));
+    dim3 block(kWave * tpb);
+#define MRPT_ROUTE_F(ML, QL, SL)                                                                             \
+    do {                                                                                                     \
+        (void)hipFuncSetAttribute((const void*)route_fast_kernel<ML, QL, SL>,                                \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                     \
+        hipLaunchKernelGGL((route_fast_kernel<ML, QL, SL>), grid, block, lds, s, Q, nq, d, ix->rowptr, ix->col, \
+                           ix->val, ix->splits, ix->T, depth, tpb, tiles, leaf);                             \
+    } while (0)
+#define MRPT_ROUTE_FQ(ML)                                      \
+    do {                                                       \
+        if (qlds && spl) MRPT_ROUTE_F(ML, true, true);         \
+        else if (qlds) MRPT_ROUTE_F(ML, true, false);          \
+        else if (spl) MRPT_ROUTE_F(ML, false, true);           \
+        else MRPT_ROUTE_F(ML, false, false);                   \
+    } while (0)
+    if (depth <= 8) MRPT_ROUTE_FQ(8);
+    else if (depth <= 12) MRPT_ROUTE_FQ(12);
+    else if (depth <= 16) MRPT_ROUTE_FQ(16);
+    else MRPT_ROUTE_FQ(24);
+#undef MRPT_ROUTE_FQ
+#undef MRPT_ROUTE_F
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s) {
     if (nq == 0) return hipSuccess;
+    if (ix->max_row_nnz <= kWave) return launch_route_fast(ix, Q, nq, leaf, s);
     const int depth = ix->depth;
     const int nsplit = (1 << depth) - 1;
     const int limit = std::min(lds_per_block_limit(), 80 * 1024);   // two workgroups per CU

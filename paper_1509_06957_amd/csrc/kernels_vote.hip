@@ -165,6 +165,167 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
     if (tid == 0) s_count[q] = nsel < cap ? nsel : (int32_t)cap;
 }
 
+// ---------------------------------------------------------------------------
+// Persistent form (every wave's windows fit its registers): one workgroup per
+// CU walks the queries blockIdx.x, blockIdx.x + gridDim.x, ...  While it counts
+// query q it already fetches the leaf of query q' = q + gridDim.x in every tree
+// and the leaf's place in the permutation (during the first pass), so only
+// the window loads of q' wait at the start of its turn.
+// The counter array is cleared once per workgroup and kept clean by resetting
+// the touched words after every pass.  The counter updates of kBatch slots are
+// issued together (read, then one update attempt each, then the rare retries)
+// so their LDS latencies overlap.
+// ---------------------------------------------------------------------------
+constexpr int kBatch = 4;
+
+template <int B>
+__device__ __forceinline__ void count_batch(const int32_t* ids, int64_t lo, int64_t hi, uint32_t* cnt, int v,
+                                            int* nsel, int32_t* out, int64_t cap) {
+    constexpr uint32_t per = 32u / B;
+    constexpr uint32_t mask = B == 32 ? 0xffffffffu : ((1u << B) - 1u);
+    uint32_t word[kBatch], sh[kBatch], cur[kBatch];
+    bool act[kBatch], elect[kBatch];
+#pragma unroll
+    for (int g = 0; g < kBatch; ++g) {
+        act[g] = ids[g] >= lo && ids[g] < hi;
+        const uint32_t rel = act[g] ? (uint32_t)(ids[g] - lo) : 0u;
+        word[g] = rel / per;
+        sh[g] = (rel % per) * B;
+        elect[g] = false;
+    }
+#pragma unroll
+    for (int g = 0; g < kBatch; ++g) cur[g] = act[g] ? cnt[word[g]] : 0u;
+#pragma unroll
+    for (int g = 0; g < kBatch; ++g) {
+        if (act[g]) {
+            const int c = (int)((cur[g] >> sh[g]) & mask);
+            if (c >= v) {
+                act[g] = false;
+            } else if constexpr (B == 1) {
+                const uint32_t old = atomicOr(&cnt[word[g]], 1u << sh[g]);
+                elect[g] = ((old >> sh[g]) & 1u) == 0u;
+                act[g] = false;
+            } else if constexpr (B == 8) {
+                const uint32_t old = atomicAdd(&cnt[word[g]], 1u << sh[g]);
+                elect[g] = (int)((old >> sh[g]) & 0xffu) + 1 == v;
+                act[g] = false;
+            } else {
+                const uint32_t prev = atomicCAS(&cnt[word[g]], cur[g], cur[g] + (1u << sh[g]));
+                if (prev == cur[g]) {
+                    elect[g] = c + 1 == v;
+                    act[g] = false;
+                } else {
+                    cur[g] = prev;
+                }
+            }
+        }
+    }
+    if constexpr (B != 1 && B != 8) {
+#pragma unroll
+        for (int g = 0; g < kBatch; ++g) {
+            while (act[g]) {
+                const int c = (int)((cur[g] >> sh[g]) & mask);
+                if (c >= v) break;
+                const uint32_t prev = atomicCAS(&cnt[word[g]], cur[g], cur[g] + (1u << sh[g]));
+                if (prev == cur[g]) {
+                    elect[g] = c + 1 == v;
+                    break;
+                }
+                cur[g] = prev;
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < kBatch; ++g) append(elect[g], ids[g], nsel, out, cap);
+}
+
+template <int B>
+__global__ __launch_bounds__(kVoteBlock) void vote_persistent_kernel(const int32_t* __restrict__ leaf,
+                                                                     const int32_t* __restrict__ perm,
+                                                                     const int32_t* __restrict__ off, int64_t n,
+                                                                     int32_t T, int32_t v, int32_t chunk,
+                                                                     int64_t nq, int32_t* __restrict__ s_ids,
+                                                                     int64_t cap, int32_t* __restrict__ s_count) {
+    extern __shared__ uint32_t vote_cnt[];   // chunk * B / 32 words
+    __shared__ int64_t tbase[2][kMaxT];
+    __shared__ int32_t tlen[2][kMaxT];
+    __shared__ int nsel[2];
+    constexpr int per = 32 / B;
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id();
+    const int w = uniform(tid >> 6);
+    const int words = chunk / per;
+    int64_t q = blockIdx.x;
+    if (q >= nq) return;
+
+    for (int i = tid; i < (words >> 2); i += kVoteBlock)
+        reinterpret_cast<uint4*>(vote_cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (tid < T) {
+        const int L = leaf[q * T + tid];
+        const int b = off[L];
+        tbase[0][tid] = (int64_t)tid * n + b;
+        tlen[0][tid] = off[L + 1] - b;
+    }
+    if (tid == 0) nsel[0] = 0;
+    lds_barrier();
+
+    int32_t ids[kVoteSlots];
+    int cur = 0;
+    while (true) {
+        {
+            int jj = w, uu = 0;
+#pragma unroll
+            for (int s = 0; s < kVoteSlots; ++s) {
+                ids[s] = -1;
+                if (jj < T) {
+                    const int len = uniform(tlen[cur][jj]);
+                    const int e = uu * kWave + lane;
+                    if (e < len) ids[s] = perm[tbase[cur][jj] + e];
+                    ++uu;
+                    if (uu * kWave >= len) { uu = 0; jj += kVoteWaves; }
+                }
+            }
+        }
+        const int64_t qn = q + gridDim.x;
+        const bool has_next = qn < nq;
+        const int nxt = cur ^ 1;
+        int Ln = 0;
+        if (has_next && tid < T) Ln = leaf[qn * T + tid];   // in flight during pass 0
+        int32_t* out = s_ids + q * cap;
+        int pass = 0;
+        for (int64_t lo = 0; lo < n; lo += chunk, ++pass) {
+            const int64_t hi = lo + chunk < n ? lo + chunk : n;
+            int* my_nsel = &nsel[cur];
+#pragma unroll
+            for (int s0 = 0; s0 < kVoteSlots; s0 += kBatch) {
+                int32_t part[kBatch];
+#pragma unroll
+                for (int g = 0; g < kBatch; ++g) part[g] = ids[s0 + g];
+                count_batch<B>(part, lo, hi, vote_cnt, v, my_nsel, out, cap);
+            }
+            lds_barrier();
+            if (pass == 0 && has_next) {
+                if (tid < T) {
+                    const int b = off[Ln];
+                    tbase[nxt][tid] = (int64_t)tid * n + b;
+                    tlen[nxt][tid] = off[Ln + 1] - b;
+                }
+                if (tid == 0) nsel[nxt] = 0;
+            }
+#pragma unroll
+            for (int s = 0; s < kVoteSlots; ++s) {
+                const int32_t id = ids[s];
+                if (id >= lo && id < hi) vote_cnt[(uint32_t)(id - lo) / per] = 0u;
+            }
+            lds_barrier();
+        }
+        if (tid == 0) s_count[q] = nsel[cur] < cap ? nsel[cur] : (int32_t)cap;
+        if (!has_next) break;
+        cur = nxt;
+        q = qn;
+    }
+}
+
 // debug: F(x; q) of every listed candidate, by binary search of x in each of
 // the query's T leaf lists (independent of the counting kernel)
 __global__ __launch_bounds__(256) void vote_counts_kernel(const int32_t* __restrict__ leaf,
@@ -201,8 +362,8 @@ template <int B>
 hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
                          int64_t cap, int32_t* s_count, hipStream_t s) {
     constexpr int per = 32 / B;
-    constexpr size_t kStatic = kMaxT * 8 + kMaxT * 4 + 16;
-    // 16 waves of ~85 VGPRs hold a CU: the workgroup may take all of its LDS
+    constexpr size_t kStatic = 2 * (kMaxT * 8 + kMaxT * 4) + 16;
+    // 16 waves of ~100 VGPRs hold a CU: the workgroup may take all of its LDS
     const size_t budget = (size_t)std::min(lds_per_block_limit(), 160 * 1024) - kStatic;
     // ids per pass: a multiple of 4 words' worth of ids, at most what the budget holds
     int64_t chunk = (int64_t)(budget / 16) * 4 * per;
@@ -212,6 +373,23 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     const int64_t passes = (ix->n + chunk - 1) / chunk;
     chunk = ((ix->n + passes - 1) / passes + 4 * per - 1) / (4 * per) * (4 * per);
     const size_t lds = (size_t)(chunk / per) * 4;
+    // windows per wave: its trees times the 64-id windows of the longest leaf
+    const int64_t windows = (int64_t)((ix->T + kVoteWaves - 1) / kVoteWaves) * ((ix->max_leaf + kWave - 1) / kWave);
+    if (windows <= kVoteSlots) {
+        static int cus = 0;
+        if (cus == 0) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+                cus = 256;
+        }
+        const int64_t grid = std::min<int64_t>(nq, cus);
+        (void)hipFuncSetAttribute((const void*)vote_persistent_kernel<B>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(vote_persistent_kernel<B>, dim3((unsigned)grid), dim3(kVoteBlock), lds, s, leaf, ix->perm,
+                           ix->off, ix->n, ix->T, v, (int32_t)chunk, nq, s_ids, cap, s_count);
+        return hipGetLastError();
+    }
     (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)nq), dim3(kVoteBlock), lds, s, leaf, ix->perm, ix->off, ix->n,
                        ix->T, v, (int32_t)chunk, s_ids, cap, s_count);
