@@ -19,6 +19,61 @@ namespace {
 using namespace dev;
 
 constexpr int kQStride = 65;
+constexpr int kStageUnroll = 8;     // global loads in flight per thread while staging
+
+// split tables of trees t_first .. t_first+count-1 into LDS (heap order)
+__device__ __forceinline__ void stage_splits(const float* __restrict__ splits, float* sp, int T, int t_first,
+                                             int count, int nsplit) {
+    const int tid = (int)threadIdx.x, nthreads = (int)blockDim.x;
+    for (int tw = 0; tw < count; ++tw) {
+        const int tt = t_first + tw;
+        if (tt >= T) break;
+        const float* src = splits + (int64_t)tt * nsplit;
+        float* dst = sp + tw * nsplit;
+        for (int e0 = tid; e0 < nsplit; e0 += kStageUnroll * nthreads) {
+            float r[kStageUnroll];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const int e = e0 + u * nthreads;
+                r[u] = e < nsplit ? src[e] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const int e = e0 + u * nthreads;
+                if (e < nsplit) dst[e] = r[u];
+            }
+        }
+    }
+}
+
+// the 64-query tile starting at q0 (contiguous rows of Q) into LDS as
+// qt[feature * 65 + query]; rows past nq read as zero
+__device__ __forceinline__ void stage_query_tile(const float* __restrict__ Q, int64_t q0, int64_t nq, int d,
+                                                 float* qt) {
+    const int tid = (int)threadIdx.x, nthreads = (int)blockDim.x;
+    const int total = kWave * d;
+    const int step_q = nthreads / d, step_f = nthreads - step_q * d;
+    int qq = tid / d, f = tid - qq * d;
+    const float* src = Q + q0 * d;
+    const int64_t rows_left = nq - q0;
+    for (int e0 = tid; e0 < total; e0 += kStageUnroll * nthreads) {
+        float r[kStageUnroll];
+        int rq[kStageUnroll], rf[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int e = e0 + u * nthreads;
+            rq[u] = qq;
+            rf[u] = f;
+            r[u] = (e < total && qq < rows_left) ? src[e] : 0.0f;
+            qq += step_q;
+            f += step_f;
+            if (f >= d) { f -= d; ++qq; }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u)
+            if (e0 + u * nthreads < total) qt[rf[u] * kQStride + rq[u]] = r[u];
+    }
+}
 
 template <int MAXL, bool CSR_LDS, bool SPLITS_LDS>
 __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q, int64_t nq, int32_t d,
@@ -167,13 +222,7 @@ __global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict
     const int nthreads = (int)blockDim.x;
     const int t_first = (int)blockIdx.y * trees_per_block;
 
-    if constexpr (SPLITS_LDS) {
-        for (int i = (int)threadIdx.x; i < trees_per_block * nsplit; i += nthreads) {
-            const int tw = i / nsplit;
-            const int tt = t_first + tw;
-            sp[i] = tt < T ? splits[(int64_t)tt * nsplit + (i - tw * nsplit)] : 0.0f;
-        }
-    }
+    if constexpr (SPLITS_LDS) stage_splits(splits, sp, T, t_first, trees_per_block, nsplit);
     int len[MAXL];
     int colr[MAXL];
     float valr[MAXL];
@@ -200,11 +249,7 @@ __global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict
         const int64_t q = q0 + lane;
         if constexpr (QLDS) {
             __syncthreads();
-            for (int i = (int)threadIdx.x; i < kWave * d; i += nthreads) {
-                const int qq = i / d, f = i - qq * d;
-                const int64_t gq = q0 + qq;
-                qt[f * kQStride + qq] = gq < nq ? Q[gq * d + f] : 0.0f;
-            }
+            stage_query_tile(Q, q0, nq, d, qt);
         }
         __syncthreads();
         const float* qrow = Q + (q < nq ? q : nq - 1) * d;
@@ -269,8 +314,11 @@ hipError_t launch_route_fast(const mrpt_index* ix, const float* Q, int64_t nq, i
     const bool spl = base + (size_t)tpb * nsplit * 4 <= limit;
     const size_t lds = base + (spl ? (size_t)tpb * nsplit * 4 : 0);
     const int64_t ntiles = (nq + kWave - 1) / kWave;
-    const int tiles = ntiles >= 4 * 256 ? 4 : (ntiles >= 2 * 256 ? 2 : 1);
-    dim3 grid((unsigned)((ntiles + tiles - 1) / tiles), (unsigned)((ix->T + tpb - 1) / tpb));
+    const int64_t tree_groups = (ix->T + tpb - 1) / tpb;
+    // several query tiles per workgroup (so each staged split table serves more
+    // queries) while keeping about 4 workgroups per CU
+    const int tiles = (int)std::max<int64_t>(1, std::min<int64_t>(8, ntiles * tree_groups / 1024));
+    dim3 grid((unsigned)((ntiles + tiles - 1) / tiles), (unsigned)tree_groups);
     dim3 block(kWave * tpb);
 #define MRPT_ROUTE_F(ML, QL, SL)                                                                             \
     do {                                                                                                     \

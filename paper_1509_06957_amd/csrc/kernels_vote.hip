@@ -11,6 +11,8 @@
 // a pass only the words that were touched are reset, so the array is cleared
 // in full once per query.  Windows that do not fit the register budget are
 // re-read from memory in every pass (and then the array is cleared in full).
+#include <cstdlib>
+
 #include "device_common.h"
 #include "mrpt_internal.h"
 
@@ -326,6 +328,151 @@ __global__ __launch_bounds__(kVoteBlock) void vote_persistent_kernel(const int32
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wave form: one wave per query, with a private slice of LDS, so waves never
+// wait for each other and a CU keeps ~20 queries in flight.  Lane l follows
+// the leaf lists of trees l, l+64, ... with a cursor; the id space is walked in
+// ranges of `range` ids whose counters (B bits each) fill the wave's slice.
+// In a range every lane reads the next 4 ids of each of its lists (ascending,
+// so the ids of the range are a prefix), counts the prefix, and advances its
+// cursors; the loop ends when no list has an id left in the range.
+// ---------------------------------------------------------------------------
+constexpr int kWaveWin = 4;            // ids read per list per step
+constexpr int kWavesPerBlock = 4;
+
+template <int B, int SPL>
+__global__ __launch_bounds__(kWavesPerBlock * kWave) void vote_wave_kernel(
+    const int32_t* __restrict__ leaf, const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
+    int64_t n, int32_t T, int32_t v, int32_t range, int32_t words_per_wave, int64_t nq,
+    int32_t* __restrict__ s_ids, int64_t cap, int32_t* __restrict__ s_count) {
+    extern __shared__ uint32_t wave_cnt[];
+    constexpr uint32_t per = 32u / B;
+    constexpr uint32_t mask = B == 32 ? 0xffffffffu : ((1u << B) - 1u);
+    const int lane = lane_id();
+    const int w = uniform((int)(threadIdx.x >> 6));
+    const int64_t q = (int64_t)blockIdx.x * kWavesPerBlock + w;
+    if (q >= nq) return;                          // whole wave; no workgroup barrier below
+    uint32_t* cnt = wave_cnt + (size_t)w * words_per_wave;
+
+    int64_t base[SPL];
+    int len[SPL], cur[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+        const int t = lane + s * kWave;
+        base[s] = 0;
+        len[s] = 0;
+        cur[s] = 0;
+        if (t < T) {
+            const int L = leaf[q * T + t];
+            const int b = off[L];
+            base[s] = (int64_t)t * n + b;
+            len[s] = off[L + 1] - b;
+        }
+    }
+    int32_t* out = s_ids + q * cap;
+    int nsel = 0;                                 // wave-uniform
+    for (int64_t lo = 0; lo < n; lo += range) {
+        const int64_t hi = lo + range < n ? lo + range : n;
+        for (int i = lane; i < (words_per_wave >> 2); i += kWave)
+            reinterpret_cast<uint4*>(cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
+        bool active[SPL];
+#pragma unroll
+        for (int s = 0; s < SPL; ++s) active[s] = cur[s] < len[s];
+        while (true) {
+            bool any = false;
+#pragma unroll
+            for (int s = 0; s < SPL; ++s) any |= active[s];
+            if (!__any(any)) break;
+            int32_t id[SPL][kWaveWin];
+#pragma unroll
+            for (int s = 0; s < SPL; ++s)
+#pragma unroll
+                for (int j = 0; j < kWaveWin; ++j)
+                    id[s][j] = (active[s] && cur[s] + j < len[s]) ? perm[base[s] + cur[s] + j] : INT32_MAX;
+            // the prefix below hi of each window is this range's share of the list
+            uint32_t word[SPL][kWaveWin], sh[SPL][kWaveWin], val[SPL][kWaveWin];
+            bool act[SPL][kWaveWin], elect[SPL][kWaveWin];
+#pragma unroll
+            for (int s = 0; s < SPL; ++s) {
+                int used = 0;
+#pragma unroll
+                for (int j = 0; j < kWaveWin; ++j) {
+                    act[s][j] = id[s][j] < hi;
+                    used += act[s][j] ? 1 : 0;
+                    const uint32_t rel = act[s][j] ? (uint32_t)(id[s][j] - lo) : 0u;
+                    word[s][j] = rel / per;
+                    sh[s][j] = (rel % per) * B;
+                    elect[s][j] = false;
+                }
+                cur[s] += used;
+                active[s] = active[s] && used == kWaveWin && cur[s] < len[s];
+            }
+#pragma unroll
+            for (int s = 0; s < SPL; ++s)
+#pragma unroll
+                for (int j = 0; j < kWaveWin; ++j) val[s][j] = act[s][j] ? cnt[word[s][j]] : 0u;
+#pragma unroll
+            for (int s = 0; s < SPL; ++s)
+#pragma unroll
+                for (int j = 0; j < kWaveWin; ++j) {
+                    if (!act[s][j]) continue;
+                    const int c = (int)((val[s][j] >> sh[s][j]) & mask);
+                    if (c >= v) {
+                        act[s][j] = false;
+                    } else if constexpr (B == 1) {
+                        const uint32_t old = atomicOr(&cnt[word[s][j]], 1u << sh[s][j]);
+                        elect[s][j] = ((old >> sh[s][j]) & 1u) == 0u;
+                        act[s][j] = false;
+                    } else if constexpr (B == 8) {
+                        const uint32_t old = atomicAdd(&cnt[word[s][j]], 1u << sh[s][j]);
+                        elect[s][j] = (int)((old >> sh[s][j]) & 0xffu) + 1 == v;
+                        act[s][j] = false;
+                    } else {
+                        const uint32_t prev = atomicCAS(&cnt[word[s][j]], val[s][j], val[s][j] + (1u << sh[s][j]));
+                        if (prev == val[s][j]) {
+                            elect[s][j] = c + 1 == v;
+                            act[s][j] = false;
+                        } else {
+                            val[s][j] = prev;
+                        }
+                    }
+                }
+            if constexpr (B != 1 && B != 8) {
+#pragma unroll
+                for (int s = 0; s < SPL; ++s)
+#pragma unroll
+                    for (int j = 0; j < kWaveWin; ++j) {
+                        while (act[s][j]) {
+                            const int c = (int)((val[s][j] >> sh[s][j]) & mask);
+                            if (c >= v) break;
+                            const uint32_t prev =
+                                atomicCAS(&cnt[word[s][j]], val[s][j], val[s][j] + (1u << sh[s][j]));
+                            if (prev == val[s][j]) {
+                                elect[s][j] = c + 1 == v;
+                                break;
+                            }
+                            val[s][j] = prev;
+                        }
+                    }
+            }
+#pragma unroll
+            for (int s = 0; s < SPL; ++s)
+#pragma unroll
+                for (int j = 0; j < kWaveWin; ++j) {
+                    const uint64_t m = __ballot(elect[s][j]);
+                    if (m) {
+                        if (elect[s][j]) {
+                            const int64_t p = (int64_t)nsel + __popcll(m & __lanemask_lt());
+                            if (p < cap) out[p] = id[s][j];
+                        }
+                        nsel += __popcll(m);
+                    }
+                }
+        }
+    }
+    if (lane == 0) s_count[q] = nsel < cap ? nsel : (int32_t)cap;
+}
+
 // debug: F(x; q) of every listed candidate, by binary search of x in each of
 // the query's T leaf lists (independent of the counting kernel)
 __global__ __launch_bounds__(256) void vote_counts_kernel(const int32_t* __restrict__ leaf,
@@ -358,6 +505,15 @@ __global__ void copy_counts_kernel(const int32_t* __restrict__ src, int64_t nq, 
     if (i < nq) dst[i] = src[i];
 }
 
+// Which vote kernel runs: 2 = one wave per query (default), 1 = persistent
+// workgroups, 0 = one workgroup per query.  MRPT_VOTE_KERNEL selects another
+// for tuning; all three compute the same S.
+int vote_kernel_choice() {
+    const char* env = std::getenv("MRPT_VOTE_KERNEL");
+    const int choice = (env && *env) ? std::atoi(env) : 2;
+    return (choice < 0 || choice > 2) ? 2 : choice;
+}
+
 template <int B>
 hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
                          int64_t cap, int32_t* s_count, hipStream_t s) {
@@ -375,7 +531,32 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     const size_t lds = (size_t)(chunk / per) * 4;
     // windows per wave: its trees times the 64-id windows of the longest leaf
     const int64_t windows = (int64_t)((ix->T + kVoteWaves - 1) / kVoteWaves) * ((ix->max_leaf + kWave - 1) / kWave);
-    if (windows <= kVoteSlots) {
+    if (vote_kernel_choice() == 2) {
+        // one wave per query: an 8 KB counter slice per wave
+        constexpr int64_t kSliceBytes = 8192;
+        const int64_t range_max = kSliceBytes * 8 / B;
+        int64_t range = std::min<int64_t>(range_max, (ix->n + 4 * per - 1) / (4 * per) * (4 * per));
+        const int32_t words = (int32_t)(range / per);
+        const size_t lds_w = (size_t)words * 4 * kWavesPerBlock;
+        const unsigned grid = (unsigned)((nq + kWavesPerBlock - 1) / kWavesPerBlock);
+        const int spl = (ix->T + kWave - 1) / kWave;
+#define MRPT_VW(SPL)                                                                                          \
+    do {                                                                                                      \
+        (void)hipFuncSetAttribute((const void*)vote_wave_kernel<B, SPL>,                                      \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_w);                    \
+        hipLaunchKernelGGL((vote_wave_kernel<B, SPL>), dim3(grid), dim3(kWavesPerBlock * kWave), lds_w, s, leaf, \
+                           ix->perm, ix->off, ix->n, ix->T, v, (int32_t)range, words, nq, s_ids, cap, s_count);  \
+    } while (0)
+        switch (spl) {
+            case 1: MRPT_VW(1); break;
+            case 2: MRPT_VW(2); break;
+            case 3: MRPT_VW(3); break;
+            default: MRPT_VW(4); break;
+        }
+#undef MRPT_VW
+        return hipGetLastError();
+    }
+    if (windows <= kVoteSlots && vote_kernel_choice() == 1) {
         static int cus = 0;
         if (cus == 0) {
             int dev = 0;

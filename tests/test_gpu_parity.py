@@ -272,3 +272,22 @@ def ctypes_build_host_pointer(X):
     Xc = np.ascontiguousarray(X)
     return lib.mrpt_build(ctypes.c_void_p(Xc.ctypes.data), Xc.shape[0], Xc.shape[1], 2, 3, 0.5, 1,
                           ctypes.byref(h))
+
+
+@pytest.mark.parametrize("kernel", ["0", "1", "2"])
+def test_vote_kernel_variants_agree(kernel, monkeypatch):
+    # the three vote kernels (workgroup per query, persistent, wave per query)
+    # compute the same candidate sets
+    _print_case(f"vote kernel {kernel}")
+    monkeypatch.setenv("MRPT_VOTE_KERNEL", kernel)
+    for n, d, T, depth, v in ((6000, 24, 20, 5, 1), (7000, 16, 12, 6, 3), (3000, 8, 9, 4, 5), (2500, 8, 140, 3, 20),
+                              (150000, 8, 10, 7, 2), (140000, 8, 70, 9, 1)):
+        X, Q = _small(n, d, T, depth, seed=n + T)
+        orc = oracle.build_index(X, T, depth, 0.5, 3)
+        g = build(X, T, depth, 0.5, 3)
+        ref = oracle.query(orc, Q, 5, v, want_sets=True)
+        ids, cnt = votes(g, dev(Q), v)
+        for q in range(len(Q)):
+            assert np.array_equal(ids[q], ref["s_ids"][q]), f"n={n} T={T} v={v} query {q}"
+            assert np.array_equal(cnt[q], ref["s_votes"][q])
+        g.close()
