@@ -77,7 +77,8 @@ mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
     const size_t leaf_b = ((size_t)nb * ix->T * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t ids_b = ((size_t)nb * (size_t)cap * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t cnt_b = ((size_t)nb * sizeof(int32_t) + 255) & ~size_t(255);
-    const size_t need = leaf_b + ids_b + cnt_b + 256;
+    const size_t pq_b = (route_workspace_floats(ix, nb) * sizeof(float) + 255) & ~size_t(255);
+    const size_t need = leaf_b + ids_b + cnt_b + 256 + pq_b;
     if (!ix->ws.done) MRPT_HIP_TRY(hipEventCreateWithFlags(&ix->ws.done, hipEventDisableTiming));
     if (need > ix->ws.bytes) {
         MRPT_HIP_TRY(hipEventSynchronize(ix->ws.done));
@@ -95,6 +96,7 @@ mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
     ix->ws.s_ids = (int32_t*)(b + leaf_b);
     ix->ws.s_count = (int32_t*)(b + leaf_b + ids_b);
     ix->ws.flag = (int32_t*)(b + leaf_b + ids_b + cnt_b);
+    ix->ws.pq = pq_b ? (float*)(b + leaf_b + ids_b + cnt_b + 256) : nullptr;
     return MRPT_OK;
 }
 
@@ -104,7 +106,8 @@ int64_t candidate_cap(const mrpt_index* ix, int32_t v) {
 }
 
 int64_t batch_size(const mrpt_index* ix, int64_t nq, int64_t cap) {
-    const int64_t per_q = (int64_t)(ix->T + cap + 1) * (int64_t)sizeof(int32_t);
+    const int64_t per_q = (int64_t)(ix->T + cap + 1) * (int64_t)sizeof(int32_t) +
+                          (int64_t)route_workspace_floats(ix, 1) * (int64_t)sizeof(float);
     const int64_t nb = std::max<int64_t>(1, (int64_t)workspace_limit() / per_q);
     return std::min(nq, nb);
 }
@@ -152,7 +155,7 @@ mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_
         const int64_t m = std::min(nb, nq - q0);
         const float* Qb = Q + q0 * ix->d;
         MRPT_HIP_TRY(mark(q0, 0));
-        MRPT_HIP_TRY(launch_route(ix, Qb, m, ix->ws.leaf, s));
+        MRPT_HIP_TRY(launch_route(ix, Qb, m, ix->ws.leaf, ix->ws.pq, s));
         MRPT_HIP_TRY(mark(q0, 1));
         MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, m, v, ix->ws.s_ids, cap, ix->ws.s_count, s));
         MRPT_HIP_TRY(mark(q0, 2));
@@ -377,8 +380,14 @@ mrpt_status mrpt_debug_leaves(const mrpt_index* ix, const float* Q, int64_t nq, 
     if (nq < 0) return fail(MRPT_EINVAL, "nq < 0");
     if (nq > 0 && (!Q || !leaf)) return fail(MRPT_EINVAL, "NULL pointer");
     if (nq == 0) return MRPT_OK;
+    mrpt_index* mix = const_cast<mrpt_index*>(ix);
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(mix->mu);
     MRPT_HIP_TRY(hipSetDevice(ix->device));
-    MRPT_HIP_TRY(launch_route(ix, Q, nq, leaf, (hipStream_t)stream));
+    MRPT_TRY(ensure_workspace(mix, nq, 1));
+    MRPT_HIP_TRY(hipStreamWaitEvent(s, mix->ws.done, 0));
+    MRPT_HIP_TRY(launch_route(ix, Q, nq, leaf, mix->ws.pq, s));
+    MRPT_HIP_TRY(hipEventRecord(mix->ws.done, s));
     return MRPT_OK;
 }
 
@@ -399,7 +408,7 @@ mrpt_status mrpt_debug_votes(const mrpt_index* cix, const float* Q, int64_t nq, 
     MRPT_HIP_TRY(hipSetDevice(ix->device));
     MRPT_TRY(ensure_workspace(ix, nq, 1));
     MRPT_HIP_TRY(hipStreamWaitEvent(s, ix->ws.done, 0));
-    MRPT_HIP_TRY(launch_route(ix, Q, nq, ix->ws.leaf, s));
+    MRPT_HIP_TRY(launch_route(ix, Q, nq, ix->ws.leaf, ix->ws.pq, s));
     MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, nq, v, s_ids, cap, s_count, s));
     if (s_votes) MRPT_HIP_TRY(launch_vote_counts(ix, ix->ws.leaf, nq, s_ids, cap, s_count, s_votes, s));
     MRPT_HIP_TRY(hipEventRecord(ix->ws.done, s));

@@ -285,6 +285,116 @@ __global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-kernel form (every projection vector has at most 64 nonzeros).
+//
+// project_kernel: Pq[r][q] = q . R_r for all T*depth rows r, i.e. the sparse
+// product of Sec. II-C for a batch of queries.  A workgroup takes a 64-query
+// tile (staged in LDS as [feature][query] when it fits) and 8 waves x RPW
+// rows; a wave keeps its RPW rows in registers (lane e holds entry e) and
+// advances them together, one nonzero per row per step, so RPW fused
+// multiply-add chains overlap while each runs in ascending feature order.
+// Writes are coalesced along queries.
+//
+// route_pq_kernel: Alg. 3's descent for one tree and a range of queries, the
+// tree's split table staged in LDS once per workgroup; each thread first
+// loads the depth projections of its query (independent loads) and then
+// walks the table.
+// ---------------------------------------------------------------------------
+constexpr int kProjWaves = 8;
+
+template <int RPW, bool QLDS>
+__global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
+                                                                     int32_t d, const int32_t* __restrict__ rowptr,
+                                                                     const int32_t* __restrict__ col,
+                                                                     const float* __restrict__ val, int32_t nrows,
+                                                                     float* __restrict__ Pq) {
+    extern __shared__ float proj_smem[];   // [d][65] when QLDS
+    const int lane = lane_id();
+    const int w = uniform((int)(threadIdx.x >> 6));
+    const int64_t q0 = (int64_t)blockIdx.x * kWave;
+    const int r0 = uniform((int)blockIdx.y * (kProjWaves * RPW) + w * RPW);
+    int len[RPW];
+    int colr[RPW];
+    float valr[RPW];
+    int maxlen = 0;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        len[i] = 0;
+        colr[i] = 0;
+        valr[i] = 0.0f;
+        if (r0 + i < nrows) {
+            const int b = uniform(rowptr[r0 + i]);
+            len[i] = uniform(rowptr[r0 + i + 1]) - b;
+            if (lane < len[i]) {
+                colr[i] = col[b + lane];
+                valr[i] = val[b + lane];
+            }
+            maxlen = len[i] > maxlen ? len[i] : maxlen;
+        }
+    }
+    if constexpr (QLDS) {
+        stage_query_tile(Q, q0, nq, d, proj_smem);
+        __syncthreads();
+    }
+    const int64_t q = q0 + lane;
+    const float* qrow = Q + (q < nq ? q : nq - 1) * d;
+    float acc[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) acc[i] = 0.0f;
+    for (int k = 0; k < maxlen; ++k) {
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            if (k < len[i]) {
+                const int c = read_lane_i(colr[i], k);
+                const float v = read_lane_f(valr[i], k);
+                float x;
+                if constexpr (QLDS) x = proj_smem[c * kQStride + lane];
+                else x = qrow[c];
+                acc[i] = __builtin_fmaf(x, v, acc[i]);
+            }
+        }
+    }
+    if (q < nq) {
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+            if (r0 + i < nrows) Pq[(int64_t)(r0 + i) * nq + q] = acc[i];
+    }
+}
+
+template <int MAXL, bool SPLITS_LDS>
+__global__ __launch_bounds__(256) void route_pq_kernel(const float* __restrict__ Pq, int64_t nq,
+                                                       const float* __restrict__ splits, int32_t T, int32_t depth,
+                                                       int32_t q_per_block, int32_t* __restrict__ leaf) {
+    extern __shared__ float rsp[];          // split table of this block's tree
+    const int nsplit = (1 << depth) - 1;
+    const int t = (int)blockIdx.y;
+    if constexpr (SPLITS_LDS) {
+        stage_splits(splits, rsp, T, t, 1, nsplit);
+        __syncthreads();
+    }
+    const float* tsp = splits + (int64_t)t * nsplit;
+    const int64_t qb = (int64_t)blockIdx.x * q_per_block;
+    const int64_t qe = qb + q_per_block < nq ? qb + q_per_block : nq;
+    for (int64_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
+        float p[MAXL];
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j)
+            p[j] = j < depth ? Pq[((int64_t)t * depth + j) * nq + q] : 0.0f;
+        int node = 0;
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) {
+            if (j < depth) {
+                float s;
+                if constexpr (SPLITS_LDS) s = rsp[node];
+                else s = tsp[node];
+                node = (p[j] <= s) ? 2 * node + 1 : 2 * node + 2;
+            }
+        }
+        leaf[q * T + t] = node - nsplit;
+    }
+}
+
 }  // namespace
 
 int lds_per_block_limit() {
@@ -343,11 +453,70 @@ hipError_t launch_route_fast(const mrpt_index* ix, const float* Q, int64_t nq, i
     return hipGetLastError();
 }
 
+constexpr int kProjRows = 16;   // rows per wave in project_kernel
+
+hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
+                            hipStream_t s) {
+    const int depth = ix->depth;
+    const int d = ix->d;
+    const int nrows = ix->T * depth;
+    if (nrows > 0) {
+        const size_t q_bytes = (size_t)d * kQStride * 4;
+        const bool qlds = q_bytes <= 64 * 1024;
+        const size_t lds = qlds ? q_bytes : 0;
+        dim3 grid((unsigned)((nq + kWave - 1) / kWave),
+                  (unsigned)((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)));
+        if (qlds) {
+            (void)hipFuncSetAttribute((const void*)project_kernel<kProjRows, true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL((project_kernel<kProjRows, true>), grid, dim3(kProjWaves * kWave), lds, s, Q, nq, d,
+                               ix->rowptr, ix->col, ix->val, nrows, pq);
+        } else {
+            hipLaunchKernelGGL((project_kernel<kProjRows, false>), grid, dim3(kProjWaves * kWave), 0, s, Q, nq, d,
+                               ix->rowptr, ix->col, ix->val, nrows, pq);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int nsplit = (1 << depth) - 1;
+    const size_t sp_bytes = (size_t)nsplit * 4;
+    const bool spl = sp_bytes <= (size_t)std::min(lds_per_block_limit(), 64 * 1024);
+    const int q_per_block = 2048;
+    dim3 grid((unsigned)((nq + q_per_block - 1) / q_per_block), (unsigned)ix->T);
+    const size_t lds = spl ? sp_bytes : 0;
+#define MRPT_RPQ(ML)                                                                                            \
+    do {                                                                                                        \
+        if (spl) {                                                                                              \
+            (void)hipFuncSetAttribute((const void*)route_pq_kernel<ML, true>,                                   \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
+            hipLaunchKernelGGL((route_pq_kernel<ML, true>), grid, dim3(256), lds, s, pq, nq, ix->splits, ix->T, \
+                               depth, q_per_block, leaf);                                                       \
+        } else {                                                                                                \
+            hipLaunchKernelGGL((route_pq_kernel<ML, false>), grid, dim3(256), 0, s, pq, nq, ix->splits, ix->T,  \
+                               depth, q_per_block, leaf);                                                       \
+        }                                                                                                       \
+    } while (0)
+    if (depth <= 8) MRPT_RPQ(8);
+    else if (depth <= 12) MRPT_RPQ(12);
+    else if (depth <= 16) MRPT_RPQ(16);
+    else MRPT_RPQ(24);
+#undef MRPT_RPQ
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s) {
+size_t route_workspace_floats(const mrpt_index* ix, int64_t nq) {
+    return ix->max_row_nnz <= kWave ? (size_t)nq * ix->T * ix->depth : 0;
+}
+
+hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
+                        hipStream_t s) {
     if (nq == 0) return hipSuccess;
-    if (ix->max_row_nnz <= kWave) return launch_route_fast(ix, Q, nq, leaf, s);
+    if (ix->max_row_nnz <= kWave) {
+        if (pq) return launch_route_two(ix, Q, nq, leaf, pq, s);
+        return launch_route_fast(ix, Q, nq, leaf, s);
+    }
     const int depth = ix->depth;
     const int nsplit = (1 << depth) - 1;
     const int limit = std::min(lds_per_block_limit(), 80 * 1024);   // two workgroups per CU

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
                                                           const int32_t* __restrict__ off, int64_t n,
                                                           int32_t T, int32_t v, int32_t chunk,
                                                           int32_t* __restrict__ s_ids, int64_t cap,
-                                                          int32_t* __restrict__ s_count) {
+                                                          int32_t* __restrict__ s_count, int32_t redo_only) {
     extern __shared__ uint32_t vote_cnt[];   // chunk * B / 32 words
     __shared__ int64_t tbase[kMaxT];
     __shared__ int32_t tlen[kMaxT];
@@ -86,6 +86,8 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
     const int w = uniform(tid >> 6);
     const int64_t q = blockIdx.x;
     const int words = chunk / per;
+    // second launch after the single-pass kernel: only queries it gave up on (count -1)
+    if (redo_only && s_count[q] >= 0) return;
 
     if (tid < T) {
         const int L = leaf[q * T + tid];
@@ -473,6 +475,156 @@ __global__ __launch_bounds__(kWavesPerBlock * kWave) void vote_wave_kernel(
     if (lane == 0) s_count[q] = nsel < cap ? nsel : (int32_t)cap;
 }
 
+// ---------------------------------------------------------------------------
+// Single-pass form (all n ids fit a 1-bit LDS map): the first occurrence of an
+// id sets its bit; a repeated id goes to an open-addressing LDS hash table that
+// holds (id + 1) << 8 | count for the ids seen at least twice.  F(x) is thus
+// 1 for ids only in the map and the table count otherwise, and the occurrence
+// that makes it v appends x to S (for v = 1, the one that sets the bit).  If
+// the table fills up the query's count is stored as -1 and the query is redone
+// by the multi-pass kernel.  The workgroup is persistent over queries q,
+// q + gridDim.x, ...: while it counts q, the leaf windows of the next query and
+// the leaf positions of the one after are already being fetched.
+// ---------------------------------------------------------------------------
+constexpr int kHashLog2 = 13;   // 8192 entries, 32 KB
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t id) {
+    return ((uint32_t)id * 2654435761u) >> (32 - kHashLog2);
+}
+
+// F(id) after this occurrence (>= 2) for an id whose map bit was already set;
+// 0 if the table is full
+__device__ __forceinline__ int hash_increment(uint32_t* tab, int32_t id) {
+    constexpr uint32_t kMask = (1u << kHashLog2) - 1u;
+    const uint32_t key = (uint32_t)(id + 1);
+    uint32_t h = hash_slot(id);
+    for (int probe = 0; probe <= (int)kMask; ++probe) {
+        uint32_t cur = tab[h];
+        if (cur == 0u) {
+            const uint32_t prev = atomicCAS(&tab[h], 0u, (key << 8) | 2u);
+            if (prev == 0u) return 2;
+            cur = prev;
+        }
+        if ((cur >> 8) == key) {
+            const uint32_t old = atomicAdd(&tab[h], 1u);
+            return (int)(old & 0xffu) + 1;
+        }
+        h = (h + 1u) & kMask;
+    }
+    return 0;
+}
+
+template <bool HASH>
+__global__ __launch_bounds__(kVoteBlock) void vote_bitmap_kernel(const int32_t* __restrict__ leaf,
+                                                                 const int32_t* __restrict__ perm,
+                                                                 const int32_t* __restrict__ off, int64_t n,
+                                                                 int32_t T, int32_t v, int64_t nq, int32_t bm_words,
+                                                                 int32_t* __restrict__ s_ids, int64_t cap,
+                                                                 int32_t* __restrict__ s_count) {
+    extern __shared__ uint32_t bm_smem[];   // bitmap [bm_words], then the table
+    __shared__ int32_t tbase[2][kMaxT];   // leaf start inside its tree
+    __shared__ int32_t tlen[2][kMaxT];
+    __shared__ int nsel[2];
+    __shared__ int ovf[2];
+    constexpr int kTab = HASH ? (1 << kHashLog2) : 0;
+    uint32_t* bm = bm_smem;
+    uint32_t* tab = bm_smem + bm_words;
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id();
+    const int w = uniform(tid >> 6);
+    const int64_t stride = gridDim.x;
+    int64_t q = blockIdx.x;
+    if (q >= nq) return;
+
+    const int clear_words = bm_words + kTab;   // multiple of 4
+    for (int i = tid; i < (clear_words >> 2); i += kVoteBlock)
+        reinterpret_cast<uint4*>(bm_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
+    // leaf positions of the first two queries
+    for (int k = 0; k < 2; ++k) {
+        const int64_t qq = q + k * stride;
+        if (qq < nq && tid < T) {
+            const int L = leaf[qq * T + tid];
+            const int b = off[L];
+            tbase[k][tid] = b;
+            tlen[k][tid] = off[L + 1] - b;
+        }
+    }
+    if (tid < 2) { nsel[tid] = 0; ovf[tid] = 0; }
+    lds_barrier();
+
+    int32_t ids[kVoteSlots], nid[kVoteSlots];
+#define MRPT_LOAD_WINDOWS(DST, BUF)                                          \
+    do {                                                                     \
+        int jj = w, uu = 0;                                                  \
+        _Pragma("unroll") for (int s = 0; s < kVoteSlots; ++s) {             \
+            DST[s] = -1;                                                     \
+            if (jj < T) {                                                    \
+                const int len = uniform(tlen[BUF][jj]);                      \
+                const int e = uu * kWave + lane;                             \
+                if (e < len) DST[s] = perm[(int64_t)jj * n + tbase[BUF][jj] + e]; \
+                ++uu;                                                        \
+                if (uu * kWave >= len) { uu = 0; jj += kVoteWaves; }         \
+            }                                                                \
+        }                                                                    \
+    } while (0)
+    MRPT_LOAD_WINDOWS(ids, 0);
+    int cur = 0;
+    while (true) {
+        const int nxt = cur ^ 1;
+        const int64_t q1 = q + stride, q2 = q + 2 * stride;
+        if (q1 < nq) MRPT_LOAD_WINDOWS(nid, nxt);            // in flight while q is counted
+        int L2 = 0;
+        if (q2 < nq && tid < T) L2 = leaf[q2 * T + tid];      // likewise
+        int32_t* out = s_ids + q * cap;
+        int* my_nsel = &nsel[cur];
+#pragma unroll
+        for (int s0 = 0; s0 < kVoteSlots; s0 += kBatch) {
+            uint32_t old[kBatch];
+            bool elect[kBatch];
+#pragma unroll
+            for (int g = 0; g < kBatch; ++g) {
+                const int32_t id = ids[s0 + g];
+                old[g] = id >= 0 ? atomicOr(&bm[(uint32_t)id >> 5], 1u << (id & 31)) : 0u;
+            }
+#pragma unroll
+            for (int g = 0; g < kBatch; ++g) {
+                const int32_t id = ids[s0 + g];
+                const bool seen = id >= 0 && ((old[g] >> (id & 31)) & 1u);
+                elect[g] = id >= 0 && !seen && v == 1;
+                if (HASH && seen) {
+                    const int c = hash_increment(tab, id);
+                    if (c == 0) ovf[cur] = 1;
+                    elect[g] = c == v;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < kBatch; ++g) append(elect[g], ids[s0 + g], my_nsel, out, cap);
+        }
+        lds_barrier();
+        if (q2 < nq && tid < T) {                             // buffer cur held q's positions: free now
+            const int b = off[L2];
+            tbase[cur][tid] = b;
+            tlen[cur][tid] = off[L2 + 1] - b;
+        }
+        if (tid == 0) { nsel[nxt] = 0; ovf[nxt] = 0; }
+#pragma unroll
+        for (int s = 0; s < kVoteSlots; ++s)
+            if (ids[s] >= 0) bm[(uint32_t)ids[s] >> 5] = 0u;
+        if constexpr (HASH) {
+            for (int i = tid; i < (kTab >> 2); i += kVoteBlock)
+                reinterpret_cast<uint4*>(tab)[i] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        lds_barrier();
+        if (tid == 0) s_count[q] = ovf[cur] ? -1 : (nsel[cur] < cap ? nsel[cur] : (int32_t)cap);
+        if (q1 >= nq) break;
+#pragma unroll
+        for (int s = 0; s < kVoteSlots; ++s) ids[s] = nid[s];
+        cur = nxt;
+        q = q1;
+    }
+#undef MRPT_LOAD_WINDOWS
+}
+
 // debug: F(x; q) of every listed candidate, by binary search of x in each of
 // the query's T leaf lists (independent of the counting kernel)
 __global__ __launch_bounds__(256) void vote_counts_kernel(const int32_t* __restrict__ leaf,
@@ -505,13 +657,61 @@ __global__ void copy_counts_kernel(const int32_t* __restrict__ src, int64_t nq, 
     if (i < nq) dst[i] = src[i];
 }
 
-// Which vote kernel runs: 2 = one wave per query (default), 1 = persistent
-// workgroups, 0 = one workgroup per query.  MRPT_VOTE_KERNEL selects another
-// for tuning; all three compute the same S.
+// Which vote kernel runs: 3 = single pass with the id map (default, when n
+// fits), 2 = one wave per query, 1 = persistent multi-pass, 0 = one workgroup
+// per query.  MRPT_VOTE_KERNEL selects another for tuning; all compute the
+// same S.
 int vote_kernel_choice() {
     const char* env = std::getenv("MRPT_VOTE_KERNEL");
-    const int choice = (env && *env) ? std::atoi(env) : 2;
-    return (choice < 0 || choice > 2) ? 2 : choice;
+    const int choice = (env && *env) ? std::atoi(env) : 3;
+    return (choice < 0 || choice > 3) ? 3 : choice;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// the single-pass kernel, then the multi-pass one for the queries whose hash
+// table overflowed; false if the id map does not fit
+template <int B>
+bool launch_vote_single_pass(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
+                             int64_t cap, int32_t* s_count, int64_t chunk, size_t multi_lds, hipStream_t s,
+                             hipError_t* err) {
+    constexpr size_t kStatic = 2 * kMaxT * 4 * 2 + 16;
+    const bool hash = v >= 2;
+    const int64_t bm_words = ((ix->n + 31) / 32 + 3) / 4 * 4;
+    const size_t lds = (size_t)(bm_words + (hash ? (1 << kHashLog2) : 0)) * 4;
+    const int64_t windows = (int64_t)((ix->T + kVoteWaves - 1) / kVoteWaves) * ((ix->max_leaf + kWave - 1) / kWave);
+    if (lds + kStatic > (size_t)std::min(lds_per_block_limit(), 160 * 1024) || windows > kVoteSlots ||
+        ix->n >= (int64_t(1) << 24))
+        return false;
+    const int64_t grid = std::min<int64_t>(nq, device_cus());
+    if (hash) {
+        (void)hipFuncSetAttribute((const void*)vote_bitmap_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        hipLaunchKernelGGL(vote_bitmap_kernel<true>, dim3((unsigned)grid), dim3(kVoteBlock), lds, s, leaf, ix->perm,
+                           ix->off, ix->n, ix->T, v, nq, (int32_t)bm_words, s_ids, cap, s_count);
+        *err = hipGetLastError();
+        if (*err != hipSuccess) return true;
+        (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)multi_lds);
+        hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)nq), dim3(kVoteBlock), multi_lds, s, leaf, ix->perm,
+                           ix->off, ix->n, ix->T, v, (int32_t)chunk, s_ids, cap, s_count, 1);
+    } else {
+        (void)hipFuncSetAttribute((const void*)vote_bitmap_kernel<false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(vote_bitmap_kernel<false>, dim3((unsigned)grid), dim3(kVoteBlock), lds, s, leaf, ix->perm,
+                           ix->off, ix->n, ix->T, v, nq, (int32_t)bm_words, s_ids, cap, s_count);
+    }
+    *err = hipGetLastError();
+    return true;
 }
 
 template <int B>
@@ -531,6 +731,10 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     const size_t lds = (size_t)(chunk / per) * 4;
     // windows per wave: its trees times the 64-id windows of the longest leaf
     const int64_t windows = (int64_t)((ix->T + kVoteWaves - 1) / kVoteWaves) * ((ix->max_leaf + kWave - 1) / kWave);
+    if (vote_kernel_choice() == 3) {
+        hipError_t err = hipSuccess;
+        if (launch_vote_single_pass<B>(ix, leaf, nq, v, s_ids, cap, s_count, chunk, lds, s, &err)) return err;
+    }
     if (vote_kernel_choice() == 2) {
         // one wave per query: an 8 KB counter slice per wave
         constexpr int64_t kSliceBytes = 8192;
@@ -557,14 +761,7 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         return hipGetLastError();
     }
     if (windows <= kVoteSlots && vote_kernel_choice() == 1) {
-        static int cus = 0;
-        if (cus == 0) {
-            int dev = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-                cus = 256;
-        }
-        const int64_t grid = std::min<int64_t>(nq, cus);
+        const int64_t grid = std::min<int64_t>(nq, device_cus());
         (void)hipFuncSetAttribute((const void*)vote_persistent_kernel<B>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(vote_persistent_kernel<B>, dim3((unsigned)grid), dim3(kVoteBlock), lds, s, leaf, ix->perm,
@@ -573,7 +770,7 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     }
     (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)nq), dim3(kVoteBlock), lds, s, leaf, ix->perm, ix->off, ix->n,
-                       ix->T, v, (int32_t)chunk, s_ids, cap, s_count);
+                       ix->T, v, (int32_t)chunk, s_ids, cap, s_count, 0);
     return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ struct Workspace {
     int32_t* s_ids = nullptr;    // nb x cap
     int32_t* s_count = nullptr;  // nb
     int32_t* flag = nullptr;     // 1 int
+    float* pq = nullptr;         // nb x T*depth projections (two-kernel routing)
     void* base = nullptr;
     size_t bytes = 0;
     hipEvent_t done = nullptr;   // recorded after the last kernel that used it
@@ -105,7 +106,10 @@ void grow_trees_host(const float* X, int64_t n, int32_t d, int32_t T, int32_t de
                      const std::vector<float>& val, HostTrees& out);
 
 // kernel launchers (kernels_route/vote/search/misc.hip); all asynchronous
-hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf,
+// pq: scratch of route_workspace_floats(ix, nq) floats for the projections
+// (nullptr selects the fused single-kernel form)
+size_t route_workspace_floats(const mrpt_index* ix, int64_t nq);
+hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
                         hipStream_t s);
 hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v,
                        int32_t* s_ids, int64_t cap, int32_t* s_count, hipStream_t s);
