@@ -78,8 +78,7 @@ mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
     const size_t ids_b = ((size_t)nb * (size_t)cap * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t cnt_b = ((size_t)nb * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t pq_b = (route_workspace_floats(ix, nb) * sizeof(float) + 255) & ~size_t(255);
-    const size_t ord_b = cnt_b;
-    const size_t need = leaf_b + ids_b + cnt_b + 256 + ord_b + pq_b;
+    const size_t need = leaf_b + ids_b + cnt_b + 256 + pq_b;
     if (!ix->ws.done) MRPT_HIP_TRY(hipEventCreateWithFlags(&ix->ws.done, hipEventDisableTiming));
     if (need > ix->ws.bytes) {
         MRPT_HIP_TRY(hipEventSynchronize(ix->ws.done));
@@ -97,8 +96,7 @@ mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
     ix->ws.s_ids = (int32_t*)(b + leaf_b);
     ix->ws.s_count = (int32_t*)(b + leaf_b + ids_b);
     ix->ws.flag = (int32_t*)(b + leaf_b + ids_b + cnt_b);
-    ix->ws.order = (int32_t*)(b + leaf_b + ids_b + cnt_b + 256);
-    ix->ws.pq = pq_b ? (float*)(b + leaf_b + ids_b + cnt_b + 256 + ord_b) : nullptr;
+    ix->ws.pq = pq_b ? (float*)(b + leaf_b + ids_b + cnt_b + 256) : nullptr;
     return MRPT_OK;
 }
 
@@ -108,7 +106,7 @@ int64_t candidate_cap(const mrpt_index* ix, int32_t v) {
 }
 
 int64_t batch_size(const mrpt_index* ix, int64_t nq, int64_t cap) {
-    const int64_t per_q = (int64_t)(ix->T + cap + 2) * (int64_t)sizeof(int32_t) +
+    const int64_t per_q = (int64_t)(ix->T + cap + 1) * (int64_t)sizeof(int32_t) +
                           (int64_t)route_workspace_floats(ix, 1) * (int64_t)sizeof(float);
     const int64_t nb = std::max<int64_t>(1, (int64_t)workspace_limit() / per_q);
     return std::min(nq, nb);
@@ -158,16 +156,15 @@ mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_
         const float* Qb = Q + q0 * ix->d;
         MRPT_HIP_TRY(mark(q0, 0));
         MRPT_HIP_TRY(launch_route(ix, Qb, m, ix->ws.leaf, ix->ws.pq, s));
-        MRPT_HIP_TRY(launch_locality_order(ix, ix->ws.leaf, m, ix->ws.order, s));
         MRPT_HIP_TRY(mark(q0, 1));
-        MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, ix->ws.order, m, v, ix->ws.s_ids, cap, ix->ws.s_count, s));
+        MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, m, v, ix->ws.s_ids, cap, ix->ws.s_count, s));
         MRPT_HIP_TRY(mark(q0, 2));
         if (o.precision == MRPT_FP32)
-            MRPT_HIP_TRY(launch_dist_fp32(ix, Qb, ix->ws.order, m, ix->ws.s_ids, cap, ix->ws.s_count, k,
-                                          out_idx + q0 * k, out_dist + q0 * k, s));
+            MRPT_HIP_TRY(launch_dist_fp32(ix, Qb, m, ix->ws.s_ids, cap, ix->ws.s_count, k, out_idx + q0 * k,
+                                          out_dist + q0 * k, s));
         else
-            MRPT_HIP_TRY(launch_dist_bf16(ix, Qb, ix->ws.order, m, ix->ws.s_ids, cap, ix->ws.s_count, k,
-                                          o.rerank_factor, o.recheck_rel, out_idx + q0 * k, out_dist + q0 * k, s));
+            MRPT_HIP_TRY(launch_dist_bf16(ix, Qb, m, ix->ws.s_ids, cap, ix->ws.s_count, k, o.rerank_factor,
+                                          o.recheck_rel, out_idx + q0 * k, out_dist + q0 * k, s));
         MRPT_HIP_TRY(mark(q0, 3));
         if (o.s_count) MRPT_HIP_TRY(launch_copy_counts(ix->ws.s_count, m, o.s_count + q0, s));
     }
@@ -412,8 +409,7 @@ mrpt_status mrpt_debug_votes(const mrpt_index* cix, const float* Q, int64_t nq, 
     MRPT_TRY(ensure_workspace(ix, nq, 1));
     MRPT_HIP_TRY(hipStreamWaitEvent(s, ix->ws.done, 0));
     MRPT_HIP_TRY(launch_route(ix, Q, nq, ix->ws.leaf, ix->ws.pq, s));
-    MRPT_HIP_TRY(launch_locality_order(ix, ix->ws.leaf, nq, ix->ws.order, s));
-    MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, ix->ws.order, nq, v, s_ids, cap, s_count, s));
+    MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, nq, v, s_ids, cap, s_count, s));
     if (s_votes) MRPT_HIP_TRY(launch_vote_counts(ix, ix->ws.leaf, nq, s_ids, cap, s_count, s_votes, s));
     MRPT_HIP_TRY(hipEventRecord(ix->ws.done, s));
     return MRPT_OK;

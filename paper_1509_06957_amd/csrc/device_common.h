@@ -30,27 +30,6 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Query placement.  Workgroups are dispatched round-robin over the 8 XCDs
-// (workgroup b runs on XCD b % 8), each with its own L2.  The batch is walked
-// in a locality order (queries sorted by their leaf in tree 0, so neighbours
-// in the order are neighbours in space and share leaves and candidates); XCD
-// x takes the contiguous stretch [x*per, (x+1)*per) of that order, per =
-// ceil(nq/8), so the queries running on one XCD at the same time are close.
-constexpr int kXcds = 8;
-
-// position in the locality order of workgroup b of a grid with one workgroup
-// per position (grid = 8*per); -1 if b has no query
-__device__ __forceinline__ int64_t xcd_position(int64_t b, int64_t nq) {
-    const int64_t per = (nq + kXcds - 1) / kXcds;
-    const int64_t p = (b % kXcds) * per + b / kXcds;
-    return p < nq ? p : -1;
-}
-
-// the query at position p of the locality order (order == nullptr: identity)
-__device__ __forceinline__ int64_t query_at(const int32_t* order, int64_t p) {
-    return order ? (int64_t)order[p] : p;
-}
-
 // strict order on (distance, id): the order in which k-NN results are ranked
 __device__ __forceinline__ bool key_less(float da, int32_t ia, float db, int32_t ib) {
     return da < db || (da == db && ia < ib);

@@ -453,50 +453,6 @@ hipError_t launch_route_fast(const mrpt_index* ix, const float* Q, int64_t nq, i
     return hipGetLastError();
 }
 
-// Locality order of the batch: queries sorted by their leaf in tree 0 (its top
-// `bits` levels), by counting sort in one workgroup.  Queries in one leaf, and
-// in sibling leaves, lie in the same region of space.
-constexpr int kOrderThreads = 1024;
-
-__global__ __launch_bounds__(kOrderThreads) void locality_order_kernel(const int32_t* __restrict__ leaf, int64_t nq,
-                                                                       int32_t T, int32_t shift, int32_t nbuckets,
-                                                                       int32_t* __restrict__ order) {
-    extern __shared__ int32_t hist[];   // nbuckets
-    __shared__ int32_t tsum[kOrderThreads];
-    const int tid = (int)threadIdx.x;
-    for (int i = tid; i < nbuckets; i += kOrderThreads) hist[i] = 0;
-    __syncthreads();
-    for (int64_t q = tid; q < nq; q += kOrderThreads) atomicAdd(&hist[leaf[q * T] >> shift], 1);
-    __syncthreads();
-    // exclusive scan: each thread owns a run of consecutive buckets
-    const int run = (nbuckets + kOrderThreads - 1) / kOrderThreads;
-    const int b0 = tid * run;
-    int s = 0;
-    for (int i = 0; i < run; ++i)
-        if (b0 + i < nbuckets) s += hist[b0 + i];
-    tsum[tid] = s;
-    __syncthreads();
-    for (int o = 1; o < kOrderThreads; o <<= 1) {
-        const int add = tid >= o ? tsum[tid - o] : 0;
-        __syncthreads();
-        tsum[tid] += add;
-        __syncthreads();
-    }
-    int acc = tsum[tid] - s;
-    for (int i = 0; i < run; ++i) {
-        if (b0 + i < nbuckets) {
-            const int c = hist[b0 + i];
-            hist[b0 + i] = acc;
-            acc += c;
-        }
-    }
-    __syncthreads();
-    for (int64_t q = tid; q < nq; q += kOrderThreads) {
-        const int pos = atomicAdd(&hist[leaf[q * T] >> shift], 1);
-        order[pos] = (int32_t)q;
-    }
-}
-
 constexpr int kProjRows = 16;   // rows per wave in project_kernel
 
 hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
@@ -549,19 +505,6 @@ hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, in
 }
 
 }  // namespace
-
-hipError_t launch_locality_order(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t* order,
-                                 hipStream_t s) {
-    if (nq == 0) return hipSuccess;
-    const int bits = std::min(ix->depth, 14);
-    const int nbuckets = 1 << bits;
-    const size_t lds = (size_t)nbuckets * sizeof(int32_t);
-    (void)hipFuncSetAttribute((const void*)locality_order_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL(locality_order_kernel, dim3(1), dim3(kOrderThreads), lds, s, leaf, nq, ix->T,
-                       ix->depth - bits, nbuckets, order);
-    return hipGetLastError();
-}
 
 size_t route_workspace_floats(const mrpt_index* ix, int64_t nq) {
     return ix->max_row_nnz <= kWave ? (size_t)nq * ix->T * ix->depth : 0;

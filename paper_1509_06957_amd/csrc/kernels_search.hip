@@ -25,7 +25,7 @@ constexpr int kDistWaves = 4;
 
 template <int G, int NV, int R>
 __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict__ X, int32_t d,
-                                                        const float* __restrict__ Q, const int32_t* __restrict__ order, int64_t nq,
+                                                        const float* __restrict__ Q,
                                                         const int32_t* __restrict__ s_ids, int64_t cap,
                                                         const int32_t* __restrict__ s_count, int32_t k,
                                                         int32_t* __restrict__ out_idx,
@@ -37,9 +37,7 @@ __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict_
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
     const int g = lane / G, gl = lane - g * G;
-    const int64_t pos = xcd_position(blockIdx.x, nq);
-    if (pos < 0) return;
-    const int64_t q = query_at(order, pos);
+    const int64_t q = blockIdx.x;
     const int ns = uniform(s_count[q]);
     const int32_t* S = s_ids + q * cap;
     const int nvec = d >> 2;
@@ -126,7 +124,7 @@ __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict_
 // generic fallback (any d): scalar loads, one wave per candidate row
 template <int R>
 __global__ __launch_bounds__(256) void dist_fp32_generic_kernel(const float* __restrict__ X, int32_t d,
-                                                                const float* __restrict__ Q, const int32_t* __restrict__ order, int64_t nq,
+                                                                const float* __restrict__ Q,
                                                                 const int32_t* __restrict__ s_ids,
                                                                 int64_t cap,
                                                                 const int32_t* __restrict__ s_count,
@@ -136,9 +134,7 @@ __global__ __launch_bounds__(256) void dist_fp32_generic_kernel(const float* __r
     __shared__ int32_t mi[kDistWaves][kWave * R];
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
-    const int64_t pos = xcd_position(blockIdx.x, nq);
-    if (pos < 0) return;
-    const int64_t q = query_at(order, pos);
+    const int64_t q = blockIdx.x;
     const int ns = uniform(s_count[q]);
     const int32_t* S = s_ids + q * cap;
     const float* gq = Q + q * d;
@@ -194,7 +190,7 @@ template <int GB, int NVB, int RB>
 __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict__ X,
                                                         const uint16_t* __restrict__ Xb,
                                                         const float* __restrict__ xnorm, int32_t d,
-                                                        const float* __restrict__ Q, const int32_t* __restrict__ order, int64_t nq,
+                                                        const float* __restrict__ Q,
                                                         const int32_t* __restrict__ s_ids, int64_t cap,
                                                         const int32_t* __restrict__ s_count, int32_t k,
                                                         int32_t kp, float recheck_rel,
@@ -207,7 +203,7 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
     __shared__ int32_t cand[kMaxRerank];      // phase-1 survivors in prefilter rank order
     __shared__ float d32[kMaxRerank];         // their float32 squared distances
     __shared__ double d64[kMaxRerank];        // float64 squared distances (window only)
-    __shared__ int32_t rank_slot[kMaxRerank];     // rank by (d32, id) -> candidate slot
+    __shared__ int32_t order[kMaxRerank];     // rank by (d32, id) -> candidate slot
     __shared__ int32_t final_slot[kMaxK];
     __shared__ int win_lo, win_hi;
     __shared__ float qs[1024 + 64];           // query (float32) for phases 2-3 when d <= 1024
@@ -215,9 +211,7 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
     const int g = lane / GB, gl = lane - g * GB;
-    const int64_t pos = xcd_position(blockIdx.x, nq);
-    if (pos < 0) return;
-    const int64_t q = query_at(order, pos);
+    const int64_t q = blockIdx.x;
     const int ns = uniform(s_count[q]);
     const int32_t* S = s_ids + q * cap;
     const int nv8 = d >> 3;
@@ -335,21 +329,21 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
             const int32_t oi = cand[o] < 0 ? kPadId + o : cand[o];
             rank += key_less(d32[o], oi, kd, ki) ? 1 : 0;
         }
-        rank_slot[rank] = c;
+        order[rank] = c;
     }
     __syncthreads();
     // phase 3: float64 recheck of the window around the k-th float32 distance
     if (threadIdx.x == 0) {
         const int kk = k < kp ? k : kp;
-        const float dk2 = d32[rank_slot[kk - 1]];
+        const float dk2 = d32[order[kk - 1]];
         int lo = kk, hi = kk;
         if (dk2 < INFINITY) {
             const float dk = sqrtf(dk2);
             const float tol = recheck_rel * dk;
             lo = kk - 1;
-            while (lo > 0 && fabsf(sqrtf(d32[rank_slot[lo - 1]]) - dk) <= tol) --lo;
+            while (lo > 0 && fabsf(sqrtf(d32[order[lo - 1]]) - dk) <= tol) --lo;
             hi = kk;
-            while (hi < kp && d32[rank_slot[hi]] < INFINITY && fabsf(sqrtf(d32[rank_slot[hi]]) - dk) <= tol) ++hi;
+            while (hi < kp && d32[order[hi]] < INFINITY && fabsf(sqrtf(d32[order[hi]]) - dk) <= tol) ++hi;
         }
         win_lo = lo;
         win_hi = hi;
@@ -357,7 +351,7 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
     __syncthreads();
     const int wlo = win_lo, whi = win_hi;
     for (int r = wlo + w; r < whi; r += kDistWaves) {
-        const int c = uniform(rank_slot[r]);
+        const int c = uniform(order[r]);
         const int32_t id = uniform(cand[c]);
         const float* xr = X + (int64_t)id * d;
         double a = 0.0;
@@ -372,16 +366,16 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
     __syncthreads();
     for (int r = (int)threadIdx.x; r < k; r += (int)blockDim.x) {
         if (r < wlo || r >= whi) {
-            final_slot[r] = r < kp ? rank_slot[r] : -1;
+            final_slot[r] = r < kp ? order[r] : -1;
         }
     }
     for (int r = wlo + (int)threadIdx.x; r < whi; r += (int)blockDim.x) {
-        const int c = rank_slot[r];
+        const int c = order[r];
         const double kd = d64[c];
         const int32_t ki = cand[c];
         int rank = wlo;
         for (int o = wlo; o < whi; ++o) {
-            const int oc = rank_slot[o];
+            const int oc = order[o];
             rank += (d64[oc] < kd || (d64[oc] == kd && cand[oc] < ki)) ? 1 : 0;
         }
         if (rank < k) final_slot[rank] = -2 - c;  // marks a rechecked slot
@@ -406,17 +400,17 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
 
 }  // namespace
 
-hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, const int32_t* order, int64_t nq,
-                            const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k, int32_t* out_idx,
-                            float* out_dist, hipStream_t s) {
+hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, int64_t nq, const int32_t* s_ids, int64_t cap,
+                            const int32_t* s_count, int32_t k, int32_t* out_idx, float* out_dist,
+                            hipStream_t s) {
     if (nq == 0) return hipSuccess;
     const int d = ix->d;
     const int R = k <= 64 ? 1 : k <= 128 ? 2 : k <= 256 ? 4 : k <= 512 ? 8 : 16;
-    dim3 grid((unsigned)((nq + kXcds - 1) / kXcds * kXcds)), block(256);   // one workgroup per position
+    dim3 grid((unsigned)nq), block(256);
     const bool vec = (d % 4) == 0 && d <= 1024 &&
                      ((uintptr_t)Q % 16) == 0 && ((uintptr_t)ix->X % 16) == 0;
-#define MRPT_DIST(G, NV, RR)                                                                             \
-    hipLaunchKernelGGL((dist_fp32_kernel<G, NV, RR>), grid, block, 0, s, ix->X, d, Q, order, nq, s_ids, cap, \
+#define MRPT_DIST(G, NV, RR)                                                                      \
+    hipLaunchKernelGGL((dist_fp32_kernel<G, NV, RR>), grid, block, 0, s, ix->X, d, Q, s_ids, cap, \
                        s_count, k, out_idx, out_dist)
 #define MRPT_DIST_R(G, NV)                     \
     switch (R) {                               \
@@ -435,8 +429,8 @@ hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, const int32_t*
         else { MRPT_DIST_R(64, 4); }
     } else {
 #define MRPT_DISTG(RR)                                                                                 \
-    hipLaunchKernelGGL((dist_fp32_generic_kernel<RR>), grid, block, 0, s, ix->X, d, Q, order, nq, s_ids, cap, \
-                       s_count, k, out_idx, out_dist)
+    hipLaunchKernelGGL((dist_fp32_generic_kernel<RR>), grid, block, 0, s, ix->X, d, Q, s_ids, cap, s_count, \
+                       k, out_idx, out_dist)
         switch (R) {
             case 1: MRPT_DISTG(1); break;
             case 2: MRPT_DISTG(2); break;
@@ -451,17 +445,17 @@ hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_dist_bf16(const mrpt_index* ix, const float* Q, const int32_t* order, int64_t nq,
-                            const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k, int32_t rerank,
-                            float recheck_rel, int32_t* out_idx, float* out_dist, hipStream_t s) {
+hipError_t launch_dist_bf16(const mrpt_index* ix, const float* Q, int64_t nq, const int32_t* s_ids, int64_t cap,
+                            const int32_t* s_count, int32_t k, int32_t rerank, float recheck_rel,
+                            int32_t* out_idx, float* out_dist, hipStream_t s) {
     if (nq == 0) return hipSuccess;
     const int d = ix->d;
     const int kp = k * rerank;
     const int RB = kp <= 64 ? 1 : kp <= 128 ? 2 : kp <= 256 ? 4 : 8;
-    dim3 grid((unsigned)((nq + kXcds - 1) / kXcds * kXcds)), block(256);   // one workgroup per position
+    dim3 grid((unsigned)nq), block(256);
 #define MRPT_BF(GB, NVB, RR)                                                                              \
     hipLaunchKernelGGL((dist_bf16_kernel<GB, NVB, RR>), grid, block, 0, s, ix->X, ix->Xb, ix->xnorm, d, Q, \
-                       order, nq, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
+                       s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
 #define MRPT_BF_R(GB, NVB)                 \
     switch (RB) {                          \
         case 1: MRPT_BF(GB, NVB, 1); break; \

@@ -81,10 +81,9 @@ __device__ __forceinline__ bool count_id(uint32_t* cnt, uint32_t rel, int v) {
 // full).  With redo_only set, only queries whose count is -1 are processed.
 template <int B>
 __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restrict__ leaf,
-                                                          const int32_t* __restrict__ order,
                                                           const int32_t* __restrict__ perm,
                                                           const int32_t* __restrict__ off, int64_t n,
-                                                          int32_t T, int32_t v, int64_t nq, int32_t chunk,
+                                                          int32_t T, int32_t v, int32_t chunk,
                                                           int32_t* __restrict__ s_ids, int64_t cap,
                                                           int32_t* __restrict__ s_count, int32_t redo_only) {
     extern __shared__ uint32_t vote_cnt[];   // chunk * B / 32 words
@@ -96,9 +95,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
     const int tid = (int)threadIdx.x;
     const int lane = lane_id();
     const int w = uniform(tid >> 6);
-    const int64_t pos = xcd_position(blockIdx.x, nq);
-    if (pos < 0) return;
-    const int64_t q = query_at(order, pos);
+    const int64_t q = blockIdx.x;
     const int words = chunk / per;
     if (redo_only && s_count[q] >= 0) return;
 
@@ -236,7 +233,6 @@ __device__ __forceinline__ void flush_repeats(const int32_t* buf, int cnt, uint3
 // next query and the leaf positions of the one after are in flight.
 template <bool HASH>
 __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __restrict__ leaf,
-                                                              const int32_t* __restrict__ order,
                                                               const int32_t* __restrict__ perm,
                                                               const int32_t* __restrict__ off, int64_t n,
                                                               int32_t T, int32_t v, int64_t nq, int32_t map_words,
@@ -255,27 +251,15 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     const int w = uniform(tid >> 6);
     int32_t* cbuf = reinterpret_cast<int32_t*>(map_smem + map_words + kTab) + w * kCompact;
     const uint32_t dummy = (uint32_t)map_words - 1u;    // a word past every real id
-    // positions of this workgroup in the locality order: a stretch of its XCD's range
-    int64_t p, step, pend;
-    if (gridDim.x % kXcds == 0) {
-        const int64_t per = (nq + kXcds - 1) / kXcds;
-        const int64_t x = blockIdx.x % kXcds;
-        p = x * per + blockIdx.x / kXcds;
-        step = gridDim.x / kXcds;
-        pend = (x + 1) * per < nq ? (x + 1) * per : nq;
-    } else {
-        p = blockIdx.x;
-        step = gridDim.x;
-        pend = nq;
-    }
-    if (p >= pend) return;
+    const int64_t stride = gridDim.x;
+    int64_t q = blockIdx.x;
+    if (q >= nq) return;
 
     for (int i = tid; i < ((map_words + kTab) >> 2); i += kVoteBlock)
         reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int k = 0; k < 2; ++k) {
-        const int64_t pk = p + k * step;
-        if (pk < pend && tid < T) {
-            const int64_t qq = query_at(order, pk);
+        const int64_t qq = q + k * stride;
+        if (qq < nq && tid < T) {
             const int L = leaf[qq * T + tid];
             const int b = off[L];
             tbase[k][tid] = b;
@@ -304,11 +288,10 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     int cur = 0;
     while (true) {
         const int nxt = cur ^ 1;
-        const int64_t q = query_at(order, p);
-        const int64_t p1 = p + step, p2 = p + 2 * step;
-        if (p1 < pend) MRPT_LOAD_WINDOWS(nid, nxt);         // in flight while q is counted
+        const int64_t q1 = q + stride, q2 = q + 2 * stride;
+        if (q1 < nq) MRPT_LOAD_WINDOWS(nid, nxt);           // in flight while q is counted
         int L2 = 0;
-        if (p2 < pend && tid < T) L2 = leaf[query_at(order, p2) * T + tid];   // likewise
+        if (q2 < nq && tid < T) L2 = leaf[q2 * T + tid];     // likewise
         int32_t* out = s_ids + q * cap;
         int* my_nsel = &nsel[cur];
         int pending = 0;                                     // wave-uniform fill of cbuf
@@ -343,7 +326,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         }
         if constexpr (HASH) flush_repeats(cbuf, pending, tab, v, &ovf[cur], my_nsel, out, cap);
         lds_barrier();
-        if (p2 < pend && tid < T) {                          // buffer cur held q's positions: free now
+        if (q2 < nq && tid < T) {                            // buffer cur held q's positions: free now
             const int b = off[L2];
             tbase[cur][tid] = b;
             tlen[cur][tid] = off[L2 + 1] - b;
@@ -357,11 +340,11 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         }
         lds_barrier();
         if (tid == 0) s_count[q] = ovf[cur] ? -1 : (nsel[cur] < cap ? nsel[cur] : (int32_t)cap);
-        if (p1 >= pend) break;
+        if (q1 >= nq) break;
 #pragma unroll
         for (int s = 0; s < kVoteSlots; ++s) ids[s] = nid[s];
         cur = nxt;
-        p = p1;
+        q = q1;
     }
 #undef MRPT_LOAD_WINDOWS
 }
@@ -417,8 +400,7 @@ int device_cus() {
 }
 
 template <int B>
-hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, const int32_t* order, int64_t nq, int32_t v,
-                         int32_t* s_ids,
+hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
                          int64_t cap, int32_t* s_count, hipStream_t s) {
     constexpr int per = 32 / B;
     const size_t limit = (size_t)std::min(lds_per_block_limit(), 160 * 1024);
@@ -445,8 +427,8 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, const int32_
     do {                                                                                                          \
         (void)hipFuncSetAttribute((const void*)vote_map_kernel<H>, hipFuncAttributeMaxDynamicSharedMemorySize,     \
                                   (int)map_lds);                                                                  \
-        hipLaunchKernelGGL(vote_map_kernel<H>, dim3((unsigned)grid), dim3(kVoteBlock), map_lds, s, leaf, order,   \
-                           ix->perm, ix->off, ix->n, ix->T, v, nq, (int32_t)map_words, s_ids, cap, s_count);      \
+        hipLaunchKernelGGL(vote_map_kernel<H>, dim3((unsigned)grid), dim3(kVoteBlock), map_lds, s, leaf, ix->perm, \
+                           ix->off, ix->n, ix->T, v, nq, (int32_t)map_words, s_ids, cap, s_count);               \
     } while (0)
         if (hash) MRPT_MAP(true);
         else MRPT_MAP(false);
@@ -457,22 +439,20 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, const int32_
     }
     (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)multi_lds);
-    const int64_t grid_multi = (nq + kXcds - 1) / kXcds * kXcds;   // one workgroup per position
-    hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)grid_multi), dim3(kVoteBlock), multi_lds, s, leaf, order,
-                       ix->perm, ix->off, ix->n, ix->T, v, nq, (int32_t)chunk, s_ids, cap, s_count, single ? 1 : 0);
+    hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)nq), dim3(kVoteBlock), multi_lds, s, leaf, ix->perm, ix->off,
+                       ix->n, ix->T, v, (int32_t)chunk, s_ids, cap, s_count, single ? 1 : 0);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, const int32_t* order, int64_t nq, int32_t v,
-                       int32_t* s_ids,
+hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
                        int64_t cap, int32_t* s_count, hipStream_t s) {
     if (nq == 0) return hipSuccess;
-    if (v == 1) return launch_vote_b<1>(ix, leaf, order, nq, v, s_ids, cap, s_count, s);
-    if (v <= 3) return launch_vote_b<2>(ix, leaf, order, nq, v, s_ids, cap, s_count, s);
-    if (v <= 15) return launch_vote_b<4>(ix, leaf, order, nq, v, s_ids, cap, s_count, s);
-    return launch_vote_b<8>(ix, leaf, order, nq, v, s_ids, cap, s_count, s);
+    if (v == 1) return launch_vote_b<1>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+    if (v <= 3) return launch_vote_b<2>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+    if (v <= 15) return launch_vote_b<4>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+    return launch_vote_b<8>(ix, leaf, nq, v, s_ids, cap, s_count, s);
 }
 
 hipError_t launch_vote_counts(const mrpt_index* ix, const int32_t* leaf, int64_t nq, const int32_t* s_ids,

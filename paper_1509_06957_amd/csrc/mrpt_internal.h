@@ -48,7 +48,6 @@ struct Workspace {
     int32_t* s_count = nullptr;  // nb
     int32_t* flag = nullptr;     // 1 int
     float* pq = nullptr;         // nb x T*depth projections (two-kernel routing)
-    int32_t* order = nullptr;    // nb: locality order of the batch
     void* base = nullptr;
     size_t bytes = 0;
     hipEvent_t done = nullptr;   // recorded after the last kernel that used it
@@ -112,18 +111,15 @@ void grow_trees_host(const float* X, int64_t n, int32_t d, int32_t T, int32_t de
 size_t route_workspace_floats(const mrpt_index* ix, int64_t nq);
 hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
                         hipStream_t s);
-// order: the batch's locality order (launch_locality_order), nb int32
-hipError_t launch_locality_order(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t* order,
-                                 hipStream_t s);
-hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, const int32_t* order, int64_t nq,
-                       int32_t v, int32_t* s_ids, int64_t cap, int32_t* s_count, hipStream_t s);
+hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v,
+                       int32_t* s_ids, int64_t cap, int32_t* s_count, hipStream_t s);
 hipError_t launch_vote_counts(const mrpt_index* ix, const int32_t* leaf, int64_t nq,
                               const int32_t* s_ids, int64_t cap, const int32_t* s_count,
                               uint8_t* s_votes, hipStream_t s);
-hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, const int32_t* order, int64_t nq,
+hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, int64_t nq,
                             const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k,
                             int32_t* out_idx, float* out_dist, hipStream_t s);
-hipError_t launch_dist_bf16(const mrpt_index* ix, const float* Q, const int32_t* order, int64_t nq,
+hipError_t launch_dist_bf16(const mrpt_index* ix, const float* Q, int64_t nq,
                             const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k,
                             int32_t rerank, float recheck_rel, int32_t* out_idx, float* out_dist,
                             hipStream_t s);
