@@ -5,15 +5,16 @@
 // Two forms, both one workgroup of 16 waves per CU-resident query:
 //
 //  * single pass (when a 1-bit map of all n ids fits LDS): the first
-//    occurrence of an id sets its bit; later occurrences are compacted per
-//    wave and counted in an LDS hash table keyed by id.  The workgroup is
-//    persistent over queries and prefetches the next query's leaf windows.
+//    occurrence of an id sets its bit; repeated occurrences are queued, and
+//    the queue is run through the map again, v - 1 times, to find the ids
+//    with F >= v.  The workgroup is persistent over queries and has the next
+//    query's leaf windows in flight while it counts.
 //  * multi pass (any n): packed counters of B bits per id (the smallest width
-//    that holds v) over id ranges that fit LDS, one pass per range.
+//    that holds v) over id ranges that fit LDS, one pass per range; it also
+//    recounts the queries whose repeat queue overflowed.
 //
-// In both, each wave owns trees w, w+16, ...; a tree's leaf list (ascending
-// ids, contiguous in that tree's permutation) is read as 64-id windows into
-// registers, coalesced.
+// A tree's leaf list (ascending ids, contiguous in that tree's permutation)
+// is read as 64-id windows into registers, coalesced.
 #include <cstdlib>
 
 #include "device_common.h"
@@ -178,175 +179,225 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
 }
 
 // ---------------------------------------------------------------------------
-// single-pass form
+// single-pass form (n < 2^24 and the id map fits LDS; windows in registers)
 // ---------------------------------------------------------------------------
-constexpr int kHashEntries = 6144;   // 24 KB of (id + 1) << 8 | count
-constexpr int kCompact = 128;        // repeated ids buffered per wave
-constexpr int kMapBatch = 8;         // slots whose map updates are issued together
+// A 1-bit map over the ids answers "seen before?" with one LDS atomic OR per
+// id occurrence.  Reading a query's windows through the map leaves the first
+// occurrence of every id in the map and queues each repeated occurrence
+// (an id with F = f is queued f - 1 times).  For v = 1 the first occurrences
+// are S.  For v >= 2 the queue is run through the cleared map v - 1 more
+// times: each of the first v - 2 runs blanks the first queued occurrence of
+// every id, so after j runs an id with F = f has f - 1 - j occurrences left,
+// and the last run elects the first remaining occurrence of every id, i.e.
+// exactly the ids with F >= v, each once.  The queue is a few thousand
+// entries, so these runs use all 1024 threads and cost little.
+//
+// The workgroup is persistent over the queries g, g + G, ...: while query q
+// is counted, the leaf windows of the next query (registers), the leaf
+// offsets of the one after and the leaf numbers of the third are in flight.
+// A query's T * wpl windows (tree u / wpl, 64-id part u % wpl) are dealt
+// round-robin over the 16 waves.  Empty lanes carry the id n + 32 lane + s
+// (s: slot), which is never queued or elected; its map bit lies in spare
+// words past the ids, a different word for every lane of a slot.  A query
+// whose queue overflows gets count -1 and is recounted by the multi-pass
+// kernel.
+constexpr int kMapBatch = 4;         // slots whose map updates are issued together
+constexpr int kPosBufs = 3;          // leaf position buffers of the pipeline
 
-__device__ __forceinline__ uint32_t hash_slot(int32_t id) {
-    const uint32_t h = (uint32_t)id * 2654435761u;
-    return (uint32_t)(((uint64_t)h * kHashEntries) >> 32);
+// number of set bits of m below this lane, plus base
+__device__ __forceinline__ uint32_t rank_below(uint64_t m, uint32_t base) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
 }
 
-// F(id) after this occurrence (>= 2) for an id whose map bit was already set;
-// 0 if the table is full
-__device__ __forceinline__ int hash_increment(uint32_t* tab, int32_t id) {
-    const uint32_t key = (uint32_t)(id + 1);
-    uint32_t h = hash_slot(id);
-    for (int probe = 0; probe < kHashEntries; ++probe) {
-        uint32_t cur = tab[h];
-        if (cur == 0u) {
-            const uint32_t prev = atomicCAS(&tab[h], 0u, (key << 8) | 2u);
-            if (prev == 0u) return 2;
-            cur = prev;
-        }
-        if ((cur >> 8) == key) {
-            const uint32_t old = atomicAdd(&tab[h], 1u);
-            return (int)(old & 0xffu) + 1;
-        }
-        h = h + 1u == (uint32_t)kHashEntries ? 0u : h + 1u;
+// wave-aggregated store of NB ballots (slot g selected the lanes of m[g])
+// at consecutive places of dst reserved with one LDS atomic on *fill; places
+// at or beyond `limit` are dropped and reported through *ovf
+template <int NB, typename Out>
+__device__ __forceinline__ void store_batch(const uint64_t (&m)[NB], const int32_t (&id)[NB], int* fill, Out* dst,
+                                            int64_t limit, int* ovf) {
+    int tot = 0;
+#pragma unroll
+    for (int g = 0; g < NB; ++g) tot += __popcll(m[g]);
+    if (tot == 0) return;
+    int base = 0;
+    if (lane_id() == 0) {
+        base = atomicAdd(fill, tot);
+        if (ovf && (int64_t)base + tot > limit) *ovf = 1;
     }
-    return 0;
-}
-
-// counts of the buffered repeated ids, all lanes busy; elected ids appended
-__device__ __forceinline__ void flush_repeats(const int32_t* buf, int cnt, uint32_t* tab, int v, int* ovf, int* nsel,
-                                              int32_t* out, int64_t cap) {
-    for (int i = 0; i < cnt; i += kWave) {
-        const int j = i + lane_id();
-        const int32_t id = j < cnt ? buf[j] : -1;
-        int c = -1;
-        if (id >= 0) {
-            c = hash_increment(tab, id);
-            if (c == 0) *ovf = 1;
+    base = __builtin_amdgcn_readfirstlane(base);
+#pragma unroll
+    for (int g = 0; g < NB; ++g) {
+        if ((m[g] >> lane_id()) & 1ull) {
+            const uint32_t at = rank_below(m[g], (uint32_t)base);
+            if ((int64_t)at < limit) dst[at] = id[g];
         }
-        append(c == v, id, nsel, out, cap);
+        base += __popcll(m[g]);
     }
 }
 
-// First occurrences set a bit of the id map (one LDS atomic OR, no branch);
-// a set bit marks a repeated occurrence, which is compacted into the wave's
-// buffer and counted in the hash table when the buffer is flushed (then all
-// 64 lanes work on repeats).  For v = 1 the map alone decides.  Persistent
-// over queries q, q + gridDim.x, ...: while q is counted, the windows of the
-// next query and the leaf positions of the one after are in flight.
-template <bool HASH>
+template <int S>
+__device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int2* __restrict__ tpos,
+                                             const int32_t* __restrict__ perm, int64_t n, int T, int t0,
+                                             int p0, int wpl, int dt, int dp) {
+    const int lane = lane_id();
+    int t = t0, part = p0;
+    // opaque to the optimizer: the per-slot addresses are the same for every
+    // query, and hoisting them out of the query loop would hold 2*S scalar
+    // registers for the whole kernel (spilled); they cost a few scalar ops here
+    asm volatile("" : "+s"(t), "+s"(part));
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        dst[s] = (int32_t)n + lane * 32 + s;
+        // keeps the S registers separate: formed as one vector (base + 0..S-1)
+        // they are allocated as a single tuple and spilled wholesale
+        asm volatile("" : "+v"(dst[s]));
+        if (t < T) {
+            const int2 bl = tpos[t];
+            // wave-uniform row base (scalar registers) + 32-bit lane offset
+            const int32_t* row = perm + (int64_t)t * n + uniform(bl.x) + part * kWave;
+            if (part * kWave + lane < uniform(bl.y)) dst[s] = row[(uint32_t)lane];
+        }
+        t += dt;
+        part += dp;
+        if (part >= wpl) { part -= wpl; ++t; }
+    }
+}
+
+// LDS: map [map_words] | queue [qcap] | leaf positions [kPosBufs][kMaxT] (int2)
+//      | qfill, nsel, ovf
+template <int S, bool QUEUE>
 __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __restrict__ leaf,
                                                               const int32_t* __restrict__ perm,
                                                               const int32_t* __restrict__ off, int64_t n,
-                                                              int32_t T, int32_t v, int64_t nq, int32_t map_words,
+                                                              int32_t T, int32_t wpl, int32_t v, int64_t nq,
+                                                              int32_t map_words, int32_t qcap,
                                                               int32_t* __restrict__ s_ids, int64_t cap,
                                                               int32_t* __restrict__ s_count) {
-    extern __shared__ uint32_t map_smem[];   // map [map_words] | table | per-wave buffers
-    __shared__ int32_t tbase[2][kMaxT];       // leaf start inside its tree
-    __shared__ int32_t tlen[2][kMaxT];
-    __shared__ int nsel[2];
-    __shared__ int ovf[2];
-    constexpr int kTab = HASH ? kHashEntries : 0;
+    extern __shared__ uint32_t map_smem[];
     uint32_t* map = map_smem;
-    uint32_t* tab = map_smem + map_words;
+    int32_t* queue = reinterpret_cast<int32_t*>(map_smem + map_words);
+    int2 (*tpos)[kMaxT] = reinterpret_cast<int2 (*)[kMaxT]>(queue + qcap);
+    int* flags = reinterpret_cast<int*>(tpos + kPosBufs);
+    int* qfill = flags;
+    int* nsel = flags + 1;
+    int* ovf = flags + 2;
     const int tid = (int)threadIdx.x;
     const int lane = lane_id();
     const int w = uniform(tid >> 6);
-    int32_t* cbuf = reinterpret_cast<int32_t*>(map_smem + map_words + kTab) + w * kCompact;
-    const uint32_t dummy = (uint32_t)map_words - 1u;    // a word past every real id
-    const int64_t stride = gridDim.x;
+    const int clear_vec = map_words >> 2;   // uint4 words of the map
+    const int32_t n32 = (int32_t)n;
+    const int64_t G = gridDim.x;
     int64_t q = blockIdx.x;
     if (q >= nq) return;
+    const int t0 = w / wpl, p0 = w - t0 * wpl;
+    const int dt = kVoteWaves / wpl, dp = kVoteWaves - dt * wpl;
 
-    for (int i = tid; i < ((map_words + kTab) >> 2); i += kVoteBlock)
+    for (int i = tid; i < clear_vec; i += kVoteBlock)
         reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
-    for (int k = 0; k < 2; ++k) {
-        const int64_t qq = q + k * stride;
-        if (qq < nq && tid < T) {
-            const int L = leaf[qq * T + tid];
-            const int b = off[L];
-            tbase[k][tid] = b;
-            tlen[k][tid] = off[L + 1] - b;
+    int Lnext = 0;                            // leaf numbers of the query two ahead
+    if (tid < T) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int64_t qq = q + k * G;
+            if (qq < nq) {
+                const int L = leaf[qq * T + tid];
+                const int b = off[L];
+                tpos[k][tid] = make_int2(b, off[L + 1] - b);
+            }
         }
+        if (q + 2 * G < nq) Lnext = leaf[(q + 2 * G) * T + tid];
     }
-    if (tid < 2) { nsel[tid] = 0; ovf[tid] = 0; }
-    lds_barrier();
+    if (tid == 0) { *qfill = 0; *nsel = 0; *ovf = 0; }
+    __syncthreads();
 
-    int32_t ids[kVoteSlots], nid[kVoteSlots];
-#define MRPT_LOAD_WINDOWS(DST, BUF)                                              \
-    do {                                                                         \
-        int jj = w, uu = 0;                                                      \
-        _Pragma("unroll") for (int s = 0; s < kVoteSlots; ++s) {                 \
-            DST[s] = -1;                                                         \
-            if (jj < T) {                                                        \
-                const int len = uniform(tlen[BUF][jj]);                          \
-                const int e = uu * kWave + lane;                                 \
-                if (e < len) DST[s] = perm[(int64_t)jj * n + tbase[BUF][jj] + e]; \
-                ++uu;                                                            \
-                if (uu * kWave >= len) { uu = 0; jj += kVoteWaves; }             \
-            }                                                                    \
-        }                                                                        \
-    } while (0)
-    MRPT_LOAD_WINDOWS(ids, 0);
+    int32_t ids[S], nid[S];
+    load_windows<S>(ids, tpos[0], perm, n, T, t0, p0, wpl, dt, dp);
     int cur = 0;
     while (true) {
-        const int nxt = cur ^ 1;
-        const int64_t q1 = q + stride, q2 = q + 2 * stride;
-        if (q1 < nq) MRPT_LOAD_WINDOWS(nid, nxt);           // in flight while q is counted
-        int L2 = 0;
-        if (q2 < nq && tid < T) L2 = leaf[q2 * T + tid];     // likewise
+        const int64_t q1 = q + G, q2 = q + 2 * G, q3 = q + 3 * G;
+        const int b1 = cur == kPosBufs - 1 ? 0 : cur + 1;
+        const int b2 = b1 == kPosBufs - 1 ? 0 : b1 + 1;
+        if (q1 < nq) load_windows<S>(nid, tpos[b1], perm, n, T, t0, p0, wpl, dt, dp);
+        int ob = 0, oe = 0, Lnn = 0;
+        if (tid < T) {
+            if (q2 < nq) { ob = off[Lnext]; oe = off[Lnext + 1]; }
+            if (q3 < nq) Lnn = leaf[q3 * T + tid];
+        }
         int32_t* out = s_ids + q * cap;
-        int* my_nsel = &nsel[cur];
-        int pending = 0;                                     // wave-uniform fill of cbuf
+
+        // the windows through the map: first occurrences (v = 1: S) or repeats
 #pragma unroll
-        for (int s0 = 0; s0 < kVoteSlots; s0 += kMapBatch) {
+        for (int s0 = 0; s0 < S; s0 += kMapBatch) {
             uint32_t old[kMapBatch];
 #pragma unroll
             for (int g = 0; g < kMapBatch; ++g) {
-                const int32_t id = ids[s0 + g];
-                const uint32_t word = id >= 0 ? (uint32_t)id >> 5 : dummy;
-                old[g] = atomicOr(&map[word], 1u << (id & 31));
+                const uint32_t id = (uint32_t)ids[s0 + g];
+                old[g] = atomicOr(&map[id >> 5], 1u << (id & 31u));
             }
+            uint64_t m[kMapBatch];
+            int32_t bid[kMapBatch];
 #pragma unroll
             for (int g = 0; g < kMapBatch; ++g) {
                 const int32_t id = ids[s0 + g];
-                const bool seen = id >= 0 && ((old[g] >> (id & 31)) & 1u);
-                if constexpr (!HASH) {
-                    append(id >= 0 && !seen, id, my_nsel, out, cap);
-                } else {
-                    const uint64_t m = __ballot(seen);
-                    if (m) {
-                        const int c = __popcll(m);
-                        if (pending + c > kCompact) {
-                            flush_repeats(cbuf, pending, tab, v, &ovf[cur], my_nsel, out, cap);
-                            pending = 0;
-                        }
-                        if (seen) cbuf[pending + __popcll(m & __lanemask_lt())] = id;
-                        pending += c;
+                const bool seen = (old[g] & (1u << (id & 31))) != 0u;
+                m[g] = __ballot((QUEUE ? seen : !seen) && id < n32);
+                bid[g] = id;
+            }
+            if constexpr (QUEUE) store_batch<kMapBatch>(m, bid, qfill, queue, qcap, ovf);
+            else store_batch<kMapBatch>(m, bid, nsel, out, cap, (int*)nullptr);
+        }
+        lds_barrier();                        // the map pass of q is complete
+        if constexpr (QUEUE) {
+            const int qn = min(*qfill, qcap);
+            for (int i = tid; i < clear_vec; i += kVoteBlock)
+                reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
+            lds_barrier();
+            for (int level = 2; level <= v; ++level) {
+                const bool last = level == v;
+                for (int base = w * kWave; base < qn; base += kVoteBlock) {   // wave-uniform trip count
+                    const int i = base + lane;
+                    const int32_t e = i < qn ? queue[i] : -1;
+                    bool first = false;
+                    if (e >= 0) {
+                        const uint32_t bit = 1u << (e & 31);
+                        first = (atomicOr(&map[(uint32_t)e >> 5], bit) & bit) == 0u;
+                        if (first && !last) queue[i] = ~e;     // blanked: one occurrence fewer
+                    }
+                    if (last) {
+                        const uint64_t m1[1] = {__ballot(first)};
+                        const int32_t e1[1] = {e};
+                        store_batch<1>(m1, e1, nsel, out, cap, (int*)nullptr);
                     }
                 }
+                lds_barrier();
+                // every bit set by this run belongs to a queued id: clear those words
+                for (int i = tid; i < qn; i += kVoteBlock) {
+                    const int32_t e = queue[i];
+                    map[(uint32_t)(e >= 0 ? e : ~e) >> 5] = 0u;
+                }
+                lds_barrier();
             }
         }
-        if constexpr (HASH) flush_repeats(cbuf, pending, tab, v, &ovf[cur], my_nsel, out, cap);
-        lds_barrier();
-        if (q2 < nq && tid < T) {                            // buffer cur held q's positions: free now
-            const int b = off[L2];
-            tbase[cur][tid] = b;
-            tlen[cur][tid] = off[L2 + 1] - b;
+        // buffer b2 last served the query before q, whose windows are loaded
+        if (tid < T && q2 < nq) tpos[b2][tid] = make_int2(ob, oe - ob);
+        if (tid == 0) {
+            s_count[q] = *ovf ? -1 : (*nsel < cap ? *nsel : (int32_t)cap);
+            *qfill = 0;
+            *nsel = 0;
+            *ovf = 0;
         }
-        if (tid == 0) { nsel[nxt] = 0; ovf[nxt] = 0; }
-#pragma unroll
-        for (int s = 0; s < kVoteSlots; ++s) map[ids[s] >= 0 ? (uint32_t)ids[s] >> 5 : dummy] = 0u;
-        if constexpr (HASH) {
-            for (int i = tid; i < (kTab >> 2); i += kVoteBlock)
-                reinterpret_cast<uint4*>(tab)[i] = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (!QUEUE) {
+            for (int i = tid; i < clear_vec; i += kVoteBlock)
+                reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
         }
         lds_barrier();
-        if (tid == 0) s_count[q] = ovf[cur] ? -1 : (nsel[cur] < cap ? nsel[cur] : (int32_t)cap);
         if (q1 >= nq) break;
 #pragma unroll
-        for (int s = 0; s < kVoteSlots; ++s) ids[s] = nid[s];
-        cur = nxt;
+        for (int s = 0; s < S; ++s) ids[s] = nid[s];
+        Lnext = Lnn;
+        cur = b1;
         q = q1;
     }
-#undef MRPT_LOAD_WINDOWS
 }
 
 // debug: F(x; q) of every listed candidate, by binary search of x in each of
@@ -381,8 +432,8 @@ __global__ void copy_counts_kernel(const int32_t* __restrict__ src, int64_t nq, 
     if (i < nq) dst[i] = src[i];
 }
 
-// MRPT_VOTE_KERNEL=0 forces the multi-pass kernel (tuning and tests); the
-// default takes the single-pass kernel whenever it fits
+// MRPT_VOTE_KERNEL=0 forces the multi-pass kernel (tuning and tests); by
+// default the single-pass kernel runs wherever it fits
 bool single_pass_allowed() {
     const char* env = std::getenv("MRPT_VOTE_KERNEL");
     return !(env && *env && std::atoi(env) == 0);
@@ -404,38 +455,52 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
                          int64_t cap, int32_t* s_count, hipStream_t s) {
     constexpr int per = 32 / B;
     const size_t limit = (size_t)std::min(lds_per_block_limit(), 160 * 1024);
-    // multi-pass geometry: ids per pass, a multiple of 4 words' worth of ids
-    constexpr size_t kStaticMulti = kMaxT * 8 + kMaxT * 4 + 16;
-    int64_t chunk = (int64_t)((limit - kStaticMulti) / 16) * 4 * per;
-    const int64_t padded = (ix->n + 4 * per - 1) / (4 * per) * (4 * per);
-    if (chunk > padded) chunk = padded;
-    const int64_t passes = (ix->n + chunk - 1) / chunk;   // same passes, smaller array
-    chunk = ((ix->n + passes - 1) / passes + 4 * per - 1) / (4 * per) * (4 * per);
+    // multi-pass geometry for `fixed` bytes of static LDS: ids per pass, a
+    // multiple of 4 words' worth of ids, and the number of passes
+    auto geometry = [&](size_t fixed, int64_t& chunk, int64_t& passes) {
+        chunk = (int64_t)((limit - fixed) / 16) * 4 * per;
+        const int64_t padded = (ix->n + 4 * per - 1) / (4 * per) * (4 * per);
+        if (chunk > padded) chunk = padded;
+        passes = (ix->n + chunk - 1) / chunk;   // same passes, smaller array
+        chunk = ((ix->n + passes - 1) / passes + 4 * per - 1) / (4 * per) * (4 * per);
+    };
+    int64_t chunk = 0, passes = 0;
+    geometry(kMaxT * 8 + kMaxT * 4 + 16, chunk, passes);
     const size_t multi_lds = (size_t)(chunk / per) * 4;
 
-    // single-pass geometry: map words (with one spare word) + table + buffers
-    const bool hash = v >= 2;
-    const int64_t map_words = ((ix->n + 31) / 32 + 1 + 3) / 4 * 4;   // the last word is never a real id's
-    const size_t map_lds = (size_t)map_words * 4 + (hash ? (size_t)kHashEntries * 4 + kVoteWaves * kCompact * 4 : 0);
-    constexpr size_t kStaticMap = 2 * kMaxT * 4 * 2 + 16;
-    const int64_t windows = (int64_t)((ix->T + kVoteWaves - 1) / kVoteWaves) * ((ix->max_leaf + kWave - 1) / kWave);
-    const bool single = single_pass_allowed() && map_lds + kStaticMap <= limit && windows <= kVoteSlots &&
-                        ix->n < (int64_t(1) << 24);
+    // single-pass geometry: map words (ids 0 .. n + 2047: real ids, then the
+    // empty lanes' ids n + 32 lane + s), the repeat queue in what LDS has left
+    const bool queued = v >= 2;   // repeats are queued and rerun
+    const int wpl = (ix->max_leaf + kWave - 1) / kWave;
+    const int64_t slots = ((int64_t)ix->T * wpl + kVoteWaves - 1) / kVoteWaves;
+    const int64_t map_words = ((ix->n + kVoteSlots * kWave) / 32 + 1 + 3) / 4 * 4;
+    constexpr size_t kTail = sizeof(int2) * kPosBufs * kMaxT + 16;        // leaf positions, flags
+    const int64_t room = ((int64_t)limit - (int64_t)kTail - map_words * 4) / 4;
+    const int64_t qcap = queued ? std::min<int64_t>(room, (int64_t)ix->T * ix->max_leaf) / 4 * 4 : 0;
+    const bool single = single_pass_allowed() && slots <= kVoteSlots && ix->n < (int64_t(1) << 24) &&
+                        room >= 0 && (!queued || qcap >= 1024);
     if (single) {
+        const size_t lds = (size_t)(map_words + qcap) * 4 + kTail;
         const int64_t grid = std::min<int64_t>(nq, device_cus());
-#define MRPT_MAP(H)                                                                                               \
-    do {                                                                                                          \
-        (void)hipFuncSetAttribute((const void*)vote_map_kernel<H>, hipFuncAttributeMaxDynamicSharedMemorySize,     \
-                                  (int)map_lds);                                                                  \
-        hipLaunchKernelGGL(vote_map_kernel<H>, dim3((unsigned)grid), dim3(kVoteBlock), map_lds, s, leaf, ix->perm, \
-                           ix->off, ix->n, ix->T, v, nq, (int32_t)map_words, s_ids, cap, s_count);               \
+#define MRPT_MAP(SS, H)                                                                                          \
+    do {                                                                                                         \
+        (void)hipFuncSetAttribute((const void*)vote_map_kernel<SS, H>,                                           \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                         \
+        hipLaunchKernelGGL((vote_map_kernel<SS, H>), dim3((unsigned)grid), dim3(kVoteBlock), lds, s, leaf,       \
+                           ix->perm, ix->off, ix->n, ix->T, wpl, v, nq, (int32_t)map_words, (int32_t)qcap,       \
+                           s_ids, cap, s_count);                                                                 \
     } while (0)
-        if (hash) MRPT_MAP(true);
-        else MRPT_MAP(false);
+        if (slots <= 8) {
+            if (queued) MRPT_MAP(8, true);
+            else MRPT_MAP(8, false);
+        } else {
+            if (queued) MRPT_MAP(kVoteSlots, true);
+            else MRPT_MAP(kVoteSlots, false);
+        }
 #undef MRPT_MAP
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess || !hash) return e;
-        // queries whose table overflowed (count -1) are counted again, multi-pass
+        if (e != hipSuccess || !queued) return e;
+        // queries whose queue overflowed (count -1) are counted again, multi-pass
     }
     (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)multi_lds);
