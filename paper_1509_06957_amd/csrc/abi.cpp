@@ -283,7 +283,9 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
     if ((e = dev_alloc(&ix->val, std::max<size_t>(nnz, 1), &ix->device_bytes)) != hipSuccess) return oom(e, "val");
     if ((e = dev_alloc(&ix->splits, std::max<size_t>((size_t)T * nsplit, 1), &ix->device_bytes)) != hipSuccess)
         return oom(e, "splits");
-    if ((e = dev_alloc(&ix->perm, (size_t)T * (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "perm");
+    ix->perm_ld = n + kPermPad;
+    if ((e = dev_alloc(&ix->perm, (size_t)T * (size_t)ix->perm_ld, &ix->device_bytes)) != hipSuccess)
+        return oom(e, "perm");
     if ((e = dev_alloc(&ix->off, (size_t)ix->nleaf + 1, &ix->device_bytes)) != hipSuccess) return oom(e, "offsets");
     if ((e = dev_alloc(&ix->Xb, nd, &ix->device_bytes)) != hipSuccess) return oom(e, "bfloat16 data");
     if ((e = dev_alloc(&ix->xnorm, (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "norms");
@@ -297,7 +299,16 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
     if (nsplit)
         MRPT_HIP_TRY(hipMemcpy(ix->splits, trees.splits.data(), (size_t)T * nsplit * sizeof(float),
                                hipMemcpyHostToDevice));
-    MRPT_HIP_TRY(hipMemcpy(ix->perm, trees.perm.data(), (size_t)T * n * sizeof(int32_t), hipMemcpyHostToDevice));
+    MRPT_HIP_TRY(hipMemcpy2D(ix->perm, (size_t)ix->perm_ld * sizeof(int32_t), trees.perm.data(),
+                             (size_t)n * sizeof(int32_t), (size_t)n * sizeof(int32_t), (size_t)T,
+                             hipMemcpyHostToDevice));
+    {
+        std::vector<int32_t> pad((size_t)T * kPermPad);
+        for (size_t i = 0; i < pad.size(); ++i) pad[i] = (int32_t)(n + (int64_t)(i % kPermPad));
+        MRPT_HIP_TRY(hipMemcpy2D(ix->perm + n, (size_t)ix->perm_ld * sizeof(int32_t), pad.data(),
+                                 (size_t)kPermPad * sizeof(int32_t), (size_t)kPermPad * sizeof(int32_t), (size_t)T,
+                                 hipMemcpyHostToDevice));
+    }
     std::vector<int32_t> off32(ix->h_off.begin(), ix->h_off.end());
     MRPT_HIP_TRY(hipMemcpy(ix->off, off32.data(), off32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MRPT_HIP_TRY(launch_quantize_bf16(ix->X, n, d, ix->Xb, ix->xnorm, nullptr));
@@ -361,7 +372,7 @@ mrpt_status mrpt_export_tree(const mrpt_index* ix, int32_t t, float* splits, int
         MRPT_HIP_TRY(hipMemcpy(splits, ix->splits + (size_t)t * nsplit, nsplit * sizeof(float),
                                hipMemcpyDeviceToHost));
     if (perm)
-        MRPT_HIP_TRY(hipMemcpy(perm, ix->perm + (size_t)t * ix->n, (size_t)ix->n * sizeof(int32_t),
+        MRPT_HIP_TRY(hipMemcpy(perm, ix->perm + (size_t)t * ix->perm_ld, (size_t)ix->n * sizeof(int32_t),
                                hipMemcpyDeviceToHost));
     return MRPT_OK;
 }

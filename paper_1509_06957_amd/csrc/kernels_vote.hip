@@ -76,15 +76,16 @@ __device__ __forceinline__ bool count_id(uint32_t* cnt, uint32_t rel, int v) {
     }
 }
 
-// One workgroup per query.  Counters of B bits per id over passes of `chunk`
-// ids; after a pass only the touched words are reset.  Windows beyond the
+// One workgroup per query (queries blockIdx.x, + gridDim.x, ...).  Counters
+// of B bits per id over passes of `chunk` ids; after a pass only the touched
+// words are reset.  Windows beyond the
 // register budget are re-read in every pass (the array is then cleared in
 // full).  With redo_only set, only queries whose count is -1 are processed.
 template <int B>
 __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restrict__ leaf,
                                                           const int32_t* __restrict__ perm,
-                                                          const int32_t* __restrict__ off, int64_t n,
-                                                          int32_t T, int32_t v, int32_t chunk,
+                                                          const int32_t* __restrict__ off, int64_t n, int64_t ld,
+                                                          int32_t T, int32_t v, int64_t nq, int32_t chunk,
                                                           int32_t* __restrict__ s_ids, int64_t cap,
                                                           int32_t* __restrict__ s_count, int32_t redo_only) {
     extern __shared__ uint32_t vote_cnt[];   // chunk * B / 32 words
@@ -96,14 +97,14 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
     const int tid = (int)threadIdx.x;
     const int lane = lane_id();
     const int w = uniform(tid >> 6);
-    const int64_t q = blockIdx.x;
     const int words = chunk / per;
-    if (redo_only && s_count[q] >= 0) return;
+    for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    if (redo_only && s_count[q] >= 0) continue;
 
     if (tid < T) {
         const int L = leaf[q * T + tid];
         const int b = off[L];
-        tbase[tid] = (int64_t)tid * n + b;
+        tbase[tid] = (int64_t)tid * ld + b;
         tlen[tid] = off[L + 1] - b;
     }
     if (tid == 0) { nsel = 0; spill = 0; }
@@ -176,6 +177,8 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
     }
     __syncthreads();
     if (tid == 0) s_count[q] = nsel < cap ? nsel : (int32_t)cap;
+    __syncthreads();                        // shared state is reused by the next query
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -190,17 +193,19 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
 // every id, so after j runs an id with F = f has f - 1 - j occurrences left,
 // and the last run elects the first remaining occurrence of every id, i.e.
 // exactly the ids with F >= v, each once.  The queue is a few thousand
-// entries, so these runs use all 1024 threads and cost little.
+// entries, so these runs use all 1024 threads and cost little.  A query whose
+// queue overflows gets count -1 and is recounted by the multi-pass kernel.
 //
 // The workgroup is persistent over the queries g, g + G, ...: while query q
 // is counted, the leaf windows of the next query (registers), the leaf
 // offsets of the one after and the leaf numbers of the third are in flight.
 // A query's T * wpl windows (tree u / wpl, 64-id part u % wpl) are dealt
-// round-robin over the 16 waves.  Empty lanes carry the id n + 32 lane + s
-// (s: slot), which is never queued or elected; its map bit lies in spare
-// words past the ids, a different word for every lane of a slot.  A query
-// whose queue overflows gets count -1 and is recounted by the multi-pass
-// kernel.
+// round-robin over the 16 waves: slot s of wave w is window w + 16 s.  Every
+// slot issues one load per lane with no branch around it (so the compiler
+// can count the loads in flight): a lane beyond its leaf, or a slot beyond
+// the last tree, reads the padding entry n + 32 lane + s of perm row 0, which
+// holds that value; such ids are never queued or elected, and their map bits
+// lie in spare words past the ids, a different word for every lane of a slot.
 constexpr int kMapBatch = 4;         // slots whose map updates are issued together
 constexpr int kPosBufs = 3;          // leaf position buffers of the pipeline
 
@@ -209,12 +214,12 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m, uint32_t base) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
 }
 
-// wave-aggregated store of NB ballots (slot g selected the lanes of m[g])
-// at consecutive places of dst reserved with one LDS atomic on *fill; places
-// at or beyond `limit` are dropped and reported through *ovf
-template <int NB, typename Out>
-__device__ __forceinline__ void store_batch(const uint64_t (&m)[NB], const int32_t (&id)[NB], int* fill, Out* dst,
-                                            int64_t limit, int* ovf) {
+// wave-aggregated store of NB ballots (slot g selected the lanes of m[g]) at
+// consecutive places of out, reserved with one LDS atomic on *fill; places at
+// or beyond cap are dropped and reported through *ovf (when given)
+template <int NB>
+__device__ __forceinline__ void append_batch(const uint64_t (&m)[NB], const int32_t (&id)[NB], int* fill,
+                                             int32_t* out, int64_t cap, int* ovf = nullptr) {
     int tot = 0;
 #pragma unroll
     for (int g = 0; g < NB; ++g) tot += __popcll(m[g]);
@@ -222,58 +227,61 @@ __device__ __forceinline__ void store_batch(const uint64_t (&m)[NB], const int32
     int base = 0;
     if (lane_id() == 0) {
         base = atomicAdd(fill, tot);
-        if (ovf && (int64_t)base + tot > limit) *ovf = 1;
+        if (ovf && (int64_t)base + tot > cap) *ovf = 1;
     }
     base = __builtin_amdgcn_readfirstlane(base);
 #pragma unroll
     for (int g = 0; g < NB; ++g) {
         if ((m[g] >> lane_id()) & 1ull) {
             const uint32_t at = rank_below(m[g], (uint32_t)base);
-            if ((int64_t)at < limit) dst[at] = id[g];
+            if ((int64_t)at < cap) out[at] = id[g];
         }
         base += __popcll(m[g]);
     }
 }
 
+// Per-slot window descriptors of wave w, one slot per lane (lanes >= S
+// unused): row = tree * ld + 64 * part (-1 past the last tree) and
+// tp = tree | 64 * part << 8.  Computed once per kernel; read back per slot
+// with readlane, so the per-query address work is a few scalar adds.
+__device__ __forceinline__ void slot_table(int w, int T, int wpl, int64_t ld, int& row, int& tp) {
+    const int u = w + kVoteWaves * lane_id();
+    const int t = u / wpl, part = u - t * wpl;
+    row = t < T ? (int)((int64_t)t * ld) + part * kWave : -1;
+    tp = t < T ? (t | (part * kWave) << 8) : 0;
+}
+
 template <int S>
 __device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int2* __restrict__ tpos,
-                                             const int32_t* __restrict__ perm, int64_t n, int T, int t0,
-                                             int p0, int wpl, int dt, int dp) {
+                                             const int32_t* __restrict__ perm, int32_t n32, int slot_row,
+                                             int slot_tp) {
     const int lane = lane_id();
-    int t = t0, part = p0;
-    // opaque to the optimizer: the per-slot addresses are the same for every
-    // query, and hoisting them out of the query loop would hold 2*S scalar
-    // registers for the whole kernel (spilled); they cost a few scalar ops here
-    asm volatile("" : "+s"(t), "+s"(part));
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        dst[s] = (int32_t)n + lane * 32 + s;
-        // keeps the S registers separate: formed as one vector (base + 0..S-1)
-        // they are allocated as a single tuple and spilled wholesale
-        asm volatile("" : "+v"(dst[s]));
-        if (t < T) {
-            const int2 bl = tpos[t];
-            // wave-uniform row base (scalar registers) + 32-bit lane offset
-            const int32_t* row = perm + (int64_t)t * n + uniform(bl.x) + part * kWave;
-            if (part * kWave + lane < uniform(bl.y)) dst[s] = row[(uint32_t)lane];
-        }
-        t += dt;
-        part += dp;
-        if (part >= wpl) { part -= wpl; ++t; }
+        const int row = __builtin_amdgcn_readlane(slot_row, s);
+        const int tp = __builtin_amdgcn_readlane(slot_tp, s);
+        const int2 bl = tpos[tp & 255];
+        const int avail = row < 0 ? 0 : uniform(bl.y) - (tp >> 8);   // ids of this window
+        int idx = n32 + lane * 32 + s;
+        // keeps the S padding offsets separate: formed as one vector (base +
+        // 0..S-1) they are allocated as a single register tuple and spilled
+        asm volatile("" : "+v"(idx));
+        if (lane < avail) idx = row + uniform(bl.x) + lane;
+        dst[s] = perm[(uint32_t)idx];
     }
 }
 
-// LDS: map [map_words] | queue [qcap] | leaf positions [kPosBufs][kMaxT] (int2)
-//      | qfill, nsel, ovf
+// LDS: map [map_words] | queue [qcap] | leaf positions [kPosBufs][kMaxT]
+//      (int2) | qfill, nsel, ovf
 template <int S, bool QUEUE>
 __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __restrict__ leaf,
                                                               const int32_t* __restrict__ perm,
                                                               const int32_t* __restrict__ off, int64_t n,
-                                                              int32_t T, int32_t wpl, int32_t v, int64_t nq,
-                                                              int32_t map_words, int32_t qcap,
+                                                              int64_t ld, int32_t T, int32_t wpl, int32_t v,
+                                                              int64_t nq, int32_t map_words, int32_t qcap,
                                                               int32_t* __restrict__ s_ids, int64_t cap,
                                                               int32_t* __restrict__ s_count) {
-    extern __shared__ uint32_t map_smem[];
+    extern __shared__ __align__(16) uint32_t map_smem[];
     uint32_t* map = map_smem;
     int32_t* queue = reinterpret_cast<int32_t*>(map_smem + map_words);
     int2 (*tpos)[kMaxT] = reinterpret_cast<int2 (*)[kMaxT]>(queue + qcap);
@@ -289,21 +297,25 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     const int64_t G = gridDim.x;
     int64_t q = blockIdx.x;
     if (q >= nq) return;
-    const int t0 = w / wpl, p0 = w - t0 * wpl;
-    const int dt = kVoteWaves / wpl, dp = kVoteWaves - dt * wpl;
+    int slot_row, slot_tp;
+    slot_table(w, T, wpl, ld, slot_row, slot_tp);
 
     for (int i = tid; i < clear_vec; i += kVoteBlock)
         reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
     int Lnext = 0;                            // leaf numbers of the query two ahead
     if (tid < T) {
+        // every buffer holds in-range positions (empty ones for absent
+        // queries): windows are loaded without checking that the query exists
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < kPosBufs; ++k) {
             const int64_t qq = q + k * G;
-            if (qq < nq) {
+            int2 p = make_int2(0, 0);
+            if (k < 2 && qq < nq) {
                 const int L = leaf[qq * T + tid];
                 const int b = off[L];
-                tpos[k][tid] = make_int2(b, off[L + 1] - b);
+                p = make_int2(b, off[L + 1] - b);
             }
+            tpos[k][tid] = p;
         }
         if (q + 2 * G < nq) Lnext = leaf[(q + 2 * G) * T + tid];
     }
@@ -311,13 +323,15 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     __syncthreads();
 
     int32_t ids[S], nid[S];
-    load_windows<S>(ids, tpos[0], perm, n, T, t0, p0, wpl, dt, dp);
+    load_windows<S>(ids, tpos[0], perm, n32, slot_row, slot_tp);
     int cur = 0;
     while (true) {
         const int64_t q1 = q + G, q2 = q + 2 * G, q3 = q + 3 * G;
         const int b1 = cur == kPosBufs - 1 ? 0 : cur + 1;
         const int b2 = b1 == kPosBufs - 1 ? 0 : b1 + 1;
-        if (q1 < nq) load_windows<S>(nid, tpos[b1], perm, n, T, t0, p0, wpl, dt, dp);
+        // (past the last query the buffer holds stale or empty positions: the
+        // loads stay in range and their values are never used)
+        load_windows<S>(nid, tpos[b1], perm, n32, slot_row, slot_tp);
         int ob = 0, oe = 0, Lnn = 0;
         if (tid < T) {
             if (q2 < nq) { ob = off[Lnext]; oe = off[Lnext + 1]; }
@@ -343,8 +357,8 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
                 m[g] = __ballot((QUEUE ? seen : !seen) && id < n32);
                 bid[g] = id;
             }
-            if constexpr (QUEUE) store_batch<kMapBatch>(m, bid, qfill, queue, qcap, ovf);
-            else store_batch<kMapBatch>(m, bid, nsel, out, cap, (int*)nullptr);
+            if constexpr (QUEUE) append_batch<kMapBatch>(m, bid, qfill, queue, qcap, ovf);
+            else append_batch<kMapBatch>(m, bid, nsel, out, cap);
         }
         lds_barrier();                        // the map pass of q is complete
         if constexpr (QUEUE) {
@@ -366,7 +380,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
                     if (last) {
                         const uint64_t m1[1] = {__ballot(first)};
                         const int32_t e1[1] = {e};
-                        store_batch<1>(m1, e1, nsel, out, cap, (int*)nullptr);
+                        append_batch<1>(m1, e1, nsel, out, cap);
                     }
                 }
                 lds_barrier();
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
 // the query's T leaf lists (independent of the counting kernels)
 __global__ __launch_bounds__(256) void vote_counts_kernel(const int32_t* __restrict__ leaf,
                                                           const int32_t* __restrict__ perm,
-                                                          const int32_t* __restrict__ off, int64_t n,
+                                                          const int32_t* __restrict__ off, int64_t ld,
                                                           int32_t T, const int32_t* __restrict__ s_ids,
                                                           int64_t cap, const int32_t* __restrict__ s_count,
                                                           uint8_t* __restrict__ s_votes) {
@@ -415,7 +429,7 @@ __global__ __launch_bounds__(256) void vote_counts_kernel(const int32_t* __restr
         int F = 0;
         for (int t = 0; t < T; ++t) {
             const int L = leaf[q * T + t];
-            const int32_t* lst = perm + (int64_t)t * n;
+            const int32_t* lst = perm + (int64_t)t * ld;
             int lo = off[L], hi = off[L + 1];
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
@@ -478,7 +492,8 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     const int64_t room = ((int64_t)limit - (int64_t)kTail - map_words * 4) / 4;
     const int64_t qcap = queued ? std::min<int64_t>(room, (int64_t)ix->T * ix->max_leaf) / 4 * 4 : 0;
     const bool single = single_pass_allowed() && slots <= kVoteSlots && ix->n < (int64_t(1) << 24) &&
-                        room >= 0 && (!queued || qcap >= 1024);
+                        (int64_t)ix->T * ix->perm_ld < (int64_t(1) << 31) && room >= 0 &&
+                        (!queued || qcap >= 1024);
     if (single) {
         const size_t lds = (size_t)(map_words + qcap) * 4 + kTail;
         const int64_t grid = std::min<int64_t>(nq, device_cus());
@@ -487,7 +502,8 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         (void)hipFuncSetAttribute((const void*)vote_map_kernel<SS, H>,                                           \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                         \
         hipLaunchKernelGGL((vote_map_kernel<SS, H>), dim3((unsigned)grid), dim3(kVoteBlock), lds, s, leaf,       \
-                           ix->perm, ix->off, ix->n, ix->T, wpl, v, nq, (int32_t)map_words, (int32_t)qcap,       \
+                           ix->perm, ix->off, ix->n, ix->perm_ld, ix->T, wpl, v, nq, (int32_t)map_words,         \
+                           (int32_t)qcap,                                                                        \
                            s_ids, cap, s_count);                                                                 \
     } while (0)
         if (slots <= 8) {
@@ -504,8 +520,10 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     }
     (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)multi_lds);
-    hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)nq), dim3(kVoteBlock), multi_lds, s, leaf, ix->perm, ix->off,
-                       ix->n, ix->T, v, (int32_t)chunk, s_ids, cap, s_count, single ? 1 : 0);
+    // a recount visits every query but counts few: a small grid loops over them
+    const int64_t grid = single ? std::min<int64_t>(nq, 4 * device_cus()) : nq;
+    hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)grid), dim3(kVoteBlock), multi_lds, s, leaf, ix->perm, ix->off,
+                       ix->n, ix->perm_ld, ix->T, v, nq, (int32_t)chunk, s_ids, cap, s_count, single ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -523,7 +541,7 @@ hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, in
 hipError_t launch_vote_counts(const mrpt_index* ix, const int32_t* leaf, int64_t nq, const int32_t* s_ids,
                               int64_t cap, const int32_t* s_count, uint8_t* s_votes, hipStream_t s) {
     if (nq == 0) return hipSuccess;
-    hipLaunchKernelGGL(vote_counts_kernel, dim3((unsigned)nq), dim3(256), 0, s, leaf, ix->perm, ix->off, ix->n,
+    hipLaunchKernelGGL(vote_counts_kernel, dim3((unsigned)nq), dim3(256), 0, s, leaf, ix->perm, ix->off, ix->perm_ld,
                        ix->T, s_ids, cap, s_count, s_votes);
     return hipGetLastError();
 }

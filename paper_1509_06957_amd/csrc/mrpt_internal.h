@@ -35,6 +35,10 @@ constexpr int kMaxT = 255;          // 8-bit vote counters
 constexpr int kMaxDepth = 24;
 constexpr int kMaxK = 1024;
 constexpr int kMaxRerank = 512;     // rerank_factor * k
+// Each tree's row of perm is padded with kPermPad entries holding n, n + 1,
+// ...: a vote kernel reads an empty lane of a window from there instead of
+// branching around the load, so every slot issues exactly one load.
+constexpr int kPermPad = 2048;
 
 // ---------------------------------------------------------------- index
 struct DeviceBuf {
@@ -81,7 +85,8 @@ struct mrpt_index {
     int32_t* col = nullptr;      // nnz
     float* val = nullptr;        // nnz
     float* splits = nullptr;     // T x (2^depth - 1)
-    int32_t* perm = nullptr;     // T x n
+    int32_t* perm = nullptr;     // T rows of perm_ld: the tree's ids, then kPermPad entries n + j
+    int64_t perm_ld = 0;         // n + kPermPad
     int32_t* off = nullptr;      // 2^depth + 1
     int64_t device_bytes = 0;
 
