@@ -262,11 +262,12 @@ __device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int2* __re
         const int tp = __builtin_amdgcn_readlane(slot_tp, s);
         const int2 bl = tpos[tp & 255];
         const int avail = row < 0 ? 0 : uniform(bl.y) - (tp >> 8);   // ids of this window
-        int idx = n32 + lane * 32 + s;
+        const int first = row + uniform(bl.x);
+        int pad = n32 + lane * 32 + s;
         // keeps the S padding offsets separate: formed as one vector (base +
         // 0..S-1) they are allocated as a single register tuple and spilled
-        asm volatile("" : "+v"(idx));
-        if (lane < avail) idx = row + uniform(bl.x) + lane;
+        asm volatile("" : "+v"(pad));
+        const int idx = lane < avail ? first + lane : pad;
         dst[s] = perm[(uint32_t)idx];
     }
 }
@@ -509,6 +510,12 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         if (slots <= 8) {
             if (queued) MRPT_MAP(8, true);
             else MRPT_MAP(8, false);
+        } else if (slots <= 16) {
+            if (queued) MRPT_MAP(16, true);
+            else MRPT_MAP(16, false);
+        } else if (slots <= 28) {
+            if (queued) MRPT_MAP(28, true);
+            else MRPT_MAP(28, false);
         } else {
             if (queued) MRPT_MAP(kVoteSlots, true);
             else MRPT_MAP(kVoteSlots, false);

@@ -289,7 +289,7 @@ def test_vote_kernel_variants_agree(kernel, monkeypatch):
         monkeypatch.setenv("MRPT_VOTE_KERNEL", kernel)
     for n, d, T, depth, v in ((6000, 24, 20, 5, 1), (7000, 16, 12, 6, 3), (3000, 8, 9, 4, 5), (2500, 8, 140, 3, 20),
                               (150000, 8, 10, 7, 2), (140000, 8, 70, 9, 1), (40000, 8, 20, 1, 2),
-                              (1_100_000, 4, 30, 12, 5), (200_000, 4, 40, 10, 17)):
+                              (1_100_000, 4, 30, 12, 5), (200_000, 4, 40, 10, 17), (200_000, 4, 120, 10, 4)):
         X, Q = _small(n, d, T, depth, seed=n + T, nq=700)
         orc = oracle.build_index(X, T, depth, 0.5, 3)
         g = build(X, T, depth, 0.5, 3)
