@@ -188,11 +188,15 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
 // id occurrence.  Reading a query's windows through the map leaves the first
 // occurrence of every id in the map and queues each repeated occurrence
 // (an id with F = f is queued f - 1 times).  For v = 1 the first occurrences
-// are S.  For v >= 2 the queue is run through the cleared map v - 1 more
-// times: each of the first v - 2 runs blanks the first queued occurrence of
-// every id, so after j runs an id with F = f has f - 1 - j occurrences left,
-// and the last run elects the first remaining occurrence of every id, i.e.
-// exactly the ids with F >= v, each once.  The queue is a few thousand
+// are S.  For v >= 2 the queue is run through the map v - 1 more times:
+// each of the first v - 2 runs blanks the first queued occurrence of every
+// id, so after j runs an id with F = f has f - 1 - j occurrences left, and
+// the last run elects the first remaining occurrence of every id, i.e.
+// exactly the ids with F >= v, each once.  No clear is needed between runs:
+// after the window pass every queued id's bit is set, so the first run finds
+// first occurrences by clearing bits (atomic AND), the next by setting them
+// again (atomic OR), and so on, since the ids a run examines are exactly ids
+// the previous run examined (their bits all flipped by it).  The queue is a few thousand
 // entries, so these runs use all 1024 threads and cost little.  A query whose
 // queue overflows gets count -1 and is recounted by the multi-pass kernel.
 //
@@ -364,18 +368,17 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         lds_barrier();                        // the map pass of q is complete
         if constexpr (QUEUE) {
             const int qn = min(*qfill, qcap);
-            for (int i = tid; i < clear_vec; i += kVoteBlock)
-                reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
-            lds_barrier();
             for (int level = 2; level <= v; ++level) {
                 const bool last = level == v;
+                const bool clearing = (level & 1) == 0;   // runs 2, 4, ...: bits start set
                 for (int base = w * kWave; base < qn; base += kVoteBlock) {   // wave-uniform trip count
                     const int i = base + lane;
                     const int32_t e = i < qn ? queue[i] : -1;
                     bool first = false;
                     if (e >= 0) {
                         const uint32_t bit = 1u << (e & 31);
-                        first = (atomicOr(&map[(uint32_t)e >> 5], bit) & bit) == 0u;
+                        if (clearing) first = (atomicAnd(&map[(uint32_t)e >> 5], ~bit) & bit) != 0u;
+                        else first = (atomicOr(&map[(uint32_t)e >> 5], bit) & bit) == 0u;
                         if (first && !last) queue[i] = ~e;     // blanked: one occurrence fewer
                     }
                     if (last) {
@@ -383,12 +386,6 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
                         const int32_t e1[1] = {e};
                         append_batch<1>(m1, e1, nsel, out, cap);
                     }
-                }
-                lds_barrier();
-                // every bit set by this run belongs to a queued id: clear those words
-                for (int i = tid; i < qn; i += kVoteBlock) {
-                    const int32_t e = queue[i];
-                    map[(uint32_t)(e >= 0 ? e : ~e) >> 5] = 0u;
                 }
                 lds_barrier();
             }
@@ -401,10 +398,8 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
             *nsel = 0;
             *ovf = 0;
         }
-        if constexpr (!QUEUE) {
-            for (int i = tid; i < clear_vec; i += kVoteBlock)
-                reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
-        }
+        for (int i = tid; i < clear_vec; i += kVoteBlock)
+            reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
         lds_barrier();
         if (q1 >= nq) break;
 #pragma unroll
