@@ -17,9 +17,13 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 // dist_fp32: one workgroup (4 waves) per query.  A group of G lanes holds a
 // candidate row as NV float4 per lane; G = 32 for d = 128 (two rows per wave
-// per load), U rows per group are in flight.  Each group's squared distance
-// (direct differences, per-lane fused accumulation, butterfly reduction) is
-// offered to the wave's sorted top-k list; the 4 lists are merged by rank.
+// per load).  Each step a wave gathers U rows per group (8 float4 per lane,
+// 8 KB per wave in flight) while the candidate ids of the next step are
+// already loaded; every load is issued unconditionally (clamped addresses,
+// masked afterwards), so the compiler can count them in flight.  Each group's
+// squared distance (direct differences, per-lane fused accumulation,
+// butterfly reduction) is offered to the wave's sorted top-k list; the 4
+// lists are merged by rank.
 // ---------------------------------------------------------------------------
 constexpr int kDistWaves = 4;
 
@@ -31,7 +35,7 @@ __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict_
                                                         int32_t* __restrict__ out_idx,
                                                         float* __restrict__ out_dist) {
     constexpr int GPW = kWave / G;
-    constexpr int U = (GPW * NV >= 4) ? 4 : (8 / (GPW * NV) > 0 ? 8 / (GPW * NV) : 1);
+    constexpr int U = 8 / NV;
     __shared__ float md[kDistWaves][kWave * R];
     __shared__ int32_t mi[kDistWaves][kWave * R];
     const int lane = lane_id();
@@ -57,13 +61,19 @@ __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict_
     top.get(k - 1, tau_d, tau_i);
 
     constexpr int kStep = kDistWaves * GPW * U;
+    // candidate slot of (step base b, row u) for this group; ids past ns read
+    // slot 0 (any in-range slot) and are marked -1 after the load
+    auto slot = [&](int b, int u) { return b + (u * kDistWaves + w) * GPW + g; };
+    int32_t craw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int ci = slot(0, u);
+        craw[u] = S[ci < ns ? ci : 0];
+    }
     for (int b0 = 0; b0 < ns; b0 += kStep) {
         int32_t cid[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int ci = b0 + (u * kDistWaves + w) * GPW + g;
-            cid[u] = ci < ns ? S[ci] : -1;
-        }
+        for (int u = 0; u < U; ++u) cid[u] = slot(b0, u) < ns ? craw[u] : -1;
         float4 xv[U][NV];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -71,8 +81,14 @@ __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict_
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 const int vi = gl + i * G;
-                xv[u][i] = (cid[u] >= 0 && vi < nvec) ? xr[vi] : qv[i];
+                xv[u][i] = xr[vi < nvec ? vi : 0];
             }
+        }
+        // ids of the next step, in flight while this step's rows arrive
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ci = slot(b0 + kStep, u);
+            craw[u] = S[ci < ns ? ci : 0];
         }
         float s[U];
 #pragma unroll
@@ -80,8 +96,10 @@ __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict_
             float a = 0.0f;
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
-                const float dx = qv[i].x - xv[u][i].x, dy = qv[i].y - xv[u][i].y;
-                const float dz = qv[i].z - xv[u][i].z, dw = qv[i].w - xv[u][i].w;
+                const bool in = gl + i * G < nvec;
+                const float4 x = xv[u][i];
+                const float dx = in ? qv[i].x - x.x : 0.f, dy = in ? qv[i].y - x.y : 0.f;
+                const float dz = in ? qv[i].z - x.z : 0.f, dw = in ? qv[i].w - x.w : 0.f;
                 a = __builtin_fmaf(dx, dx, a);
                 a = __builtin_fmaf(dy, dy, a);
                 a = __builtin_fmaf(dz, dz, a);
