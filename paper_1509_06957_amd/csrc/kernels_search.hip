@@ -215,7 +215,12 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
                                                         int32_t* __restrict__ out_idx,
                                                         float* __restrict__ out_dist) {
     constexpr int GPW = kWave / GB;
-    constexpr int U = (GPW * NVB >= 4) ? 4 : (8 / (GPW * NVB) > 0 ? 8 / (GPW * NVB) : 1);
+    constexpr int U = 8 / NVB;
+    // phase 2 reads float32 rows as the fp32 kernel does: G2 lanes x NV2 float4
+    constexpr int G2 = GB <= 32 ? 2 * GB : 64;
+    constexpr int NV2 = GB <= 32 ? NVB : 2 * NVB;
+    constexpr int GPW2 = kWave / G2;
+    constexpr int U2 = 8 / NV2;
     __shared__ float md[kDistWaves][kWave * RB];
     __shared__ int32_t mi[kDistWaves][kWave * RB];
     __shared__ int32_t cand[kMaxRerank];      // phase-1 survivors in prefilter rank order
@@ -224,7 +229,7 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
     __shared__ int32_t order[kMaxRerank];     // rank by (d32, id) -> candidate slot
     __shared__ int32_t final_slot[kMaxK];
     __shared__ int win_lo, win_hi;
-    __shared__ float qs[1024 + 64];           // query (float32) for phases 2-3 when d <= 1024
+    __shared__ __align__(16) float qs[1024 + 64];   // query (float32) for phases 2-3, d <= 1024
 
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
@@ -257,14 +262,20 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
     int32_t tau_i;
     top.get(kp - 1, tau_d, tau_i);
 
+    // as in dist_fp32: the next step's candidate ids are loaded while this
+    // step's rows arrive, and every load is unconditional (clamped, masked)
     constexpr int kStep = kDistWaves * GPW * U;
+    auto slot = [&](int b, int u) { return b + (u * kDistWaves + w) * GPW + g; };
+    int32_t craw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int ci = slot(0, u);
+        craw[u] = S[ci < ns ? ci : 0];
+    }
     for (int b0 = 0; b0 < ns; b0 += kStep) {
         int32_t cid[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int ci = b0 + (u * kDistWaves + w) * GPW + g;
-            cid[u] = ci < ns ? S[ci] : -1;
-        }
+        for (int u = 0; u < U; ++u) cid[u] = slot(b0, u) < ns ? craw[u] : -1;
         uint4 xv[U][NVB];
         float xn[U];
 #pragma unroll
@@ -274,9 +285,14 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
 #pragma unroll
             for (int i = 0; i < NVB; ++i) {
                 const int vi = gl + i * GB;
-                xv[u][i] = (cid[u] >= 0 && vi < nv8) ? xr[vi] : make_uint4(0u, 0u, 0u, 0u);
+                xv[u][i] = xr[vi < nv8 ? vi : 0];
             }
             xn[u] = xnorm[row];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ci = slot(b0 + kStep, u);
+            craw[u] = S[ci < ns ? ci : 0];
         }
         float s[U];
 #pragma unroll
@@ -284,7 +300,9 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
             float a = 0.0f;
 #pragma unroll
             for (int i = 0; i < NVB; ++i) {
-                const uint32_t wv[4] = {xv[u][i].x, xv[u][i].y, xv[u][i].z, xv[u][i].w};
+                const bool in = gl + i * GB < nv8;
+                const uint32_t wv[4] = {in ? xv[u][i].x : 0u, in ? xv[u][i].y : 0u, in ? xv[u][i].z : 0u,
+                                        in ? xv[u][i].w : 0u};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     a = __builtin_fmaf(qf[i][2 * j], bf16_lo(wv[j]), a);
@@ -322,20 +340,55 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
     }
     __syncthreads();
 
-    // phase 2: float32 direct distances of the survivors, one wave per candidate
-    for (int c = w; c < kp; c += kDistWaves) {
-        const int32_t id = uniform(cand[c]);
-        float r = INFINITY;
-        if (id >= 0) {
-            const float* xr = X + (int64_t)id * d;
-            float a = 0.0f;
-            for (int i = lane; i < d; i += kWave) {
-                const float df = qs[i] - xr[i];
-                a = __builtin_fmaf(df, df, a);
-            }
-            r = read_lane_f(group_sum<kWave>(a), 0);
+    // phase 2: float32 direct distances of the survivors, gathered as in
+    // dist_fp32 (same lanes per row, same summation order, U2 rows per group
+    // in flight)
+    {
+        const int g2 = lane / G2, gl2 = lane - g2 * G2;
+        const int nvec = d >> 2;
+        float4 q2[NV2];
+#pragma unroll
+        for (int i = 0; i < NV2; ++i) {
+            const int vi = gl2 + i * G2;
+            q2[i] = vi < nvec ? reinterpret_cast<const float4*>(qs)[vi] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        if (lane == 0) d32[c] = r;
+        constexpr int kStep2 = kDistWaves * GPW2 * U2;
+        for (int c0 = 0; c0 < kp; c0 += kStep2) {
+            int32_t id[U2];
+#pragma unroll
+            for (int u = 0; u < U2; ++u) {
+                const int c = c0 + (u * kDistWaves + w) * GPW2 + g2;
+                id[u] = c < kp ? cand[c] : -1;
+            }
+            float4 xv2[U2][NV2];
+#pragma unroll
+            for (int u = 0; u < U2; ++u) {
+                const float4* xr = reinterpret_cast<const float4*>(X + (int64_t)(id[u] < 0 ? 0 : id[u]) * d);
+#pragma unroll
+                for (int i = 0; i < NV2; ++i) {
+                    const int vi = gl2 + i * G2;
+                    xv2[u][i] = xr[vi < nvec ? vi : 0];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U2; ++u) {
+                float a = 0.0f;
+#pragma unroll
+                for (int i = 0; i < NV2; ++i) {
+                    const bool in = gl2 + i * G2 < nvec;
+                    const float4 x = xv2[u][i];
+                    const float dx = in ? q2[i].x - x.x : 0.f, dy = in ? q2[i].y - x.y : 0.f;
+                    const float dz = in ? q2[i].z - x.z : 0.f, dw = in ? q2[i].w - x.w : 0.f;
+                    a = __builtin_fmaf(dx, dx, a);
+                    a = __builtin_fmaf(dy, dy, a);
+                    a = __builtin_fmaf(dz, dz, a);
+                    a = __builtin_fmaf(dw, dw, a);
+                }
+                const float r = group_sum<G2>(a);
+                const int c = c0 + (u * kDistWaves + w) * GPW2 + g2;
+                if (gl2 == 0 && c < kp) d32[c] = id[u] >= 0 ? r : INFINITY;
+            }
+        }
     }
     __syncthreads();
     // order by (d32, id); empty slots (id -1, +inf) go last in slot order
