@@ -231,13 +231,16 @@ def main():
         orc = oracle.build_index(X, w.T, w.depth, w.a, w.index_seed, nthreads=nth)
         log(f"oracle index built in {time.perf_counter() - t0:.1f}s on {nth} threads")
         m = min(args.cpu_sample, nq)
-        t0 = time.perf_counter()
-        oracle.query(orc, Q[:m], k, v, nthreads=nth)
-        el = time.perf_counter() - t0
-        cpu = {"value": round(m / el, 1), "unit": "queries/s", "cores": nth, "kind": "oracle",
-               "sample": f"first {m} of the {nq} queries, oracle index of the same seed, "
-                         f"{el:.2f}s wall on {nth} host threads"}
-        log(f"oracle: {m / el:.1f} queries/s")
+        reps, el = 0, 0.0
+        while reps == 0 or (el < 10.0 and reps < 100):      # about 10 s of host work
+            t0 = time.perf_counter()
+            oracle.query(orc, Q[:m], k, v, nthreads=nth)
+            el += time.perf_counter() - t0
+            reps += 1
+        cpu = {"value": round(m * reps / el, 1), "unit": "queries/s", "cores": nth, "kind": "oracle",
+               "sample": f"first {m} of the {nq} queries x {reps} passes, oracle index of the same "
+                         f"seed, {el:.2f}s wall on {nth} host threads"}
+        log(f"oracle: {m * reps / el:.1f} queries/s ({reps} passes)")
 
     rec = {
         "metric": METRIC,
