@@ -97,6 +97,25 @@ typedef struct {
 mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32_t depth,
                        float a, uint64_t seed, mrpt_index** out);
 
+/* Index build options. */
+typedef struct {
+    int32_t on_device;     /* 1 (default): grow the trees on the GPU (data projected by the
+                              query path's projection kernel, every level cut by a segmented
+                              sort of (projection, id) keys); 0: on host threads.  Both give
+                              bit-identical trees.  The GPU build needs every projection
+                              vector to have at most 64 nonzeros (else the host build runs)
+                              and takes scratch device memory of about n*(4*depth + 16) bytes
+                              per tree of a group (groups sized to MRPT_BUILD_LIMIT bytes,
+                              default 8 GiB). */
+} mrpt_build_opts;
+
+/* Default build options (on_device = 1). */
+void mrpt_default_build_opts(mrpt_build_opts* opts);
+
+/* mrpt_build with options (opts = NULL: the defaults). */
+mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, int32_t depth, float a,
+                          uint64_t seed, const mrpt_build_opts* opts, mrpt_index** out);
+
 /* Approximate k-NN of nq queries (paper Alg. 4 approximate_knn with Alg. 3
  * tree_query), float32 exact search in S.
  *   Q        : device, nq x d float32.

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrpt.so")
 SOURCES = ["abi.cpp", "host_build.cpp", "kernels_route.hip", "kernels_vote.hip", "kernels_search.hip",
-           "kernels_misc.hip"]
+           "kernels_misc.hip", "kernels_build.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -100,6 +100,56 @@ mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
     return MRPT_OK;
 }
 
+size_t build_limit() {
+    const char* env = std::getenv("MRPT_BUILD_LIMIT");
+    if (env && *env) {
+        const long long v = std::atoll(env);
+        if (v > 0) return (size_t)v;
+    }
+    return (size_t)8 << 30;
+}
+
+// grows all trees on the device in groups that fit build_limit() of scratch
+mrpt_status build_trees_on_device(mrpt_index* ix) {
+    const int64_t n = ix->n;
+    const int32_t depth = ix->depth, T = ix->T;
+    std::vector<std::vector<int64_t>> level_off((size_t)depth + 1);
+    for (int32_t lv = 0; lv <= depth; ++lv) leaf_offsets(n, lv, level_off[lv]);
+    const size_t per_tree = device_build_bytes_per_tree(n, depth);
+    int64_t g = std::max<int64_t>(1, (int64_t)(build_limit() / per_tree));
+    g = std::min<int64_t>({g, (int64_t)T, (int64_t)((int64_t(1) << 31) - 1) / n});   // int32 key offsets
+    float* P = nullptr;
+    uint64_t *ka = nullptr, *kb = nullptr;
+    int32_t* seg = nullptr;
+    int64_t* node = nullptr;
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    auto release = [&]() {
+        for (void* p : {(void*)P, (void*)ka, (void*)kb, (void*)seg, (void*)node, temp})
+            if (p) (void)hipFree(p);
+    };
+    const size_t nodes = (size_t)1 << depth;
+    hipError_t e = hipMalloc((void**)&P, (size_t)g * std::max(depth, 1) * n * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&ka, (size_t)g * n * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&kb, (size_t)g * n * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&seg, ((size_t)g * nodes + 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&node, (nodes + 1) * sizeof(int64_t));
+    if (e != hipSuccess) {
+        release();
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? MRPT_ENOMEM : MRPT_EDEVICE, "device build scratch: %s",
+                    hipGetErrorString(e));
+    }
+    for (int32_t t0 = 0; t0 < T && e == hipSuccess; t0 += (int32_t)g) {
+        const int32_t gg = (int32_t)std::min<int64_t>(g, T - t0);
+        e = grow_trees_device(ix, t0, gg, level_off, P, ka, kb, temp, temp_bytes, seg, node, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    release();
+    if (e != hipSuccess) return fail(MRPT_EDEVICE, "device build: %s", hipGetErrorString(e));
+    return MRPT_OK;
+}
+
 int64_t candidate_cap(const mrpt_index* ix, int32_t v) {
     const int64_t bound = (int64_t)ix->T * ix->max_leaf / v;
     return std::max<int64_t>(1, std::min<int64_t>(ix->n, bound));
@@ -204,9 +254,22 @@ void mrpt_default_opts(mrpt_query_opts* o) {
     o->stage_events = nullptr;
 }
 
+void mrpt_default_build_opts(mrpt_build_opts* o) {
+    if (!o) return;
+    o->on_device = 1;
+}
+
 mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32_t depth, float a, uint64_t seed,
                        mrpt_index** out) {
+    return mrpt_build_ex(data, n, d, T, depth, a, seed, nullptr, out);
+}
+
+mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, int32_t depth, float a,
+                          uint64_t seed, const mrpt_build_opts* opts, mrpt_index** out) {
     clear_error();
+    mrpt_build_opts bo;
+    mrpt_default_build_opts(&bo);
+    if (opts) bo = *opts;
     if (!out) return fail(MRPT_EINVAL, "out is NULL");
     if (!data) return fail(MRPT_EINVAL, "data is NULL");
     if (n < 1 || n >= (int64_t(1) << 31)) return fail(MRPT_EINVAL, "n = %lld outside [1, 2^31)", (long long)n);
@@ -256,25 +319,29 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
         if (h) return fail(MRPT_ENONFINITE, "data holds NaN or Inf");
     }
 
-    std::vector<float> hX;
-    try {
-        hX.resize(nd);
-    } catch (const std::bad_alloc&) {
-        return fail(MRPT_ENOMEM, "host copy of the data (%zu bytes)", nd * sizeof(float));
-    }
-    MRPT_HIP_TRY(hipMemcpy(hX.data(), ix->X, nd * sizeof(float), hipMemcpyDeviceToHost));
-
     generate_projection(d, T, depth, a, seed, ix->h_rowptr, ix->h_col, ix->h_val);
     for (int32_t t = 0; t < T; ++t)
         ix->max_tree_nnz = std::max(ix->max_tree_nnz, ix->h_rowptr[(size_t)(t + 1) * depth] -
                                                         ix->h_rowptr[(size_t)t * depth]);
     for (size_t r = 0; r + 1 < ix->h_rowptr.size(); ++r)
         ix->max_row_nnz = std::max(ix->max_row_nnz, ix->h_rowptr[r + 1] - ix->h_rowptr[r]);
+    // the GPU build projects with the query path's kernel (<= 64 nonzeros per vector)
+    const bool on_device = bo.on_device != 0 && ix->max_row_nnz <= 64;
+    ix->built_on_device = on_device ? 1 : 0;
     HostTrees trees;
-    grow_trees_host(hX.data(), n, d, T, depth, ix->h_rowptr, ix->h_col, ix->h_val, trees);
+    if (on_device) {
+        leaf_offsets(n, depth, trees.off);
+    } else {
+        std::vector<float> hX;
+        try {
+            hX.resize(nd);
+        } catch (const std::bad_alloc&) {
+            return fail(MRPT_ENOMEM, "host copy of the data (%zu bytes)", nd * sizeof(float));
+        }
+        MRPT_HIP_TRY(hipMemcpy(hX.data(), ix->X, nd * sizeof(float), hipMemcpyDeviceToHost));
+        grow_trees_host(hX.data(), n, d, T, depth, ix->h_rowptr, ix->h_col, ix->h_val, trees);
+    }
     ix->h_off = trees.off;
-    hX.clear();
-    hX.shrink_to_fit();
 
     const size_t nnz = ix->h_col.size();
     const size_t nsplit = ((size_t)1 << depth) - 1;
@@ -296,12 +363,14 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
         MRPT_HIP_TRY(hipMemcpy(ix->col, ix->h_col.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         MRPT_HIP_TRY(hipMemcpy(ix->val, ix->h_val.data(), nnz * sizeof(float), hipMemcpyHostToDevice));
     }
-    if (nsplit)
-        MRPT_HIP_TRY(hipMemcpy(ix->splits, trees.splits.data(), (size_t)T * nsplit * sizeof(float),
-                               hipMemcpyHostToDevice));
-    MRPT_HIP_TRY(hipMemcpy2D(ix->perm, (size_t)ix->perm_ld * sizeof(int32_t), trees.perm.data(),
-                             (size_t)n * sizeof(int32_t), (size_t)n * sizeof(int32_t), (size_t)T,
-                             hipMemcpyHostToDevice));
+    if (!on_device) {
+        if (nsplit)
+            MRPT_HIP_TRY(hipMemcpy(ix->splits, trees.splits.data(), (size_t)T * nsplit * sizeof(float),
+                                   hipMemcpyHostToDevice));
+        MRPT_HIP_TRY(hipMemcpy2D(ix->perm, (size_t)ix->perm_ld * sizeof(int32_t), trees.perm.data(),
+                                 (size_t)n * sizeof(int32_t), (size_t)n * sizeof(int32_t), (size_t)T,
+                                 hipMemcpyHostToDevice));
+    }
     {
         std::vector<int32_t> pad((size_t)T * kPermPad);
         for (size_t i = 0; i < pad.size(); ++i) pad[i] = (int32_t)(n + (int64_t)(i % kPermPad));
@@ -311,6 +380,7 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
     }
     std::vector<int32_t> off32(ix->h_off.begin(), ix->h_off.end());
     MRPT_HIP_TRY(hipMemcpy(ix->off, off32.data(), off32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (on_device) MRPT_TRY(build_trees_on_device(ix.get()));
     MRPT_HIP_TRY(launch_quantize_bf16(ix->X, n, d, ix->Xb, ix->xnorm, nullptr));
     MRPT_HIP_TRY(hipDeviceSynchronize());
 

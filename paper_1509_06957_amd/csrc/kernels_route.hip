@@ -455,27 +455,36 @@ hipError_t launch_route_fast(const mrpt_index* ix, const float* Q, int64_t nq, i
 
 constexpr int kProjRows = 16;   // rows per wave in project_kernel
 
+}  // namespace
+
+hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32_t row0, int32_t nrows, float* P,
+                          hipStream_t s) {
+    if (m == 0 || nrows == 0) return hipSuccess;
+    const int d = ix->d;
+    const size_t q_bytes = (size_t)d * kQStride * 4;
+    const bool qlds = q_bytes <= 64 * 1024;
+    const size_t lds = qlds ? q_bytes : 0;
+    dim3 grid((unsigned)((m + kWave - 1) / kWave),
+              (unsigned)((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)));
+    if (qlds) {
+        (void)hipFuncSetAttribute((const void*)project_kernel<kProjRows, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((project_kernel<kProjRows, true>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,
+                           ix->rowptr + row0, ix->col, ix->val, nrows, P);
+    } else {
+        hipLaunchKernelGGL((project_kernel<kProjRows, false>), grid, dim3(kProjWaves * kWave), 0, s, A, m, d,
+                           ix->rowptr + row0, ix->col, ix->val, nrows, P);
+    }
+    return hipGetLastError();
+}
+
+namespace {
+
 hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
                             hipStream_t s) {
     const int depth = ix->depth;
-    const int d = ix->d;
-    const int nrows = ix->T * depth;
-    if (nrows > 0) {
-        const size_t q_bytes = (size_t)d * kQStride * 4;
-        const bool qlds = q_bytes <= 64 * 1024;
-        const size_t lds = qlds ? q_bytes : 0;
-        dim3 grid((unsigned)((nq + kWave - 1) / kWave),
-                  (unsigned)((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)));
-        if (qlds) {
-            (void)hipFuncSetAttribute((const void*)project_kernel<kProjRows, true>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL((project_kernel<kProjRows, true>), grid, dim3(kProjWaves * kWave), lds, s, Q, nq, d,
-                               ix->rowptr, ix->col, ix->val, nrows, pq);
-        } else {
-            hipLaunchKernelGGL((project_kernel<kProjRows, false>), grid, dim3(kProjWaves * kWave), 0, s, Q, nq, d,
-                               ix->rowptr, ix->col, ix->val, nrows, pq);
-        }
-        hipError_t e = hipGetLastError();
+    {
+        hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s);
         if (e != hipSuccess) return e;
     }
     const int nsplit = (1 << depth) - 1;

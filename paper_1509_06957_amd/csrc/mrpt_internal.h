@@ -69,6 +69,7 @@ struct mrpt_index {
     int32_t id_chunk = 0;        // ids per vote pass at v = 1 (reported by mrpt_index_info)
     int32_t max_tree_nnz = 0;    // largest number of projection nonzeros of one tree
     int32_t max_row_nnz = 0;     // largest number of nonzeros of one projection vector
+    int32_t built_on_device = 0; // trees grown by the GPU build
     int device = 0;
 
     // host copy of the projection CSR (for export)
@@ -110,7 +111,21 @@ void grow_trees_host(const float* X, int64_t n, int32_t d, int32_t T, int32_t de
                      const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,
                      const std::vector<float>& val, HostTrees& out);
 
+// device index build (kernels_build.hip): trees [t0, t0 + g) into ix->splits
+// and ix->perm.  level_off[lv]: node offsets of level lv (lv = 0..depth).
+// Scratch: P (g * depth * n floats), keys_a/keys_b (g * n each), seg_off
+// (g * 2^depth + 1), node_off (2^depth + 1); temp grows as the sort needs.
+size_t device_build_bytes_per_tree(int64_t n, int32_t depth);
+hipError_t grow_trees_device(mrpt_index* ix, int32_t t0, int32_t g,
+                             const std::vector<std::vector<int64_t>>& level_off, float* P, uint64_t* keys_a,
+                             uint64_t* keys_b, void*& temp, size_t& temp_bytes, int32_t* seg_off,
+                             int64_t* node_off, hipStream_t s);
+
 // kernel launchers (kernels_route/vote/search/misc.hip); all asynchronous
+// projections of the m rows of A onto vectors row0 .. row0 + nrows - 1:
+// P[r * m + i] (the float32 fused multiply-add chain of Sec. II-C)
+hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32_t row0, int32_t nrows, float* P,
+                          hipStream_t s);
 // pq: scratch of route_workspace_floats(ix, nq) floats for the projections
 // (nullptr selects the fused single-kernel form)
 size_t route_workspace_floats(const mrpt_index* ix, int64_t nq);

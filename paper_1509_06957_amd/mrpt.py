@@ -32,6 +32,10 @@ class mrpt_query_opts(ctypes.Structure):
                 ("s_count", ctypes.c_void_p), ("stage_events", ctypes.c_void_p)]
 
 
+class mrpt_build_opts(ctypes.Structure):
+    _fields_ = [("on_device", ctypes.c_int32)]
+
+
 class mrpt_index_desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("T", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("a", ctypes.c_float), ("seed", ctypes.c_uint64), ("nnz", ctypes.c_int64),
@@ -41,7 +45,7 @@ class mrpt_index_desc(ctypes.Structure):
 _lib = None
 
 EXPORTED = [
-    "mrpt_build", "mrpt_query", "mrpt_query_ex", "mrpt_default_opts", "mrpt_free", "mrpt_last_error",
+    "mrpt_build", "mrpt_build_ex", "mrpt_default_build_opts", "mrpt_query", "mrpt_query_ex", "mrpt_default_opts", "mrpt_free", "mrpt_last_error",
     "mrpt_index_info", "mrpt_export_projection", "mrpt_export_tree", "mrpt_export_leaf_offsets",
     "mrpt_debug_leaves", "mrpt_debug_votes", "mrpt_candidate_cap",
 ]
@@ -59,6 +63,10 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, i32, i64, f32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64
     lib.mrpt_build.argtypes = [vp, i64, i32, i32, i32, f32, u64, ctypes.POINTER(vp)]
+    lib.mrpt_build_ex.argtypes = [vp, i64, i32, i32, i32, f32, u64, ctypes.POINTER(mrpt_build_opts),
+                                  ctypes.POINTER(vp)]
+    lib.mrpt_default_build_opts.argtypes = [ctypes.POINTER(mrpt_build_opts)]
+    lib.mrpt_default_build_opts.restype = None
     lib.mrpt_query.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp]
     lib.mrpt_query_ex.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.POINTER(mrpt_query_opts), vp]
     lib.mrpt_default_opts.argtypes = [ctypes.POINTER(mrpt_query_opts)]
@@ -75,7 +83,8 @@ def load(path: str = LIB_PATH):
     lib.mrpt_candidate_cap.argtypes = [vp, i32]
     lib.mrpt_candidate_cap.restype = i64
     for name in EXPORTED:
-        if name not in ("mrpt_default_opts", "mrpt_free", "mrpt_last_error", "mrpt_candidate_cap"):
+        if name not in ("mrpt_default_opts", "mrpt_default_build_opts", "mrpt_free", "mrpt_last_error",
+                        "mrpt_candidate_cap"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -112,6 +121,21 @@ def mrpt_build(data, T: int, depth: int, a: float, seed: int) -> ctypes.c_void_p
     n, d = data.shape
     h = ctypes.c_void_p()
     _check(load().mrpt_build(_dev(data, "float32"), n, d, T, depth, a, seed & (2**64 - 1), ctypes.byref(h)))
+    return h
+
+
+def mrpt_default_build_opts() -> mrpt_build_opts:
+    o = mrpt_build_opts()
+    load().mrpt_default_build_opts(ctypes.byref(o))
+    return o
+
+
+def mrpt_build_ex(data, T: int, depth: int, a: float, seed: int, opts: mrpt_build_opts = None) -> ctypes.c_void_p:
+    """mrpt_build with options (None: the defaults)."""
+    n, d = data.shape
+    h = ctypes.c_void_p()
+    _check(load().mrpt_build_ex(_dev(data, "float32"), n, d, T, depth, a, seed & (2**64 - 1),
+                                None if opts is None else ctypes.byref(opts), ctypes.byref(h)))
     return h
 
 
@@ -189,8 +213,10 @@ def mrpt_candidate_cap(ix, v: int) -> int:
 class Index:
     """Owning wrapper of an index handle (frees it on close / garbage collection)."""
 
-    def __init__(self, data, T: int, depth: int, a: float, seed: int):
-        self.handle = mrpt_build(data, T, depth, a, seed)
+    def __init__(self, data, T: int, depth: int, a: float, seed: int, on_device: bool = True):
+        opts = mrpt_default_build_opts()
+        opts.on_device = 1 if on_device else 0
+        self.handle = mrpt_build_ex(data, T, depth, a, seed, opts)
         self.info = mrpt_index_info(self.handle)
 
     def query(self, Q, k: int, v: int, precision: int = MRPT_FP32, rerank_factor: int = 4,

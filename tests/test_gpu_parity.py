@@ -299,3 +299,26 @@ def test_vote_kernel_variants_agree(kernel, monkeypatch):
             assert np.array_equal(ids[q], ref["s_ids"][q]), f"n={n} T={T} v={v} query {q}"
             assert np.array_equal(cnt[q], ref["s_votes"][q])
         g.close()
+
+
+@pytest.mark.parametrize("n,d,T,depth,integer", [(5000, 16, 6, 5, False), (4099, 8, 5, 7, True),
+                                                 (3000, 24, 3, 0, False), (777, 4, 9, 9, True),
+                                                 (20000, 3, 2, 11, True), (65537, 12, 3, 12, False)])
+def test_device_build_matches_host_and_oracle(n, d, T, depth, integer, monkeypatch):
+    # the GPU build (projection kernel + per-level segmented sort of
+    # (projection, id) keys) and the host build give the oracle's trees bit
+    # for bit; integer data in {0..3} ties projections often, depth 0 is one
+    # leaf, and the scratch limit forces groups of two trees
+    _print_case(f"device build n={n} d={d} T={T} depth={depth} integer={integer}")
+    monkeypatch.setenv("MRPT_BUILD_LIMIT", str(2 * n * (4 * max(depth, 1) + 16)))
+    X, _ = _small(n, d, T, depth, seed=n + depth, integer=integer)
+    orc = oracle.build_index(X, T, depth, 0.5, 11)
+    for on_device in (True, False):
+        g = mrpt.Index(dev(X), T, depth, 0.5, 11, on_device=on_device)
+        assert np.array_equal(mrpt.mrpt_export_leaf_offsets(g.handle), orc.off)
+        for t in range(T):
+            splits, perm = mrpt.mrpt_export_tree(g.handle, t)
+            assert np.array_equal(splits.view(np.uint32), orc.splits[t].view(np.uint32)), \
+                f"on_device={on_device} tree {t} splits"
+            assert np.array_equal(perm, orc.perm[t]), f"on_device={on_device} tree {t} perm"
+        g.close()
