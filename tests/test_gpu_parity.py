@@ -322,3 +322,16 @@ def test_device_build_matches_host_and_oracle(n, d, T, depth, integer, monkeypat
                 f"on_device={on_device} tree {t} splits"
             assert np.array_equal(perm, orc.perm[t]), f"on_device={on_device} tree {t} perm"
         g.close()
+
+
+@pytest.mark.parametrize("k,precision", [(10, None), (100, None), (10, "bf16")])
+def test_gist_like_shape_full_parity(k, precision):
+    # the gist-like data (d = 960, values in (0, 1)) at a size the oracle
+    # handles in seconds: 16 trees of depth 5, v = 5, k = 10 and 100; the
+    # windows exceed the single-pass vote kernel's registers (multi-pass), the
+    # search runs 64 lanes x 4 float4 per row, the bf16 arm 64 lanes x 2 x 8
+    w = W.GIST_LIKE.scaled(n=30000, nq=48, T=16, depth=5)
+    _print_case(f"gist-like shape n={w.n} T={w.T} depth={w.depth} k={k} {precision or 'fp32'}")
+    X, Q = W.data(w), W.queries(w)
+    prec = mrpt.MRPT_BF16_RERANK if precision == "bf16" else None
+    _full_compare(X, Q, w.T, w.depth, w.a, w.index_seed, k, w.v, precision=prec)
