@@ -111,11 +111,19 @@ def main():
     log(f"workload {w.name}: generated in {time.perf_counter() - t0:.1f}s")
     Xd = torch.from_numpy(X).cuda()
     Qd = torch.from_numpy(Q).cuda()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ix = mrpt.Index(Xd, w.T, w.depth, w.a, w.index_seed)
-    build_s = time.perf_counter() - t0
-    log(f"index built in {build_s:.1f}s")
+    # index build (outside the timed query region): GPU build, then the host
+    # build of the same index for comparison (bit-identical trees)
+    build = {}
+    for name, on_dev in (("device", True), ("host", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ix = mrpt.Index(Xd, w.T, w.depth, w.a, w.index_seed, on_device=on_dev)
+        build[name] = time.perf_counter() - t0
+        if not on_dev:
+            ix.close()
+    ix = mrpt.Index(Xd, w.T, w.depth, w.a, w.index_seed, on_device=True)
+    build_s = build["device"]
+    log(f"index built in {build['device']:.3f}s on the GPU, {build['host']:.2f}s on host threads")
     nq, k, v = w.nq, w.k, w.v
 
     # |S| per query and the leaf sizes visited (for the algorithmic bytes)
@@ -140,6 +148,7 @@ def main():
     bytes_search = {
         "fp32": nq * 4 + sum_s * 4 + sum_s * w.d * 4 + nq * w.d * 4 + nq * k * 8,
         "bf16": nq * 4 + sum_s * 4 + sum_s * (w.d * 2 + 4) + rerank_rows * w.d * 4 + nq * w.d * 4 + nq * k * 8,
+        "fp8": nq * 4 + sum_s * 4 + sum_s * (w.d + 8) + rerank_rows * w.d * 4 + nq * w.d * 4 + nq * k * 8,
     }
 
     def run_arm(precision, steps, warmup):
@@ -173,6 +182,9 @@ def main():
     log(f"fp32: {el32 / args.steps * 1e3:.3f} ms/step, stages(ms) {np.round(st32, 4).tolist()}")
     el16, st16, out16 = run_arm(mrpt.MRPT_BF16_RERANK, args.steps, args.warmup)
     log(f"bf16+rerank: {el16 / args.steps * 1e3:.3f} ms/step, stages(ms) {np.round(st16, 4).tolist()}")
+    el8, st8, out8 = run_arm(mrpt.MRPT_FP8_RERANK, args.steps, args.warmup)
+    log(f"fp8+rerank: {el8 / args.steps * 1e3:.3f} ms/step, stages(ms) {np.round(st8, 4).tolist()}")
+    gi8, gd8 = out8[0].cpu().numpy(), out8[1].cpu().numpy()
     gi32, gd32 = out32[0].cpu().numpy(), out32[1].cpu().numpy()
     gi16, gd16 = out16[0].cpu().numpy(), out16[1].cpu().numpy()
 
@@ -196,7 +208,9 @@ def main():
 
     rec32, err32 = quality(gi32, gd32)
     rec16, err16 = quality(gi16, gd16)
-    log(f"recall@{k}: fp32 {rec32:.4f} bf16+rerank {rec16:.4f}; max rel err {err32:.2e} / {err16:.2e}")
+    rec8, err8 = quality(gi8, gd8)
+    log(f"recall@{k}: fp32 {rec32:.4f} bf16+rerank {rec16:.4f} fp8+rerank {rec8:.4f}; "
+        f"max rel err {err32:.2e} / {err16:.2e} / {err8:.2e}")
 
     def arm_record(elapsed, stage_ms, arm):
         qps = nq * args.steps / elapsed
@@ -211,6 +225,7 @@ def main():
 
     qps32, stages32, tb32 = arm_record(el32, st32, "fp32")
     qps16, stages16, tb16 = arm_record(el16, st16, "bf16")
+    qps8, stages8, tb8 = arm_record(el8, st8, "fp8")
     dom = max(STAGES, key=lambda s: stages32[s]["ms"])
     traffic = read_traffic(STAGE_KERNEL[dom], args.workload)
     copy_gbps = hbm_copy_gbps(torch)
@@ -274,8 +289,16 @@ def main():
                             "stages": stages16,
                             "path_hbm_frac": round(tb16 / (el16 / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
                             "identical_to_fp32": bool(np.array_equal(gi32, gi16) and np.array_equal(gd32, gd16))},
+            "fp8_rerank": {"qps": round(qps8, 1), "ms_per_step": round(el8 / args.steps * 1e3, 4),
+                           "recall_at_k": round(rec8, 4), "max_rel_err_vs_fp64": err8, "stages": stages8,
+                           "path_hbm_frac": round(tb8 / (el8 / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+                           "ids_equal_fp32_frac": round(float(np.mean(np.all(gi8 == gi32, axis=1))), 4)},
         },
-        "build_s": round(build_s, 2),
+        "build_s": round(build_s, 3),
+        "build": {"device_s": round(build["device"], 3), "host_s": round(build["host"], 2),
+                  # projection work of the build: n * (nonzeros of all T*depth vectors) multiply-adds
+                  "projection_fma": int(w.n) * nnz,
+                  "note": "device: projection kernel + per-level segmented sort; host: threads over trees"},
         "recall_sample": len(rs),
     }
     ix.close()

@@ -53,15 +53,20 @@ typedef enum {
 
 typedef enum {
     MRPT_FP32 = 0,         /* exact search in S with float32 distances */
-    MRPT_BF16_RERANK = 1   /* bfloat16 prefilter over S, float32 rerank of the best
-                              rerank_factor*k, float64 recheck at the k-th boundary */
+    MRPT_BF16_RERANK = 1,  /* bfloat16 prefilter over S, float32 rerank of the best
+                              rerank_factor*k, float64 recheck at the k-th boundary
+                              (d % 8 == 0, d <= 1024) */
+    MRPT_FP8_RERANK = 2    /* as MRPT_BF16_RERANK with an fp8 (e4m3) prefilter: rows
+                              quantized at build time with a per-row scale max|x|/240
+                              (d % 16 == 0, d <= 1024); lossy for general data, so S's
+                              true k nearest can fall outside the reranked set */
 } mrpt_precision;
 
 typedef struct {
     int32_t precision;     /* mrpt_precision; default MRPT_FP32 */
-    int32_t rerank_factor; /* BF16 arm: keep the best rerank_factor*k of the prefilter
+    int32_t rerank_factor; /* prefilter arms: keep the best rerank_factor*k of the prefilter
                               (default 4; rerank_factor*k <= 512) */
-    float recheck_rel;     /* BF16 arm: candidates whose float32 distance is within
+    float recheck_rel;     /* prefilter arms: candidates whose float32 distance is within
                               recheck_rel (relative) of the k-th are re-ranked in
                               float64 (default 1e-6) */
     int32_t check_finite;  /* 1: scan Q for NaN/Inf first and return MRPT_ENONFINITE

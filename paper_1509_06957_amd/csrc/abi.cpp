@@ -39,8 +39,8 @@ hipError_t dev_alloc(T** p, size_t count, int64_t* tally) {
 }
 
 void dev_release(mrpt_index* ix) {
-    void* ptrs[] = {ix->X, ix->Xb, ix->xnorm, ix->rowptr, ix->col, ix->val, ix->splits, ix->perm, ix->off,
-                    ix->ws.base};
+    void* ptrs[] = {ix->X, ix->Xb, ix->xnorm, ix->X8, ix->scale8, ix->norm8, ix->rowptr, ix->col, ix->val,
+                    ix->splits, ix->perm, ix->off, ix->ws.base};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (ix->ws.done) (void)hipEventDestroy(ix->ws.done);
@@ -169,16 +169,18 @@ mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_
     mrpt_query_opts o;
     mrpt_default_opts(&o);
     if (opts) o = *opts;
-    if (o.precision != MRPT_FP32 && o.precision != MRPT_BF16_RERANK)
+    if (o.precision != MRPT_FP32 && o.precision != MRPT_BF16_RERANK && o.precision != MRPT_FP8_RERANK)
         return fail(MRPT_EINVAL, "unknown precision %d", o.precision);
-    if (o.precision == MRPT_BF16_RERANK) {
+    if (o.precision == MRPT_FP8_RERANK && !cix->X8)
+        return fail(MRPT_EINVAL, "the fp8 arm needs d %% 16 == 0 and d <= 1024 (d = %d)", cix->d);
+    if (o.precision != MRPT_FP32) {
         if (o.rerank_factor < 1 || (int64_t)o.rerank_factor * k > kMaxRerank)
             return fail(MRPT_EINVAL, "rerank_factor*k = %lld outside [1, %d]",
                         (long long)o.rerank_factor * k, kMaxRerank);
         if (!(o.recheck_rel >= 0.0f) || !std::isfinite(o.recheck_rel))
             return fail(MRPT_EINVAL, "recheck_rel must be finite and >= 0");
         if (cix->d % 8 != 0 || cix->d > 1024)
-            return fail(MRPT_EINVAL, "the bfloat16 arm needs d %% 8 == 0 and d <= 1024 (d = %d)", cix->d);
+            return fail(MRPT_EINVAL, "the prefilter arms need d %% 8 == 0 and d <= 1024 (d = %d)", cix->d);
     }
     if (nq == 0) return MRPT_OK;
     mrpt_index* ix = const_cast<mrpt_index*>(cix);
@@ -213,8 +215,9 @@ mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_
             MRPT_HIP_TRY(launch_dist_fp32(ix, Qb, m, ix->ws.s_ids, cap, ix->ws.s_count, k, out_idx + q0 * k,
                                           out_dist + q0 * k, s));
         else
-            MRPT_HIP_TRY(launch_dist_bf16(ix, Qb, m, ix->ws.s_ids, cap, ix->ws.s_count, k, o.rerank_factor,
-                                          o.recheck_rel, out_idx + q0 * k, out_dist + q0 * k, s));
+            MRPT_HIP_TRY(launch_dist_prefilter(ix, o.precision == MRPT_FP8_RERANK ? 1 : 0, Qb, m, ix->ws.s_ids,
+                                               cap, ix->ws.s_count, k, o.rerank_factor, o.recheck_rel,
+                                               out_idx + q0 * k, out_dist + q0 * k, s));
         MRPT_HIP_TRY(mark(q0, 3));
         if (o.s_count) MRPT_HIP_TRY(launch_copy_counts(ix->ws.s_count, m, o.s_count + q0, s));
     }
@@ -356,6 +359,12 @@ mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, in
     if ((e = dev_alloc(&ix->off, (size_t)ix->nleaf + 1, &ix->device_bytes)) != hipSuccess) return oom(e, "offsets");
     if ((e = dev_alloc(&ix->Xb, nd, &ix->device_bytes)) != hipSuccess) return oom(e, "bfloat16 data");
     if ((e = dev_alloc(&ix->xnorm, (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "norms");
+    const bool fp8 = d % 16 == 0 && d <= 1024;
+    if (fp8) {
+        if ((e = dev_alloc(&ix->X8, nd, &ix->device_bytes)) != hipSuccess) return oom(e, "fp8 data");
+        if ((e = dev_alloc(&ix->scale8, (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "fp8 scales");
+        if ((e = dev_alloc(&ix->norm8, (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "fp8 norms");
+    }
 
     MRPT_HIP_TRY(hipMemcpy(ix->rowptr, ix->h_rowptr.data(), ix->h_rowptr.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice));
@@ -382,6 +391,7 @@ mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, in
     MRPT_HIP_TRY(hipMemcpy(ix->off, off32.data(), off32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (on_device) MRPT_TRY(build_trees_on_device(ix.get()));
     MRPT_HIP_TRY(launch_quantize_bf16(ix->X, n, d, ix->Xb, ix->xnorm, nullptr));
+    if (fp8) MRPT_HIP_TRY(launch_quantize_fp8(ix->X, n, d, ix->X8, ix->scale8, ix->norm8, nullptr));
     MRPT_HIP_TRY(hipDeviceSynchronize());
 
     guard.p = nullptr;

@@ -58,6 +58,59 @@ hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hip
     return hipGetLastError();
 }
 
+// FP8 (e4m3) rows with a per-row scale: scale = max|x| / 240 (0 rows: 1), the
+// codes are x / scale rounded to nearest by the hardware conversion (|x /
+// scale| <= 240 is finite in both e4m3 encodings), and norm = scale^2 *
+// sum(decode(code)^2) in float32, so that the prefilter's ||x^||^2 is the
+// squared norm of exactly the row it decodes.  One wave per row, d % 4 == 0.
+__global__ __launch_bounds__(256) void quantize_fp8_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                           uint8_t* __restrict__ X8, float* __restrict__ scale8,
+                                                           float* __restrict__ norm8) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < n; row += waves) {
+        const float4* xr = reinterpret_cast<const float4*>(X + row * d);
+        uint32_t* cr = reinterpret_cast<uint32_t*>(X8 + row * d);
+        const int nv = d >> 2;
+        float mx = 0.0f;
+        for (int i = lane; i < nv; i += 64) {
+            const float4 v = xr[i];
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        const float scale = mx > 0.0f ? mx / 240.0f : 1.0f;
+        float acc = 0.0f;
+        for (int i = lane; i < nv; i += 64) {
+            const float4 v = xr[i];
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(v.x / scale, v.y / scale, 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(v.z / scale, v.w / scale, w, true);
+            cr[i] = (uint32_t)w;
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+            acc = __builtin_fmaf(lo[0], lo[0], acc);
+            acc = __builtin_fmaf(lo[1], lo[1], acc);
+            acc = __builtin_fmaf(hi[0], hi[0], acc);
+            acc = __builtin_fmaf(hi[1], hi[1], acc);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) {
+            scale8[row] = scale;
+            norm8[row] = (scale * scale) * acc;
+        }
+    }
+}
+
+hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8, float* scale8, float* norm8,
+                               hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(quantize_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, X8, scale8, norm8);
+    return hipGetLastError();
+}
+
 hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, float* xnorm, hipStream_t s) {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 3) / 4;

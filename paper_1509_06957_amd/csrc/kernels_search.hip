@@ -193,21 +193,27 @@ __global__ __launch_bounds__(256) void dist_fp32_generic_kernel(const float* __r
 }
 
 // ---------------------------------------------------------------------------
-// dist_bf16: phase 1 ranks S by ||q||^2 - 2 q.x~ + ||x~||^2 with x~ the
-// bfloat16 row (8 values per lane per 16-byte load, float32 accumulation) and
-// keeps the best kp = r*k; phase 2 recomputes those kp with float32 direct
-// differences from the float32 rows and orders them by (distance, id);
-// phase 3 recomputes in float64 every candidate whose float32 distance is
-// within recheck_rel of the k-th and orders that window by (float64 distance,
-// id).  One workgroup (4 waves) per query.
+// dist_prefilter (bf16 and fp8 arms): phase 1 ranks S by
+// ||q||^2 - 2 q.x~ + ||x~||^2 with x~ the low-precision row (bfloat16: 8
+// values per 16-byte load; fp8 e4m3: 16 values per load and a per-row scale,
+// x~ = scale * decode(code)), float32 accumulation, and keeps the best
+// kp = r*k; phase 2 recomputes those kp with float32 direct differences from
+// the float32 rows and orders them by (distance, id); phase 3 recomputes in
+// float64 every candidate whose float32 distance is within recheck_rel of the
+// k-th and orders that window by (float64 distance, id).  One workgroup (4
+// waves) per query.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
 
-template <int GB, int NVB, int RB>
-__global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict__ X,
-                                                        const uint16_t* __restrict__ Xb,
-                                                        const float* __restrict__ xnorm, int32_t d,
+constexpr int kFmtBf16 = 0;
+constexpr int kFmtFp8 = 1;
+
+template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
+__global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __restrict__ X,
+                                                             const uint8_t* __restrict__ Xq,
+                                                             const float* __restrict__ xscale,
+                                                             const float* __restrict__ xnorm, int32_t d,
                                                         const float* __restrict__ Q,
                                                         const int32_t* __restrict__ s_ids, int64_t cap,
                                                         const int32_t* __restrict__ s_count, int32_t k,
@@ -216,9 +222,9 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
                                                         float* __restrict__ out_dist) {
     constexpr int GPW = kWave / GB;
     constexpr int U = 8 / NVB;
+    constexpr int EPU = FMT == kFmtBf16 ? 8 : 16;      // row values per 16-byte load
+    constexpr int ROWB = FMT == kFmtBf16 ? 2 : 1;       // bytes per row value
     // phase 2 reads float32 rows as the fp32 kernel does: G2 lanes x NV2 float4
-    constexpr int G2 = GB <= 32 ? 2 * GB : 64;
-    constexpr int NV2 = GB <= 32 ? NVB : 2 * NVB;
     constexpr int GPW2 = kWave / G2;
     constexpr int U2 = 8 / NV2;
     __shared__ float md[kDistWaves][kWave * RB];
@@ -237,20 +243,20 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
     const int64_t q = blockIdx.x;
     const int ns = uniform(s_count[q]);
     const int32_t* S = s_ids + q * cap;
-    const int nv8 = d >> 3;
+    const int nv8 = d / EPU;                       // 16-byte loads per row
     const float* qrow = Q + q * d;
 
     for (int i = (int)threadIdx.x; i < d; i += (int)blockDim.x) qs[i] = qrow[i];
 
-    // query slice (8 floats per 16-byte bf16 slot) and ||q||^2
-    float qf[NVB][8];
+    // query slice (EPU floats per 16-byte load) and ||q||^2
+    float qf[NVB][EPU];
     float qn_part = 0.0f;
 #pragma unroll
     for (int i = 0; i < NVB; ++i) {
         const int vi = gl + i * GB;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            qf[i][j] = vi < nv8 ? qrow[vi * 8 + j] : 0.0f;
+        for (int j = 0; j < EPU; ++j) {
+            qf[i][j] = vi < nv8 ? qrow[vi * EPU + j] : 0.0f;
             qn_part = __builtin_fmaf(qf[i][j], qf[i][j], qn_part);
         }
     }
@@ -277,17 +283,18 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
 #pragma unroll
         for (int u = 0; u < U; ++u) cid[u] = slot(b0, u) < ns ? craw[u] : -1;
         uint4 xv[U][NVB];
-        float xn[U];
+        float xn[U], xs[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = cid[u] < 0 ? 0 : cid[u];
-            const uint4* xr = reinterpret_cast<const uint4*>(Xb + row * d);
+            const uint4* xr = reinterpret_cast<const uint4*>(Xq + row * d * ROWB);
 #pragma unroll
             for (int i = 0; i < NVB; ++i) {
                 const int vi = gl + i * GB;
                 xv[u][i] = xr[vi < nv8 ? vi : 0];
             }
             xn[u] = xnorm[row];
+            xs[u] = FMT == kFmtFp8 ? xscale[row] : 1.0f;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -305,12 +312,21 @@ __global__ __launch_bounds__(256) void dist_bf16_kernel(const float* __restrict_
                                         in ? xv[u][i].w : 0u};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    a = __builtin_fmaf(qf[i][2 * j], bf16_lo(wv[j]), a);
-                    a = __builtin_fmaf(qf[i][2 * j + 1], bf16_hi(wv[j]), a);
+                    if constexpr (FMT == kFmtBf16) {
+                        a = __builtin_fmaf(qf[i][2 * j], bf16_lo(wv[j]), a);
+                        a = __builtin_fmaf(qf[i][2 * j + 1], bf16_hi(wv[j]), a);
+                    } else {
+                        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], false);
+                        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], true);
+                        a = __builtin_fmaf(qf[i][4 * j], lo[0], a);
+                        a = __builtin_fmaf(qf[i][4 * j + 1], lo[1], a);
+                        a = __builtin_fmaf(qf[i][4 * j + 2], hi[0], a);
+                        a = __builtin_fmaf(qf[i][4 * j + 3], hi[1], a);
+                    }
                 }
             }
             const float dot = group_sum<GB>(a);
-            s[u] = (qn + xn[u]) - 2.0f * dot;
+            s[u] = (qn + xn[u]) - 2.0f * (xs[u] * dot);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -516,31 +532,45 @@ hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, int64_t nq, co
     return hipGetLastError();
 }
 
-hipError_t launch_dist_bf16(const mrpt_index* ix, const float* Q, int64_t nq, const int32_t* s_ids, int64_t cap,
-                            const int32_t* s_count, int32_t k, int32_t rerank, float recheck_rel,
-                            int32_t* out_idx, float* out_dist, hipStream_t s) {
+hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, int64_t nq, const int32_t* s_ids,
+                                 int64_t cap, const int32_t* s_count, int32_t k, int32_t rerank, float recheck_rel,
+                                 int32_t* out_idx, float* out_dist, hipStream_t s) {
     if (nq == 0) return hipSuccess;
     const int d = ix->d;
     const int kp = k * rerank;
     const int RB = kp <= 64 ? 1 : kp <= 128 ? 2 : kp <= 256 ? 4 : 8;
     dim3 grid((unsigned)nq), block(256);
-#define MRPT_BF(GB, NVB, RR)                                                                              \
-    hipLaunchKernelGGL((dist_bf16_kernel<GB, NVB, RR>), grid, block, 0, s, ix->X, ix->Xb, ix->xnorm, d, Q, \
-                       s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
-#define MRPT_BF_R(GB, NVB)                 \
-    switch (RB) {                          \
-        case 1: MRPT_BF(GB, NVB, 1); break; \
-        case 2: MRPT_BF(GB, NVB, 2); break; \
-        case 4: MRPT_BF(GB, NVB, 4); break; \
-        default: MRPT_BF(GB, NVB, 8); break; \
+    const uint8_t* Xq = fp8 ? ix->X8 : reinterpret_cast<const uint8_t*>(ix->Xb);
+    const float* norm = fp8 ? ix->norm8 : ix->xnorm;
+#define MRPT_PF(F, GB, NVB, RR, G2, NV2)                                                                           \
+    hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, RR, G2, NV2>), grid, block, 0, s, ix->X, Xq, ix->scale8, \
+                       norm, d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
+#define MRPT_PF_R(F, GB, NVB, G2, NV2)                  \
+    switch (RB) {                                       \
+        case 1: MRPT_PF(F, GB, NVB, 1, G2, NV2); break; \
+        case 2: MRPT_PF(F, GB, NVB, 2, G2, NV2); break; \
+        case 4: MRPT_PF(F, GB, NVB, 4, G2, NV2); break; \
+        default: MRPT_PF(F, GB, NVB, 8, G2, NV2); break; \
     }
-    const int nv8 = d / 8;
-    if (nv8 <= 16) { MRPT_BF_R(16, 1); }
-    else if (nv8 <= 32) { MRPT_BF_R(32, 1); }
-    else if (nv8 <= 64) { MRPT_BF_R(64, 1); }
-    else { MRPT_BF_R(64, 2); }
-#undef MRPT_BF_R
-#undef MRPT_BF
+    if (!fp8) {
+        // bf16 loads per row d/8; the float32 rerank layout follows from it
+        const int nv8 = d / 8;
+        if (nv8 <= 16) { MRPT_PF_R(kFmtBf16, 16, 1, 32, 1); }
+        else if (nv8 <= 32) { MRPT_PF_R(kFmtBf16, 32, 1, 64, 1); }
+        else if (nv8 <= 64) { MRPT_PF_R(kFmtBf16, 64, 1, 64, 2); }
+        else { MRPT_PF_R(kFmtBf16, 64, 2, 64, 4); }
+    } else {
+        // fp8 loads per row d/16 (d % 16 == 0, d <= 1024); rerank as dist_fp32
+        const int nv16 = d / 16, nvec = d / 4;
+        if (nvec <= 16) { MRPT_PF_R(kFmtFp8, 8, 1, 16, 1); }
+        else if (nvec <= 32) { MRPT_PF_R(kFmtFp8, 8, 1, 32, 1); }
+        else if (nvec <= 64) { MRPT_PF_R(kFmtFp8, 16, 1, 64, 1); }
+        else if (nvec <= 128) { MRPT_PF_R(kFmtFp8, 32, 1, 64, 2); }
+        else { MRPT_PF_R(kFmtFp8, 64, 1, 64, 4); }
+        (void)nv16;
+    }
+#undef MRPT_PF_R
+#undef MRPT_PF
     return hipGetLastError();
 }
 

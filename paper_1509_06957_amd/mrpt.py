@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmrpt.so")
 
 MRPT_OK, MRPT_EINVAL, MRPT_ENOMEM, MRPT_EDEVICE, MRPT_ENONFINITE, MRPT_EINTERNAL = 0, -1, -2, -3, -4, -5
-MRPT_FP32, MRPT_BF16_RERANK = 0, 1
+MRPT_FP32, MRPT_BF16_RERANK, MRPT_FP8_RERANK = 0, 1, 2
 _STATUS = {0: "MRPT_OK", -1: "MRPT_EINVAL", -2: "MRPT_ENOMEM", -3: "MRPT_EDEVICE", -4: "MRPT_ENONFINITE",
            -5: "MRPT_EINTERNAL"}
 

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-from gpu_helpers import build, check_knn, dev, leaves, query, recall, votes  # noqa: E402
+from gpu_helpers import build, check_knn, dev, dist64, leaves, query, recall, votes  # noqa: E402
 from paper_1509_06957_amd import mrpt  # noqa: E402
 
 
@@ -335,3 +335,52 @@ def test_gist_like_shape_full_parity(k, precision):
     X, Q = W.data(w), W.queries(w)
     prec = mrpt.MRPT_BF16_RERANK if precision == "bf16" else None
     _full_compare(X, Q, w.T, w.depth, w.a, w.index_seed, k, w.v, precision=prec)
+
+
+def test_fp8_arm_exact_when_rerank_covers_s():
+    # fp8 prefilter + float32 rerank + float64 recheck: when rerank_factor * k
+    # is at least |S| every candidate is reranked, so the arm must return the
+    # oracle's k nearest of S whatever the fp8 rounding did
+    _print_case("fp8 arm, rerank covering S")
+    X, Q = _small(6000, 32, 8, 5, seed=41, nq=70)
+    opts = dict(precision=mrpt.MRPT_FP8_RERANK, rerank_factor=100)
+    gi, gd, ref = _full_compare(X, Q, 8, 5, 0.5, 5, 5, 4, precision=None)
+    g = build(X, 8, 5, 0.5, 5)
+    assert int(ref["s_count"].max()) <= 5 * 100
+    fi, fd, fs = query(g, dev(Q), 5, 4, **opts)
+    assert np.array_equal(fs, ref["s_count"])
+    check_knn(X, Q, fi, fd, ref["idx"], ref["dist"], exact_ids=False,
+              S=[set(s.tolist()) for s in ref["s_ids"]])
+    g.close()
+
+
+@pytest.mark.parametrize("k", [10, 100])
+def test_fp8_arm_gist_like_shape(k):
+    # gist-like rows (d = 960, values in (0, 1)) through the fp8 arm with the
+    # default rerank factor 4: results lie in S, carry float32-exact
+    # distances, are ordered by (distance, id) and padded; their overlap with
+    # the fp32 arm (the fp8 rounding can push a true neighbour out of the
+    # reranked set) is reported
+    w = W.GIST_LIKE.scaled(n=30000, nq=48, T=16, depth=5)
+    _print_case(f"fp8 arm gist-like shape k={k}")
+    X, Q = W.data(w), W.queries(w)
+    g = build(X, w.T, w.depth, w.a, w.index_seed)
+    Qd = dev(Q)
+    ids, _ = votes(g, Qd, w.v, with_counts=False)
+    pi, pd, ps = query(g, Qd, k, w.v)
+    fi, fd, fs = query(g, Qd, k, w.v, precision=mrpt.MRPT_FP8_RERANK)
+    assert np.array_equal(fs, ps)
+    overlap = []
+    for q in range(len(Q)):
+        nreal = min(k, len(ids[q]))
+        real = fi[q][:nreal]
+        assert np.all(fi[q][nreal:] == -1) and np.all(np.isinf(fd[q][nreal:]))
+        assert set(real.tolist()) <= set(ids[q].tolist()) and len(set(real.tolist())) == nreal
+        d64 = dist64(X, Q[q], real)
+        assert np.all(np.abs(fd[q][:nreal].astype(np.float64) - d64) <= 1e-5 * d64 + 1e-6)
+        # ordered by float32 distance, except inside the float64 recheck window
+        # (recheck_rel 1e-6 of the k-th distance), which is ordered by float64
+        assert all(fd[q][r] <= fd[q][r + 1] * (1 + 2e-6) for r in range(nreal - 1))
+        overlap.append(len(set(real.tolist()) & set(pi[q][:nreal].tolist())) / max(nreal, 1))
+    print(f"[fp8] gist-like shape k={k}: mean overlap with the fp32 arm {np.mean(overlap):.4f}", flush=True)
+    g.close()
