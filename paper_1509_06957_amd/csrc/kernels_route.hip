@@ -303,13 +303,18 @@ __global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict
 // ---------------------------------------------------------------------------
 constexpr int kProjWaves = 8;
 
-template <int RPW, bool QLDS>
+// where the query tile is read from: LDS ([feature][query] tile staged by the
+// workgroup), Q row-major in global memory, or its transpose QT (feature-major,
+// QT[c * nq + q]: lanes, one query each, read consecutive words)
+constexpr int kQLds = 0, kQRows = 1, kQTransposed = 2;
+
+template <int RPW, int QMODE>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
                                                                      int32_t d, const int32_t* __restrict__ rowptr,
                                                                      const int32_t* __restrict__ col,
                                                                      const float* __restrict__ val, int32_t nrows,
                                                                      float* __restrict__ Pq) {
-    extern __shared__ float proj_smem[];   // [d][65] when QLDS
+    extern __shared__ float proj_smem[];   // [d][65] when QMODE == kQLds
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
     const int64_t q0 = (int64_t)blockIdx.x * kWave;
@@ -333,12 +338,13 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
             maxlen = len[i] > maxlen ? len[i] : maxlen;
         }
     }
-    if constexpr (QLDS) {
+    if constexpr (QMODE == kQLds) {
         stage_query_tile(Q, q0, nq, d, proj_smem);
         __syncthreads();
     }
     const int64_t q = q0 + lane;
-    const float* qrow = Q + (q < nq ? q : nq - 1) * d;
+    const int64_t qc = q < nq ? q : nq - 1;
+    const float* qrow = Q + qc * d;
     float acc[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) acc[i] = 0.0f;
@@ -349,8 +355,9 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
                 const int c = read_lane_i(colr[i], k);
                 const float v = read_lane_f(valr[i], k);
                 float x;
-                if constexpr (QLDS) x = proj_smem[c * kQStride + lane];
-                else x = qrow[c];
+                if constexpr (QMODE == kQLds) x = proj_smem[c * kQStride + lane];
+                else if constexpr (QMODE == kQRows) x = qrow[c];
+                else x = Q[(int64_t)c * nq + qc];
                 acc[i] = __builtin_fmaf(x, v, acc[i]);
             }
         }
@@ -457,24 +464,59 @@ constexpr int kProjRows = 16;   // rows per wave in project_kernel
 
 }  // namespace
 
+bool project_tile_fits_lds(int32_t d) { return (size_t)d * kQStride * 4 <= 64 * 1024; }
+
 hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32_t row0, int32_t nrows, float* P,
-                          hipStream_t s) {
+                          hipStream_t s, const float* AT) {
     if (m == 0 || nrows == 0) return hipSuccess;
     const int d = ix->d;
-    const size_t q_bytes = (size_t)d * kQStride * 4;
-    const bool qlds = q_bytes <= 64 * 1024;
-    const size_t lds = qlds ? q_bytes : 0;
+    const bool qlds = project_tile_fits_lds(d);
+    const size_t lds = qlds ? (size_t)d * kQStride * 4 : 0;
     dim3 grid((unsigned)((m + kWave - 1) / kWave),
               (unsigned)((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)));
     if (qlds) {
-        (void)hipFuncSetAttribute((const void*)project_kernel<kProjRows, true>,
+        (void)hipFuncSetAttribute((const void*)project_kernel<kProjRows, kQLds>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((project_kernel<kProjRows, true>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,
+        hipLaunchKernelGGL((project_kernel<kProjRows, kQLds>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,
                            ix->rowptr + row0, ix->col, ix->val, nrows, P);
+    } else if (AT) {
+        hipLaunchKernelGGL((project_kernel<kProjRows, kQTransposed>), grid, dim3(kProjWaves * kWave), 0, s, AT, m,
+                           d, ix->rowptr + row0, ix->col, ix->val, nrows, P);
     } else {
-        hipLaunchKernelGGL((project_kernel<kProjRows, false>), grid, dim3(kProjWaves * kWave), 0, s, A, m, d,
+        hipLaunchKernelGGL((project_kernel<kProjRows, kQRows>), grid, dim3(kProjWaves * kWave), 0, s, A, m, d,
                            ix->rowptr + row0, ix->col, ix->val, nrows, P);
     }
+    return hipGetLastError();
+}
+
+namespace {
+
+// AT[c * m + i] = A[i * d + c] through 64 x 64 LDS tiles (padded rows)
+__global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ A, int64_t m, int32_t d,
+                                                        float* __restrict__ AT) {
+    __shared__ float tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int c0 = (int)blockIdx.y * 64;
+    const int tx = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t i = i0 + r;
+        const int c = c0 + tx;
+        tile[r][tx] = (i < m && c < d) ? A[i * d + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int c = c0 + r;
+        const int64_t i = i0 + tx;
+        if (c < d && i < m) AT[(int64_t)c * m + i] = tile[tx][r];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_transpose(const float* A, int64_t m, int32_t d, float* AT, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    dim3 grid((unsigned)((m + 63) / 64), (unsigned)((d + 63) / 64));
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, A, m, d, AT);
     return hipGetLastError();
 }
 
@@ -484,7 +526,15 @@ hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, in
                             hipStream_t s) {
     const int depth = ix->depth;
     {
-        hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s);
+        // a query tile too wide for LDS is read from a transposed copy (after
+        // the projections in the workspace)
+        float* qt = nullptr;
+        if (!project_tile_fits_lds(ix->d) && ix->T * depth > 0) {
+            qt = pq + (size_t)nq * ix->T * depth;
+            hipError_t e = launch_transpose(Q, nq, ix->d, qt, s);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s, qt);
         if (e != hipSuccess) return e;
     }
     const int nsplit = (1 << depth) - 1;
@@ -516,7 +566,9 @@ hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, in
 }  // namespace
 
 size_t route_workspace_floats(const mrpt_index* ix, int64_t nq) {
-    return ix->max_row_nnz <= kWave ? (size_t)nq * ix->T * ix->depth : 0;
+    if (ix->max_row_nnz > kWave) return 0;
+    // projections, then (wide queries) the transposed query batch
+    return (size_t)nq * ix->T * ix->depth + (project_tile_fits_lds(ix->d) ? 0 : (size_t)nq * ix->d);
 }
 
 hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
