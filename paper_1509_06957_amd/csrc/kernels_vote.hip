@@ -218,36 +218,57 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m, uint32_t base) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
 }
 
-// wave-aggregated store of NB ballots (slot g selected the lanes of m[g]) at
-// consecutive places of out, reserved with one LDS atomic on *fill; places at
-// or beyond cap are dropped and reported through *ovf (when given)
-template <int NB>
-__device__ __forceinline__ void append_batch(const uint64_t (&m)[NB], const int32_t (&id)[NB], int* fill,
-                                             int32_t* out, int64_t cap, int* ovf = nullptr) {
+// tot places reserved on the LDS counter *fill, its old value returned to
+// the wave: lane 0 adds tot, lanes 1..63 add 0 to spare words of their own,
+// so the add is one full-wave LDS atomic with no branch around it
+__device__ __forceinline__ uint32_t reserve(int* fill, int* spare, int tot) {
+    const int lane = lane_id();
+    const int old = atomicAdd(lane == 0 ? fill : spare + lane, lane == 0 ? tot : 0);
+    return (uint32_t)__builtin_amdgcn_readfirstlane(old);
+}
+
+// The ids of NB slots whose lanes pass the test (old & bit) != 0 (REPEAT) or
+// == 0 (first occurrence), real ids only (id < n32), stored at consecutive
+// places of out from one reservation on *fill.  Places at or beyond cap are
+// dropped; the caller sees that as *fill > cap.  The per-lane test is written
+// out where it is used: a bool kept across the stores' branches would be
+// rebuilt from a vector 0/1 value.
+template <bool REPEAT, int NB>
+__device__ __forceinline__ void append_batch(const uint32_t (&ob)[NB], const int32_t (&id)[NB], int32_t n32,
+                                             int* fill, int* spare, int32_t* out, uint32_t cap) {
+    uint64_t m[NB];
     int tot = 0;
 #pragma unroll
-    for (int g = 0; g < NB; ++g) tot += __popcll(m[g]);
-    if (tot == 0) return;
-    int base = 0;
-    if (lane_id() == 0) {
-        base = atomicAdd(fill, tot);
-        if (ovf && (int64_t)base + tot > cap) *ovf = 1;
-    }
-    base = __builtin_amdgcn_readfirstlane(base);
-#pragma unroll
     for (int g = 0; g < NB; ++g) {
-        if ((m[g] >> lane_id()) & 1ull) {
-            const uint32_t at = rank_below(m[g], (uint32_t)base);
-            if ((int64_t)at < cap) out[at] = id[g];
+        m[g] = __builtin_amdgcn_ballot_w64(REPEAT ? ob[g] != 0u : ob[g] == 0u) &
+               __builtin_amdgcn_ballot_w64(id[g] < n32);
+        tot += __popcll(m[g]);
+    }
+    if (tot == 0) return;
+    const uint32_t base = reserve(fill, spare, tot);
+    if (base + (uint32_t)tot <= cap) {
+        int32_t* o = out + base;
+#pragma unroll
+        for (int g = 0; g < NB; ++g) {
+            if ((REPEAT ? ob[g] != 0u : ob[g] == 0u) && id[g] < n32) o[rank_below(m[g], 0u)] = id[g];
+            o += __popcll(m[g]);
         }
-        base += __popcll(m[g]);
+    } else {
+        uint32_t at0 = base;
+#pragma unroll
+        for (int g = 0; g < NB; ++g) {
+            if ((REPEAT ? ob[g] != 0u : ob[g] == 0u) && id[g] < n32) {
+                const uint32_t at = rank_below(m[g], at0);
+                if (at < cap) out[at] = id[g];
+            }
+            at0 += (uint32_t)__popcll(m[g]);
+        }
     }
 }
 
 // Per-slot window descriptors of wave w, one slot per lane (lanes >= S
 // unused): row = tree * ld + 64 * part (-1 past the last tree) and
-// tp = tree | 64 * part << 8.  Computed once per kernel; read back per slot
-// with readlane, so the per-query address work is a few scalar adds.
+// tp = tree | 64 * part << 8.  Computed once per kernel.
 __device__ __forceinline__ void slot_table(int w, int T, int wpl, int64_t ld, int& row, int& tp) {
     const int u = w + kVoteWaves * lane_id();
     const int t = u / wpl, part = u - t * wpl;
@@ -255,18 +276,24 @@ __device__ __forceinline__ void slot_table(int w, int T, int wpl, int64_t ld, in
     tp = t < T ? (t | (part * kWave) << 8) : 0;
 }
 
+// the windows of one query, lane s holding slot s's: first = perm index of
+// its first id, avail = ids in it (0 past the last tree).  One LDS read of the
+// query's leaf positions per wave; the slots read these back with readlane.
+__device__ __forceinline__ void slot_windows(const int2* __restrict__ tpos, int slot_row, int slot_tp, int& first,
+                                             int& avail) {
+    const int2 bl = tpos[slot_tp & 255];
+    first = slot_row + bl.x;
+    avail = slot_row < 0 ? 0 : bl.y - (slot_tp >> 8);
+}
+
 template <int S>
-__device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int2* __restrict__ tpos,
-                                             const int32_t* __restrict__ perm, int32_t n32, int slot_row,
-                                             int slot_tp) {
+__device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int32_t* __restrict__ perm, int32_t n32,
+                                             int first_v, int avail_v) {
     const int lane = lane_id();
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const int row = __builtin_amdgcn_readlane(slot_row, s);
-        const int tp = __builtin_amdgcn_readlane(slot_tp, s);
-        const int2 bl = tpos[tp & 255];
-        const int avail = row < 0 ? 0 : uniform(bl.y) - (tp >> 8);   // ids of this window
-        const int first = row + uniform(bl.x);
+        const int first = __builtin_amdgcn_readlane(first_v, s);
+        const int avail = __builtin_amdgcn_readlane(avail_v, s);
         int pad = n32 + lane * 32 + s;
         // keeps the S padding offsets separate: formed as one vector (base +
         // 0..S-1) they are allocated as a single register tuple and spilled
@@ -277,7 +304,7 @@ __device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int2* __re
 }
 
 // LDS: map [map_words] | queue [qcap] | leaf positions [kPosBufs][kMaxT]
-//      (int2) | qfill, nsel, ovf
+//      (int2) | qfill, nsel, 2 unused | kWave spare words
 template <int S, bool QUEUE>
 __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __restrict__ leaf,
                                                               const int32_t* __restrict__ perm,
@@ -293,12 +320,13 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     int* flags = reinterpret_cast<int*>(tpos + kPosBufs);
     int* qfill = flags;
     int* nsel = flags + 1;
-    int* ovf = flags + 2;
+    int* spare = flags + 4;   // kWave words, targets of the reservations' idle lanes
     const int tid = (int)threadIdx.x;
     const int lane = lane_id();
     const int w = uniform(tid >> 6);
     const int clear_vec = map_words >> 2;   // uint4 words of the map
     const int32_t n32 = (int32_t)n;
+    const int32_t cap32 = (int32_t)std::min<int64_t>(cap, INT32_MAX);
     const int64_t G = gridDim.x;
     int64_t q = blockIdx.x;
     if (q >= nq) return;
@@ -324,11 +352,15 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         }
         if (q + 2 * G < nq) Lnext = leaf[(q + 2 * G) * T + tid];
     }
-    if (tid == 0) { *qfill = 0; *nsel = 0; *ovf = 0; }
+    if (tid == 0) { *qfill = 0; *nsel = 0; }
     __syncthreads();
 
     int32_t ids[S], nid[S];
-    load_windows<S>(ids, tpos[0], perm, n32, slot_row, slot_tp);
+    {
+        int first_v, avail_v;
+        slot_windows(tpos[0], slot_row, slot_tp, first_v, avail_v);
+        load_windows<S>(ids, perm, n32, first_v, avail_v);
+    }
     int cur = 0;
     while (true) {
         const int64_t q1 = q + G, q2 = q + 2 * G, q3 = q + 3 * G;
@@ -336,7 +368,11 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         const int b2 = b1 == kPosBufs - 1 ? 0 : b1 + 1;
         // (past the last query the buffer holds stale or empty positions: the
         // loads stay in range and their values are never used)
-        load_windows<S>(nid, tpos[b1], perm, n32, slot_row, slot_tp);
+        {
+            int first_v, avail_v;
+            slot_windows(tpos[b1], slot_row, slot_tp, first_v, avail_v);
+            load_windows<S>(nid, perm, n32, first_v, avail_v);
+        }
         int ob = 0, oe = 0, Lnn = 0;
         if (tid < T) {
             if (q2 < nq) { ob = off[Lnext]; oe = off[Lnext + 1]; }
@@ -345,25 +381,26 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         int32_t* out = s_ids + q * cap;
 
         // the windows through the map: first occurrences (v = 1: S) or repeats
+        // (a batch past slot S - 1 is cut short: its conditions are
+        // compile-time constants once the loops are unrolled)
 #pragma unroll
         for (int s0 = 0; s0 < S; s0 += kMapBatch) {
-            uint32_t old[kMapBatch];
+            constexpr int NB = kMapBatch;
+            uint32_t ob[NB];
+            int32_t bid[NB];
 #pragma unroll
-            for (int g = 0; g < kMapBatch; ++g) {
-                const uint32_t id = (uint32_t)ids[s0 + g];
-                old[g] = atomicOr(&map[id >> 5], 1u << (id & 31u));
+            for (int g = 0; g < NB; ++g) {
+                ob[g] = 0u;
+                bid[g] = n32;   // an absent slot: never real, never stored
+                if (s0 + g < S) {
+                    const uint32_t id = (uint32_t)ids[s0 + g];
+                    const uint32_t bit = 1u << (id & 31u);
+                    ob[g] = atomicOr(&map[id >> 5], bit) & bit;
+                    bid[g] = (int32_t)id;
+                }
             }
-            uint64_t m[kMapBatch];
-            int32_t bid[kMapBatch];
-#pragma unroll
-            for (int g = 0; g < kMapBatch; ++g) {
-                const int32_t id = ids[s0 + g];
-                const bool seen = (old[g] & (1u << (id & 31))) != 0u;
-                m[g] = __ballot((QUEUE ? seen : !seen) && id < n32);
-                bid[g] = id;
-            }
-            if constexpr (QUEUE) append_batch<kMapBatch>(m, bid, qfill, queue, qcap, ovf);
-            else append_batch<kMapBatch>(m, bid, nsel, out, cap);
+            if constexpr (QUEUE) append_batch<true, NB>(ob, bid, n32, qfill, spare, queue, (uint32_t)qcap);
+            else append_batch<false, NB>(ob, bid, n32, nsel, spare, out, (uint32_t)cap32);
         }
         lds_barrier();                        // the map pass of q is complete
         if constexpr (QUEUE) {
@@ -381,10 +418,9 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
                         else first = (atomicOr(&map[(uint32_t)e >> 5], bit) & bit) == 0u;
                         if (first && !last) queue[i] = ~e;     // blanked: one occurrence fewer
                     }
-                    if (last) {
-                        const uint64_t m1[1] = {__ballot(first)};
-                        const int32_t e1[1] = {e};
-                        append_batch<1>(m1, e1, nsel, out, cap);
+                    if (last && first) {
+                        const uint32_t at = (uint32_t)atomicAdd(nsel, 1);
+                        if (at < (uint32_t)cap32) out[at] = e;
                     }
                 }
                 lds_barrier();
@@ -393,16 +429,15 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         // buffer b2 last served the query before q, whose windows are loaded
         if (tid < T && q2 < nq) tpos[b2][tid] = make_int2(ob, oe - ob);
         if (tid == 0) {
-            s_count[q] = *ovf ? -1 : (*nsel < cap ? *nsel : (int32_t)cap);
+            // a queue that overflowed (more reserved than qcap) marks the query
+            s_count[q] = *qfill > qcap ? -1 : (*nsel < cap ? *nsel : (int32_t)cap);
             *qfill = 0;
             *nsel = 0;
-            *ovf = 0;
         }
         for (int i = tid; i < clear_vec; i += kVoteBlock)
             reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
         lds_barrier();
         if (q1 >= nq) break;
-#pragma unroll
         for (int s = 0; s < S; ++s) ids[s] = nid[s];
         Lnext = Lnn;
         cur = b1;
@@ -484,7 +519,7 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     const int wpl = (ix->max_leaf + kWave - 1) / kWave;
     const int64_t slots = ((int64_t)ix->T * wpl + kVoteWaves - 1) / kVoteWaves;
     const int64_t map_words = ((ix->n + kVoteSlots * kWave) / 32 + 1 + 3) / 4 * 4;
-    constexpr size_t kTail = sizeof(int2) * kPosBufs * kMaxT + 16;        // leaf positions, flags
+    constexpr size_t kTail = sizeof(int2) * kPosBufs * kMaxT + 16 + 4 * kWave;   // positions, flags, spare
     const int64_t room = ((int64_t)limit - (int64_t)kTail - map_words * 4) / 4;
     const int64_t qcap = queued ? std::min<int64_t>(room, (int64_t)ix->T * ix->max_leaf) / 4 * 4 : 0;
     const bool single = single_pass_allowed() && slots <= kVoteSlots && ix->n < (int64_t(1) << 24) &&
@@ -502,19 +537,18 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
                            (int32_t)qcap,                                                                        \
                            s_ids, cap, s_count);                                                                 \
     } while (0)
-        if (slots <= 8) {
-            if (queued) MRPT_MAP(8, true);
-            else MRPT_MAP(8, false);
-        } else if (slots <= 16) {
-            if (queued) MRPT_MAP(16, true);
-            else MRPT_MAP(16, false);
-        } else if (slots <= 28) {
-            if (queued) MRPT_MAP(28, true);
-            else MRPT_MAP(28, false);
-        } else {
+        // the smallest instantiated slot count that holds the windows: every
+        // slot costs its loads and map updates even when it is empty
+#define MRPT_MAP_S(SS)                                                                                           \
+    if (slots <= SS) {                                                                                           \
+        if (queued) MRPT_MAP(SS, true);                                                                          \
+        else MRPT_MAP(SS, false);                                                                                \
+    } else
+        MRPT_MAP_S(8) MRPT_MAP_S(13) MRPT_MAP_S(16) MRPT_MAP_S(20) MRPT_MAP_S(25) MRPT_MAP_S(28) {
             if (queued) MRPT_MAP(kVoteSlots, true);
             else MRPT_MAP(kVoteSlots, false);
         }
+#undef MRPT_MAP_S
 #undef MRPT_MAP
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !queued) return e;
