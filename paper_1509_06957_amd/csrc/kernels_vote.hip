@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
 // the last tree, reads the padding entry n + 32 lane + s of perm row 0, which
 // holds that value; such ids are never queued or elected, and their map bits
 // lie in spare words past the ids, a different word for every lane of a slot.
-constexpr int kMapBatch = 4;         // slots whose map updates are issued together
+constexpr int kMapBatch = 5;         // slots whose map updates are issued together
 constexpr int kPosBufs = 3;          // leaf position buffers of the pipeline
 
 // number of set bits of m below this lane, plus base
@@ -300,6 +300,46 @@ __device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int32_t* _
         asm volatile("" : "+v"(pad));
         const int idx = lane < avail ? first + lane : pad;
         dst[s] = perm[(uint32_t)idx];
+    }
+}
+
+// One run over the queue: every id's first remaining occurrence flips its
+// bit (CLEARING: set -> clear, else clear -> set; exactly one occurrence of
+// each id finds the old state) and is blanked (~e), or, on the last run,
+// elected.  Wave w takes entries w * 256 + 4096 j + [0, 256), four per lane:
+// the four loads, then the four atomics, are issued back to back.  Lanes
+// without an entry send a no-op atomic to their own spare word, so no branch
+// surrounds the atomics.
+constexpr int kRerunUnroll = 4;
+
+template <bool CLEARING>
+__device__ __forceinline__ void rerun(uint32_t* map, int32_t* queue, int qn, bool last, int w, int32_t n32,
+                                      int* nsel, int* spare, int32_t* out, uint32_t cap) {
+    constexpr int R = kRerunUnroll;
+    const int lane = lane_id();
+    for (int base = w * kWave * R; base < qn; base += kVoteBlock * R) {   // wave-uniform trip count
+        int32_t e[R];
+        uint32_t f[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = base + j * kWave + lane;
+            e[j] = i < qn ? queue[i] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const bool live = e[j] >= 0;
+            const uint32_t bit = live ? 1u << (e[j] & 31) : 0u;
+            uint32_t* word = live ? &map[(uint32_t)e[j] >> 5] : reinterpret_cast<uint32_t*>(spare + lane);
+            const uint32_t old = CLEARING ? atomicAnd(word, ~bit) : atomicOr(word, bit);
+            f[j] = CLEARING ? (old & bit) : (~old & bit);   // nonzero: the first remaining occurrence
+        }
+        if (!last) {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (f[j] != 0u) queue[base + j * kWave + lane] = ~e[j];
+        } else {
+            append_batch<true, R>(f, e, n32, nsel, spare, out, cap);
+        }
     }
 }
 
@@ -407,22 +447,9 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
             const int qn = min(*qfill, qcap);
             for (int level = 2; level <= v; ++level) {
                 const bool last = level == v;
-                const bool clearing = (level & 1) == 0;   // runs 2, 4, ...: bits start set
-                for (int base = w * kWave; base < qn; base += kVoteBlock) {   // wave-uniform trip count
-                    const int i = base + lane;
-                    const int32_t e = i < qn ? queue[i] : -1;
-                    bool first = false;
-                    if (e >= 0) {
-                        const uint32_t bit = 1u << (e & 31);
-                        if (clearing) first = (atomicAnd(&map[(uint32_t)e >> 5], ~bit) & bit) != 0u;
-                        else first = (atomicOr(&map[(uint32_t)e >> 5], bit) & bit) == 0u;
-                        if (first && !last) queue[i] = ~e;     // blanked: one occurrence fewer
-                    }
-                    if (last && first) {
-                        const uint32_t at = (uint32_t)atomicAdd(nsel, 1);
-                        if (at < (uint32_t)cap32) out[at] = e;
-                    }
-                }
+                // runs 2, 4, ...: the bits of the queued ids start set
+                if ((level & 1) == 0) rerun<true>(map, queue, qn, last, w, n32, nsel, spare, out, (uint32_t)cap32);
+                else rerun<false>(map, queue, qn, last, w, n32, nsel, spare, out, (uint32_t)cap32);
                 lds_barrier();
             }
         }
