@@ -151,6 +151,58 @@ const char* mrpt_last_error(void);
 /* Sizes and parameters of a built index. */
 mrpt_status mrpt_index_info(const mrpt_index* ix, mrpt_index_desc* out);
 
+/* ---------------------------------------------------------------------------
+ * Query plans: many query batches, over any number of indexes, recorded once
+ * as one HIP graph and replayed with a single launch.  Each batch is the
+ * search of Sec. III (Alg. 3-4) exactly as mrpt_query_ex runs it, with the same
+ * kernels, so a batch's results equal mrpt_query_ex's for the same arguments.
+ *
+ * A plan owns a workspace per batch, so batches do not wait for each other:
+ * they are dealt over `branches` independent chains of the graph (balanced by
+ * estimated work), and the GPU may run the chains concurrently.  The plan
+ * keeps the pointers it was given: each launch reads the current contents of
+ * every batch's Q and overwrites its outputs, in the launch stream's order.
+ * The indexes must outlive the plan.  Launches of one plan must not overlap
+ * (they share the workspaces): order them on one stream or synchronise.
+ */
+typedef struct mrpt_batch {
+    const mrpt_index* index;  /* the index searched */
+    const float* Q;           /* device float[nq*d] (d of that index) */
+    int64_t nq;               /* queries of the batch, >= 1 */
+    int32_t k;                /* neighbours per query, as for mrpt_query */
+    int32_t v;                /* vote threshold, as for mrpt_query */
+    int32_t* out_idx;         /* device int32[nq*k] */
+    float* out_dist;          /* device float[nq*k] */
+} mrpt_batch;
+
+typedef struct mrpt_plan_opts {
+    int32_t precision;      /* mrpt_precision of every batch (default MRPT_FP32) */
+    int32_t rerank_factor;  /* as in mrpt_query_opts (default 4) */
+    float recheck_rel;      /* as in mrpt_query_opts (default 1e-6) */
+    int32_t branches;       /* independent chains, 1..64 (default 4) */
+} mrpt_plan_opts;
+
+typedef struct mrpt_plan mrpt_plan;
+
+/* Fills *opts with the defaults above. */
+void mrpt_default_plan_opts(mrpt_plan_opts* opts);
+
+/* Checks every batch as mrpt_query_ex would (MRPT_EINVAL names the first bad
+ * batch), allocates the workspaces (MRPT_ENOMEM) and records the graph.
+ * Synchronous; nothing is computed.  nbatch >= 1.  *out receives the plan. */
+mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mrpt_plan_opts* opts,
+                             mrpt_plan** out);
+
+/* Runs every batch of the plan: one graph launch on `stream` (hipStream_t,
+ * NULL = the null stream).  Asynchronous. */
+mrpt_status mrpt_plan_launch(mrpt_plan* plan, void* stream);
+
+/* Bytes of device memory the plan holds (its workspaces). */
+int64_t mrpt_plan_device_bytes(const mrpt_plan* plan);
+
+/* Releases the plan (after its last launch has completed).  NULL is a no-op. */
+void mrpt_plan_free(mrpt_plan* plan);
+
 /* Debug export of the projection vectors (Sec. II-B), one CSR row per (tree,
  * level) in order tree*depth + level, features ascending.
  *   rowptr : host int32[T*depth + 1];  col : host int32[nnz];  val : host float[nnz]. */

@@ -72,13 +72,28 @@ mrpt_status check_query_args(const mrpt_index* ix, const float* Q, int64_t nq, i
     return MRPT_OK;
 }
 
-// workspace for nb queries at candidate cap `cap` (caller holds ix->mu)
-mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
+// bytes of a query workspace for nb queries at candidate cap `cap`; with
+// base given, also lays the workspace out there (leaf | s_ids | s_count |
+// flag | pq, each 256-byte aligned)
+size_t workspace_layout(const mrpt_index* ix, int64_t nb, int64_t cap, void* base, Workspace* ws) {
     const size_t leaf_b = ((size_t)nb * ix->T * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t ids_b = ((size_t)nb * (size_t)cap * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t cnt_b = ((size_t)nb * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t pq_b = (route_workspace_floats(ix, nb) * sizeof(float) + 255) & ~size_t(255);
-    const size_t need = leaf_b + ids_b + cnt_b + 256 + pq_b;
+    if (base && ws) {
+        char* b = (char*)base;
+        ws->leaf = (int32_t*)b;
+        ws->s_ids = (int32_t*)(b + leaf_b);
+        ws->s_count = (int32_t*)(b + leaf_b + ids_b);
+        ws->flag = (int32_t*)(b + leaf_b + ids_b + cnt_b);
+        ws->pq = pq_b ? (float*)(b + leaf_b + ids_b + cnt_b + 256) : nullptr;
+    }
+    return leaf_b + ids_b + cnt_b + 256 + pq_b;
+}
+
+// workspace for nb queries at candidate cap `cap` (caller holds ix->mu)
+mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
+    const size_t need = workspace_layout(ix, nb, cap, nullptr, nullptr);
     if (!ix->ws.done) MRPT_HIP_TRY(hipEventCreateWithFlags(&ix->ws.done, hipEventDisableTiming));
     if (need > ix->ws.bytes) {
         MRPT_HIP_TRY(hipEventSynchronize(ix->ws.done));
@@ -91,12 +106,7 @@ mrpt_status ensure_workspace(mrpt_index* ix, int64_t nb, int64_t cap) {
         }
         ix->ws.bytes = need;
     }
-    char* b = (char*)ix->ws.base;
-    ix->ws.leaf = (int32_t*)b;
-    ix->ws.s_ids = (int32_t*)(b + leaf_b);
-    ix->ws.s_count = (int32_t*)(b + leaf_b + ids_b);
-    ix->ws.flag = (int32_t*)(b + leaf_b + ids_b + cnt_b);
-    ix->ws.pq = pq_b ? (float*)(b + leaf_b + ids_b + cnt_b + 256) : nullptr;
+    (void)workspace_layout(ix, nb, cap, ix->ws.base, &ix->ws);
     return MRPT_OK;
 }
 
@@ -162,13 +172,8 @@ int64_t batch_size(const mrpt_index* ix, int64_t nq, int64_t cap) {
     return std::min(nq, nb);
 }
 
-mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_t k, int32_t v, int32_t* out_idx,
-                       float* out_dist, const mrpt_query_opts* opts, void* stream) {
-    clear_error();
-    MRPT_TRY(check_query_args(cix, Q, nq, k, v, out_idx, out_dist));
-    mrpt_query_opts o;
-    mrpt_default_opts(&o);
-    if (opts) o = *opts;
+// the precision arm and its parameters against the index
+mrpt_status check_arm(const mrpt_index* cix, int32_t k, const mrpt_query_opts& o) {
     if (o.precision != MRPT_FP32 && o.precision != MRPT_BF16_RERANK && o.precision != MRPT_FP8_RERANK)
         return fail(MRPT_EINVAL, "unknown precision %d", o.precision);
     if (o.precision == MRPT_FP8_RERANK && !cix->X8)
@@ -182,6 +187,43 @@ mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_
         if (cix->d % 8 != 0 || cix->d > 1024)
             return fail(MRPT_EINVAL, "the prefilter arms need d %% 8 == 0 and d <= 1024 (d = %d)", cix->d);
     }
+    return MRPT_OK;
+}
+
+// the kernels of one query batch of m <= workspace queries, in stream order:
+// routing (Alg. 3), voting (Alg. 4), exact search in S.  Kernel launches
+// only (no allocation, copy, memset or synchronisation), so a stream capture
+// can record it.
+hipError_t enqueue_batch(const mrpt_index* ix, const Workspace& ws, const float* Qb, int64_t m, int32_t k,
+                         int32_t v, int64_t cap, const mrpt_query_opts& o, int32_t* out_idx, float* out_dist,
+                         hipStream_t s, bool mark_stages) {
+    auto mark = [&](int i) -> hipError_t {
+        if (!mark_stages || !o.stage_events || !o.stage_events[i]) return hipSuccess;
+        return hipEventRecord((hipEvent_t)o.stage_events[i], s);
+    };
+    hipError_t e;
+    if ((e = mark(0)) != hipSuccess) return e;
+    if ((e = launch_route(ix, Qb, m, ws.leaf, ws.pq, s)) != hipSuccess) return e;
+    if ((e = mark(1)) != hipSuccess) return e;
+    if ((e = launch_vote(ix, ws.leaf, m, v, ws.s_ids, cap, ws.s_count, s)) != hipSuccess) return e;
+    if ((e = mark(2)) != hipSuccess) return e;
+    if (o.precision == MRPT_FP32)
+        e = launch_dist_fp32(ix, Qb, m, ws.s_ids, cap, ws.s_count, k, out_idx, out_dist, s);
+    else
+        e = launch_dist_prefilter(ix, o.precision == MRPT_FP8_RERANK ? 1 : 0, Qb, m, ws.s_ids, cap, ws.s_count, k,
+                                  o.rerank_factor, o.recheck_rel, out_idx, out_dist, s);
+    if (e != hipSuccess) return e;
+    return mark(3);
+}
+
+mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_t k, int32_t v, int32_t* out_idx,
+                       float* out_dist, const mrpt_query_opts* opts, void* stream) {
+    clear_error();
+    MRPT_TRY(check_query_args(cix, Q, nq, k, v, out_idx, out_dist));
+    mrpt_query_opts o;
+    mrpt_default_opts(&o);
+    if (opts) o = *opts;
+    MRPT_TRY(check_arm(cix, k, o));
     if (nq == 0) return MRPT_OK;
     mrpt_index* ix = const_cast<mrpt_index*>(cix);
     hipStream_t s = (hipStream_t)stream;
@@ -199,26 +241,10 @@ mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_
         MRPT_HIP_TRY(hipStreamSynchronize(s));
         if (h) return fail(MRPT_ENONFINITE, "query matrix holds NaN or Inf");
     }
-    auto mark = [&](int64_t q0, int i) -> hipError_t {
-        if (!o.stage_events || q0 != 0 || !o.stage_events[i]) return hipSuccess;
-        return hipEventRecord((hipEvent_t)o.stage_events[i], s);
-    };
     for (int64_t q0 = 0; q0 < nq; q0 += nb) {
         const int64_t m = std::min(nb, nq - q0);
-        const float* Qb = Q + q0 * ix->d;
-        MRPT_HIP_TRY(mark(q0, 0));
-        MRPT_HIP_TRY(launch_route(ix, Qb, m, ix->ws.leaf, ix->ws.pq, s));
-        MRPT_HIP_TRY(mark(q0, 1));
-        MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, m, v, ix->ws.s_ids, cap, ix->ws.s_count, s));
-        MRPT_HIP_TRY(mark(q0, 2));
-        if (o.precision == MRPT_FP32)
-            MRPT_HIP_TRY(launch_dist_fp32(ix, Qb, m, ix->ws.s_ids, cap, ix->ws.s_count, k, out_idx + q0 * k,
-                                          out_dist + q0 * k, s));
-        else
-            MRPT_HIP_TRY(launch_dist_prefilter(ix, o.precision == MRPT_FP8_RERANK ? 1 : 0, Qb, m, ix->ws.s_ids,
-                                               cap, ix->ws.s_count, k, o.rerank_factor, o.recheck_rel,
-                                               out_idx + q0 * k, out_dist + q0 * k, s));
-        MRPT_HIP_TRY(mark(q0, 3));
+        MRPT_HIP_TRY(enqueue_batch(ix, ix->ws, Q + q0 * ix->d, m, k, v, cap, o, out_idx + q0 * k,
+                                   out_dist + q0 * k, s, q0 == 0));
         if (o.s_count) MRPT_HIP_TRY(launch_copy_counts(ix->ws.s_count, m, o.s_count + q0, s));
     }
     MRPT_HIP_TRY(hipEventRecord(ix->ws.done, s));
@@ -240,6 +266,21 @@ mrpt_status fail(mrpt_status st, const char* fmt, ...) {
 void clear_error() { g_error.clear(); }
 
 }  // namespace mrpt
+
+// A recorded query plan: one workspace per batch in one allocation, and the
+// graph of all batches' kernels (chains of batches, one per branch).
+struct mrpt_plan {
+    int device = 0;
+    void* ws_base = nullptr;
+    size_t ws_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~mrpt_plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ws_base) (void)hipFree(ws_base);
+    }
+};
 
 using namespace mrpt;
 
@@ -510,5 +551,139 @@ int64_t mrpt_candidate_cap(const mrpt_index* ix, int32_t v) {
     if (!ix || v < 1) return 0;
     return candidate_cap(ix, v);
 }
+
+void mrpt_default_plan_opts(mrpt_plan_opts* o) {
+    if (!o) return;
+    o->precision = MRPT_FP32;
+    o->rerank_factor = 4;
+    o->recheck_rel = 1e-6f;
+    o->branches = 4;
+}
+
+mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mrpt_plan_opts* opts,
+                             mrpt_plan** out) {
+    clear_error();
+    if (!out) return fail(MRPT_EINVAL, "out is NULL");
+    if (!batches || nbatch < 1) return fail(MRPT_EINVAL, "a plan needs nbatch >= 1 batches");
+    mrpt_plan_opts po;
+    mrpt_default_plan_opts(&po);
+    if (opts) po = *opts;
+    if (po.branches < 1 || po.branches > 64) return fail(MRPT_EINVAL, "branches = %d outside [1, 64]", po.branches);
+    mrpt_query_opts o;
+    mrpt_default_opts(&o);
+    o.precision = (mrpt_precision)po.precision;
+    o.rerank_factor = po.rerank_factor;
+    o.recheck_rel = po.recheck_rel;
+    int dev = 0;
+    MRPT_HIP_TRY(hipGetDevice(&dev));
+
+    // every batch checked as a query call would be; workspace offsets
+    std::vector<int64_t> cap((size_t)nbatch);
+    std::vector<size_t> off((size_t)nbatch);
+    std::vector<double> work((size_t)nbatch);
+    size_t total = 0;
+    for (int32_t i = 0; i < nbatch; ++i) {
+        const mrpt_batch& b = batches[i];
+        mrpt_status st = check_query_args(b.index, b.Q, b.nq, b.k, b.v, b.out_idx, b.out_dist);
+        if (st == MRPT_OK && b.nq < 1) st = fail(MRPT_EINVAL, "nq = %lld < 1", (long long)b.nq);
+        if (st == MRPT_OK) st = check_arm(b.index, b.k, o);
+        if (st == MRPT_OK && b.index->device != dev)
+            st = fail(MRPT_EINVAL, "index on device %d, current device %d", b.index->device, dev);
+        if (st != MRPT_OK) {
+            const std::string why = g_error;
+            return fail(st, "batch %d: %s", i, why.c_str());
+        }
+        cap[i] = candidate_cap(b.index, b.v);
+        off[i] = total;
+        total += workspace_layout(b.index, b.nq, cap[i], nullptr, nullptr);
+        // estimated bytes moved: leaf id lists, and candidate rows (about
+        // T * leaf / v of them)
+        const double ids = (double)b.index->T * b.index->max_leaf;
+        work[i] = (double)b.nq * (4.0 * ids + 4.0 * b.index->d * ids / b.v);
+    }
+
+    std::unique_ptr<mrpt_plan> plan;
+    try {
+        plan.reset(new mrpt_plan());
+    } catch (const std::bad_alloc&) {
+        return fail(MRPT_ENOMEM, "host allocation of the plan");
+    }
+    plan->device = dev;
+    if (hipMalloc(&plan->ws_base, total) != hipSuccess) {
+        (void)hipGetLastError();
+        plan->ws_base = nullptr;
+        return fail(MRPT_ENOMEM, "plan workspaces of %zu bytes", total);
+    }
+    plan->ws_bytes = total;
+
+    // batches dealt to branches, largest first, each to the least loaded
+    std::vector<int32_t> order((size_t)nbatch);
+    for (int32_t i = 0; i < nbatch; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+    const int nbr = std::min<int>(po.branches, nbatch);
+    std::vector<double> load((size_t)nbr, 0.0);
+    std::vector<std::vector<int32_t>> chain((size_t)nbr);
+    for (int32_t i : order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += work[i];
+        chain[b].push_back(i);
+    }
+
+    // record: fork from an origin stream to one stream per branch, every
+    // branch's batches in sequence, join back
+    std::vector<hipStream_t> bs((size_t)nbr, nullptr);
+    std::vector<hipEvent_t> ev((size_t)nbr + 1, nullptr);
+    hipStream_t origin = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&origin, hipStreamNonBlocking);
+    for (int b = 0; b < nbr && e == hipSuccess; ++b) e = hipStreamCreateWithFlags(&bs[b], hipStreamNonBlocking);
+    for (int b = 0; b <= nbr && e == hipSuccess; ++b) e = hipEventCreateWithFlags(&ev[b], hipEventDisableTiming);
+    bool capturing = false;
+    if (e == hipSuccess) {
+        e = hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed);
+        capturing = e == hipSuccess;
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[nbr], origin);
+    for (int b = 0; b < nbr && e == hipSuccess; ++b) e = hipStreamWaitEvent(bs[b], ev[nbr], 0);
+    for (int b = 0; b < nbr && e == hipSuccess; ++b) {
+        for (int32_t i : chain[b]) {
+            const mrpt_batch& bt = batches[i];
+            Workspace ws;
+            (void)workspace_layout(bt.index, bt.nq, cap[i], (char*)plan->ws_base + off[i], &ws);
+            e = enqueue_batch(bt.index, ws, bt.Q, bt.nq, bt.k, bt.v, cap[i], o, bt.out_idx, bt.out_dist, bs[b],
+                              false);
+            if (e != hipSuccess) break;
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev[b], bs[b]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(origin, ev[b], 0);
+    }
+    if (capturing) {
+        const hipError_t e2 = hipStreamEndCapture(origin, &plan->graph);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    for (hipStream_t x : bs)
+        if (x) (void)hipStreamDestroy(x);
+    if (origin) (void)hipStreamDestroy(origin);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MRPT_EDEVICE, "recording the plan: %s", hipGetErrorString(e));
+    }
+    *out = plan.release();
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_plan_launch(mrpt_plan* plan, void* stream) {
+    clear_error();
+    if (!plan || !plan->exec) return fail(MRPT_EINVAL, "plan is NULL");
+    MRPT_HIP_TRY(hipSetDevice(plan->device));
+    MRPT_HIP_TRY(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    return MRPT_OK;
+}
+
+int64_t mrpt_plan_device_bytes(const mrpt_plan* plan) { return plan ? (int64_t)plan->ws_bytes : 0; }
+
+void mrpt_plan_free(mrpt_plan* plan) { delete plan; }
 
 }  // extern "C"

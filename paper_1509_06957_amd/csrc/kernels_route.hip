@@ -219,7 +219,6 @@ __global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict
     const int w = uniform((int)(threadIdx.x >> 6));
     const int t = uniform((int)blockIdx.y * trees_per_block + w);
     const bool tree_ok = t < T;
-    const int nthreads = (int)blockDim.x;
     const int t_first = (int)blockIdx.y * trees_per_block;
 
     if constexpr (SPLITS_LDS) stage_splits(splits, sp, T, t_first, trees_per_block, nsplit);

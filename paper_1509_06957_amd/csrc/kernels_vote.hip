@@ -362,7 +362,6 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     int* nsel = flags + 1;
     int* spare = flags + 4;   // kWave words, targets of the reservations' idle lanes
     const int tid = (int)threadIdx.x;
-    const int lane = lane_id();
     const int w = uniform(tid >> 6);
     const int clear_vec = map_words >> 2;   // uint4 words of the map
     const int32_t n32 = (int32_t)n;
@@ -579,6 +578,10 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
 #undef MRPT_MAP
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !queued) return e;
+        // a query queues sum(F - 1) <= T * max_leaf - (its first leaf's size)
+        // ids; when the queue holds that many, none can overflow
+        const int64_t most = (int64_t)ix->T * ix->max_leaf - ix->n / ((int64_t)1 << ix->depth);
+        if (qcap >= most) return e;
         // queries whose queue overflowed (count -1) are counted again, multi-pass
     }
     (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize,

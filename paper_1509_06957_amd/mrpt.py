@@ -42,12 +42,23 @@ class mrpt_index_desc(ctypes.Structure):
                 ("max_leaf", ctypes.c_int32), ("id_chunk", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
+class mrpt_batch(ctypes.Structure):
+    _fields_ = [("index", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("nq", ctypes.c_int64), ("k", ctypes.c_int32),
+                ("v", ctypes.c_int32), ("out_idx", ctypes.c_void_p), ("out_dist", ctypes.c_void_p)]
+
+
+class mrpt_plan_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rerank_factor", ctypes.c_int32), ("recheck_rel", ctypes.c_float),
+                ("branches", ctypes.c_int32)]
+
+
 _lib = None
 
 EXPORTED = [
     "mrpt_build", "mrpt_build_ex", "mrpt_default_build_opts", "mrpt_query", "mrpt_query_ex", "mrpt_default_opts", "mrpt_free", "mrpt_last_error",
     "mrpt_index_info", "mrpt_export_projection", "mrpt_export_tree", "mrpt_export_leaf_offsets",
     "mrpt_debug_leaves", "mrpt_debug_votes", "mrpt_candidate_cap",
+    "mrpt_default_plan_opts", "mrpt_plan_create", "mrpt_plan_launch", "mrpt_plan_device_bytes", "mrpt_plan_free",
 ]
 
 
@@ -82,9 +93,19 @@ def load(path: str = LIB_PATH):
     lib.mrpt_debug_votes.argtypes = [vp, vp, i64, i32, vp, vp, vp, i64, vp]
     lib.mrpt_candidate_cap.argtypes = [vp, i32]
     lib.mrpt_candidate_cap.restype = i64
+    lib.mrpt_default_plan_opts.argtypes = [ctypes.POINTER(mrpt_plan_opts)]
+    lib.mrpt_default_plan_opts.restype = None
+    lib.mrpt_plan_create.argtypes = [ctypes.POINTER(mrpt_batch), i32, ctypes.POINTER(mrpt_plan_opts),
+                                     ctypes.POINTER(vp)]
+    lib.mrpt_plan_launch.argtypes = [vp, vp]
+    lib.mrpt_plan_device_bytes.argtypes = [vp]
+    lib.mrpt_plan_device_bytes.restype = i64
+    lib.mrpt_plan_free.argtypes = [vp]
+    lib.mrpt_plan_free.restype = None
     for name in EXPORTED:
         if name not in ("mrpt_default_opts", "mrpt_default_build_opts", "mrpt_free", "mrpt_last_error",
-                        "mrpt_candidate_cap"):
+                        "mrpt_candidate_cap", "mrpt_default_plan_opts", "mrpt_plan_device_bytes",
+                        "mrpt_plan_free"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -208,6 +229,74 @@ def mrpt_debug_votes(ix, Q, v: int, s_count, s_ids, s_votes, cap: int, stream=No
 
 def mrpt_candidate_cap(ix, v: int) -> int:
     return int(load().mrpt_candidate_cap(ix, v))
+
+
+def mrpt_default_plan_opts() -> mrpt_plan_opts:
+    o = mrpt_plan_opts()
+    load().mrpt_default_plan_opts(ctypes.byref(o))
+    return o
+
+
+def mrpt_plan_create(batches, opts: Optional[mrpt_plan_opts] = None) -> ctypes.c_void_p:
+    """batches: sequence of (index handle, Q, k, v, out_idx, out_dist) with torch
+    CUDA tensors; returns the plan handle.  The tensors must outlive the plan."""
+    arr = (mrpt_batch * len(batches))()
+    for i, (ix, Q, k, v, out_idx, out_dist) in enumerate(batches):
+        arr[i] = mrpt_batch(ix, _dev(Q, "float32"), Q.shape[0], k, v, _dev(out_idx, "int32"),
+                            _dev(out_dist, "float32"))
+    h = ctypes.c_void_p()
+    _check(load().mrpt_plan_create(arr, len(batches), None if opts is None else ctypes.byref(opts),
+                                   ctypes.byref(h)))
+    return h
+
+
+def mrpt_plan_launch(plan, stream=None):
+    _check(load().mrpt_plan_launch(plan, _stream(stream)))
+
+
+def mrpt_plan_device_bytes(plan) -> int:
+    return int(load().mrpt_plan_device_bytes(plan))
+
+
+def mrpt_plan_free(plan):
+    if plan:
+        load().mrpt_plan_free(plan)
+
+
+class Plan:
+    """Owning wrapper of a query plan over (Index, Q, k, v) batches; results
+    land in self.out[i] = (idx, dist) at every launch()."""
+
+    def __init__(self, batches, precision: int = MRPT_FP32, rerank_factor: int = 4, recheck_rel: float = 1e-6,
+                 branches: int = 4):
+        import torch
+        self.handle = None
+        self.batches = list(batches)
+        self.out = [(torch.empty((Q.shape[0], k), dtype=torch.int32, device=Q.device),
+                     torch.empty((Q.shape[0], k), dtype=torch.float32, device=Q.device))
+                    for (_, Q, k, _) in self.batches]
+        o = mrpt_default_plan_opts()
+        o.precision, o.rerank_factor, o.recheck_rel, o.branches = precision, rerank_factor, recheck_rel, branches
+        self.handle = mrpt_plan_create([(ix.handle, Q, k, v, oi, od) for (ix, Q, k, v), (oi, od)
+                                        in zip(self.batches, self.out)], o)
+
+    def launch(self, stream=None):
+        mrpt_plan_launch(self.handle, stream)
+        return self.out
+
+    def device_bytes(self) -> int:
+        return mrpt_plan_device_bytes(self.handle)
+
+    def close(self):
+        if self.handle:
+            mrpt_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Index:

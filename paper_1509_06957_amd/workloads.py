@@ -11,6 +11,9 @@ for them with the stated shapes and value distributions:
   sift-like    : n=1,000,000, d=128 8-bit descriptors, Gamma(0.5, 40) marginals,
                  intrinsic dimension about 10
   gist-like    : n=1,000,000, d=960 sigmoid of a Gaussian mixture (GIST shape)
+  batched      : 16 Gaussian-mixture indexes of uneven size (n log-uniform in
+                 [10k, 500k], d in {128, 256, 784}) and a stream of 50,000
+                 queries in batches of 1..4096, each batch for one index
 """
 from dataclasses import dataclass, field
 from typing import Optional
@@ -173,3 +176,103 @@ SIFT_LIKE = Workload("sift-like (n=1M, d=128)", 1_000_000, 128, 10_000, 100, 12,
 GIST_LIKE = Workload("gist-like (n=1M, d=960)", 1_000_000, 960, 10_000, 200, 10, 10, 5, "gist_like", 104, 204, 304)
 
 ALL = {"mixture128": MIXTURE_128, "mnist_like": MNIST_LIKE, "sift_like": SIFT_LIKE, "gist_like": GIST_LIKE}
+
+
+# ---------------------------------------------------------------------------
+# batched: many indexes of uneven size and a stream of mixed query batches
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class BatchedWorkload:
+    name: str = "batched (16 indexes, 50k queries)"
+    n_indexes: int = 16
+    n_lo: int = 10_000
+    n_hi: int = 500_000
+    dims: tuple = (128, 256, 784)
+    T: int = 64
+    leaf_target: int = 32        # depth = round(log2(n / leaf_target))
+    total_queries: int = 50_000
+    max_batch: int = 4096
+    ks: tuple = (1, 10, 100)
+    v: int = 3
+    seed: int = 105
+
+    def scaled(self, **kw) -> "BatchedWorkload":
+        vals = dict(self.__dict__)
+        vals.update(kw)
+        return BatchedWorkload(**vals)
+
+
+@dataclass(frozen=True)
+class IndexSpec:
+    no: int
+    n: int
+    d: int
+    depth: int
+    data_seed: int
+    center_seed: int
+    index_seed: int
+
+    @property
+    def a(self) -> float:
+        return float(np.float32(1.0 / np.sqrt(self.d)))
+
+
+def batched_indexes(bw: BatchedWorkload):
+    """The index specs: n log-uniform in [n_lo, n_hi], d uniform over dims,
+    depth so that leaves hold about leaf_target points."""
+    rng = np.random.Generator(np.random.PCG64(bw.seed))
+    out = []
+    for i in range(bw.n_indexes):
+        n = int(round(float(np.exp(rng.uniform(np.log(bw.n_lo), np.log(bw.n_hi))))))
+        d = int(bw.dims[int(rng.integers(0, len(bw.dims)))])
+        depth = max(0, int(round(float(np.log2(n / bw.leaf_target)))))
+        while (1 << depth) > n:
+            depth -= 1
+        out.append(IndexSpec(i, n, d, depth, bw.seed * 1000 + 2 * i, bw.seed * 1000 + 2 * i + 1,
+                             bw.seed * 1000 + 500 + i))
+    return out
+
+
+def _mixture_f32(rng, m, centers):
+    """m rows: a uniformly chosen center plus unit Gaussian noise (float32)."""
+    comp = rng.integers(0, len(centers), size=m)
+    out = rng.standard_normal((m, centers.shape[1]), dtype=np.float32)
+    out += centers[comp]
+    return out
+
+
+def _centers(spec: IndexSpec):
+    crng = np.random.Generator(np.random.PCG64(spec.center_seed))
+    return (crng.standard_normal((32, spec.d)) * 2.0).astype(np.float32)
+
+
+def batched_index_data(spec: IndexSpec) -> np.ndarray:
+    """n x d data of one index: a 32-component Gaussian mixture, means
+    N(0, 4 I), unit isotropic covariance."""
+    rng = np.random.Generator(np.random.PCG64(spec.data_seed))
+    return _mixture_f32(rng, spec.n, _centers(spec))
+
+
+def batched_stream(bw: BatchedWorkload):
+    """The query stream: (batch number, index number, size, k) with sizes
+    round(exp(U[0, ln max_batch])) until total_queries are drawn (the last
+    batch cut to fit), a uniformly chosen index and k per batch."""
+    rng = np.random.Generator(np.random.PCG64(bw.seed + 100))
+    out, total = [], 0
+    while total < bw.total_queries:
+        m = int(round(float(np.exp(rng.uniform(0.0, np.log(bw.max_batch))))))
+        m = max(1, min(m, bw.total_queries - total))
+        ix = int(rng.integers(0, bw.n_indexes))
+        k = int(bw.ks[int(rng.integers(0, len(bw.ks)))])
+        out.append((len(out), ix, m, k))
+        total += m
+    return out
+
+
+def batched_queries(bw: BatchedWorkload, spec: IndexSpec, batch_no: int, m: int) -> np.ndarray:
+    """m queries of one batch, drawn independently from its index's mixture."""
+    rng = np.random.Generator(np.random.PCG64(bw.seed * 1000 + 10_000 + batch_no))
+    return _mixture_f32(rng, m, _centers(spec))
+
+
+BATCHED = BatchedWorkload()

@@ -47,3 +47,46 @@ def test_error_path_without_gpu():
     assert "data" in mrpt.mrpt_last_error()
     st = lib.mrpt_query(None, None, 1, 1, 1, None, None, None)
     assert st == mrpt.MRPT_EINVAL
+
+
+def test_plan_structs_match_header_layout():
+    from paper_1509_06957_amd import mrpt
+    # mrpt_batch: index, Q pointers; int64 nq; int32 k, v; two pointers
+    assert ctypes.sizeof(mrpt.mrpt_batch) == 8 + 8 + 8 + 4 + 4 + 8 + 8
+    assert mrpt.mrpt_batch.k.offset == 24 and mrpt.mrpt_batch.out_idx.offset == 32
+    assert ctypes.sizeof(mrpt.mrpt_plan_opts) == 16
+
+
+def test_plan_error_paths_without_gpu():
+    from paper_1509_06957_amd import mrpt
+    lib = mrpt.load()
+    o = mrpt.mrpt_plan_opts()
+    lib.mrpt_default_plan_opts(ctypes.byref(o))
+    assert (o.precision, o.rerank_factor, o.branches) == (mrpt.MRPT_FP32, 4, 4)
+    h = ctypes.c_void_p()
+    assert lib.mrpt_plan_create(None, 0, None, ctypes.byref(h)) == mrpt.MRPT_EINVAL
+    assert "nbatch" in mrpt.mrpt_last_error()
+    arr = (mrpt.mrpt_batch * 1)()
+    assert lib.mrpt_plan_create(arr, 1, None, None) == mrpt.MRPT_EINVAL
+    o.branches = 0
+    assert lib.mrpt_plan_create(arr, 1, ctypes.byref(o), ctypes.byref(h)) == mrpt.MRPT_EINVAL
+    assert "branches" in mrpt.mrpt_last_error()
+    assert lib.mrpt_plan_launch(None, None) == mrpt.MRPT_EINVAL
+    assert lib.mrpt_plan_device_bytes(None) == 0
+    lib.mrpt_plan_free(None)
+
+
+def test_batched_workload_stream():
+    """The batched workload's stream covers the stated number of queries in
+    batches of 1..max_batch, with every index and k drawn from their sets."""
+    from paper_1509_06957_amd import workloads as W
+    bw = W.BATCHED
+    specs = W.batched_indexes(bw)
+    assert len(specs) == bw.n_indexes
+    for sp in specs:
+        assert bw.n_lo <= sp.n <= bw.n_hi and sp.d in bw.dims
+        assert (1 << sp.depth) <= sp.n and 16 <= sp.n / (1 << sp.depth) <= 64
+    st = W.batched_stream(bw)
+    assert sum(m for _, _, m, _ in st) == bw.total_queries
+    assert all(1 <= m <= bw.max_batch and 0 <= ix < bw.n_indexes and k in bw.ks for _, ix, m, k in st)
+    assert [b for b, _, _, _ in st] == list(range(len(st)))

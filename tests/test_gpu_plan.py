@@ -1,0 +1,128 @@
+"""GPU parity of query plans: many batches over several indexes of uneven
+size, recorded as one HIP graph and replayed.
+
+  * every batch's results equal mrpt_query_ex's for the same arguments,
+    bit for bit (the plan runs the same kernels), at every replay, with eager
+    work and synchronisation between the replays;
+  * a replay reads the current contents of the query buffers;
+  * one branch or several give the same results;
+  * the results agree with the oracle under the query path's tolerances.
+
+Workload: the batched workload scaled down to 3 indexes (n in [2k, 20k],
+d in {128, 256, 784}, T = 64, leaves of about 32) and 600 queries in batches of
+1..150 with k in {1, 10, 100} (k = 100 pads where |S| < 100), v = 3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_06957_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_helpers import check_knn, dev  # noqa: E402
+from paper_1509_06957_amd import mrpt  # noqa: E402
+
+SMALL = W.BATCHED.scaled(n_indexes=3, n_lo=2_000, n_hi=20_000, total_queries=600, max_batch=150)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    print(f"[case] plan setup {SMALL}", flush=True)
+    specs = W.batched_indexes(SMALL)
+    X = [W.batched_index_data(sp) for sp in specs]
+    ixs = [mrpt.Index(dev(x), SMALL.T, sp.depth, sp.a, sp.index_seed) for sp, x in zip(specs, X)]
+    stream = W.batched_stream(SMALL)
+    Qh = [W.batched_queries(SMALL, specs[ix], b, m) for b, ix, m, _ in stream]
+    Qs = [dev(q) for q in Qh]
+    yield specs, X, ixs, stream, Qh, Qs
+    for ix in ixs:
+        ix.close()
+
+
+def eager(ixs, stream, Qs, precision):
+    out = [ixs[ix].query(Q, k, SMALL.v, precision=precision) for (_, ix, _, k), Q in zip(stream, Qs)]
+    torch.cuda.synchronize()
+    return [(i.cpu().numpy(), d.cpu().numpy()) for i, d in out]
+
+
+def same(out, ref, what):
+    for j, ((oi, od), (ri, rd)) in enumerate(zip(out, ref)):
+        oi, od = oi.cpu().numpy(), od.cpu().numpy()
+        assert np.array_equal(oi, ri), f"{what}: batch {j} ids"
+        assert np.array_equal(od.view(np.uint32), rd.view(np.uint32)), f"{what}: batch {j} distances"
+
+
+@pytest.mark.parametrize("precision", [mrpt.MRPT_FP32, mrpt.MRPT_BF16_RERANK])
+@pytest.mark.parametrize("branches", [1, 5])
+def test_plan_equals_query_calls(setup, precision, branches):
+    _, _, ixs, stream, _, Qs = setup
+    print(f"[case] plan precision={precision} branches={branches} batches={len(stream)}", flush=True)
+    ref = eager(ixs, stream, Qs, precision)
+    plan = mrpt.Plan([(ixs[ix], Q, k, SMALL.v) for (_, ix, _, k), Q in zip(stream, Qs)],
+                     precision=precision, branches=branches)
+    assert plan.device_bytes() > 0
+    for rep in range(3):
+        out = plan.launch()
+        torch.cuda.synchronize()
+        same(out, ref, f"replay {rep}")
+        for o in out:                       # stale results must not survive a replay
+            o[0].fill_(-7)
+            o[1].fill_(-7.0)
+        ref = eager(ixs, stream, Qs, precision)
+    plan.close()
+
+
+def test_plan_reads_current_queries(setup):
+    _, _, ixs, stream, _, Qs = setup
+    print("[case] plan replay after the query buffers change", flush=True)
+    plan = mrpt.Plan([(ixs[ix], Q, k, SMALL.v) for (_, ix, _, k), Q in zip(stream, Qs)], branches=3)
+    plan.launch()
+    saved = [Q.clone() for Q in Qs]
+    try:
+        for Q in Qs:
+            Q.copy_(torch.flip(Q, dims=[0]) * 0.5)
+        ref = eager(ixs, stream, Qs, mrpt.MRPT_FP32)
+        out = plan.launch()
+        torch.cuda.synchronize()
+        same(out, ref, "changed queries")
+    finally:
+        for Q, s in zip(Qs, saved):
+            Q.copy_(s)
+        torch.cuda.synchronize()
+        plan.close()
+
+
+def test_plan_matches_oracle(setup):
+    specs, X, ixs, stream, Qh, Qs = setup
+    print("[case] plan against the oracle", flush=True)
+    plan = mrpt.Plan([(ixs[ix], Q, k, SMALL.v) for (_, ix, _, k), Q in zip(stream, Qs)], branches=4)
+    out = plan.launch()
+    torch.cuda.synchronize()
+    orc = {}
+    for (b, ix, m, k), Qb, (gi, gd) in zip(stream, Qh, out):
+        sp = specs[ix]
+        if ix not in orc:
+            orc[ix] = oracle.build_index(X[ix], SMALL.T, sp.depth, sp.a, sp.index_seed)
+        ref = oracle.query(orc[ix], Qb, k, SMALL.v, want_sets=True)
+        S = [set(s.tolist()) for s in ref["s_ids"]]
+        check_knn(X[ix], Qb, gi.cpu().numpy(), gd.cpu().numpy(), ref["idx"], ref["dist"], exact_ids=False, S=S)
+    plan.close()
+
+
+def test_plan_rejects_bad_batch(setup):
+    _, _, ixs, stream, _, Qs = setup
+    (_, ix, _, k), Q = stream[0], Qs[0]
+    with pytest.raises(mrpt.MrptError, match="batch 1"):
+        mrpt.Plan([(ixs[ix], Q, k, SMALL.v), (ixs[ix], Q, k, SMALL.T + 1)])
+    with pytest.raises(mrpt.MrptError, match="d % 8"):
+        bad = W.BATCHED.scaled(n_indexes=1, n_lo=300, n_hi=300, dims=(12,))
+        sp = W.batched_indexes(bad)[0]
+        tiny = mrpt.Index(dev(W.batched_index_data(sp)), 4, 2, sp.a, 1)
+        try:
+            q = dev(W.batched_queries(bad, sp, 0, 3))
+            mrpt.Plan([(tiny, q, 1, 1)], precision=mrpt.MRPT_BF16_RERANK)
+        finally:
+            tiny.close()
