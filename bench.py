@@ -42,6 +42,7 @@ def parse():
     p.add_argument("--workload", default="sift_like")
     p.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     p.add_argument("--recall-sample", type=int, default=500)
+    p.add_argument("--latency-reps", type=int, default=50, help="timed calls per batch size")
     p.add_argument("--cpu-sample", type=int, default=10000)
     p.add_argument("--no-host-build", action="store_true", help="skip timing the host build of the index")
     return p.parse_args()
@@ -245,6 +246,27 @@ def main():
         "copy_GBps": round(copy_gbps, 1),
     }
 
+    # latency of one query call (fp32 arm, all five steps) per batch size:
+    # host clock around the call and a synchronisation, inputs resident
+    latency = {}
+    for b in (1, 16, 256, 4096):
+        if b > nq:
+            continue
+        ob = (torch.empty((b, k), dtype=torch.int32, device="cuda"),
+              torch.empty((b, k), dtype=torch.float32, device="cuda"))
+        Qb = Qd[:b].contiguous()
+        ts = []
+        for r in range(args.latency_reps + 5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mrpt.mrpt_query(ix.handle, Qb, k, v, ob[0], ob[1])
+            torch.cuda.synchronize()
+            if r >= 5:
+                ts.append((time.perf_counter() - t0) * 1e3)
+        latency[str(b)] = {"p50_ms": round(float(np.percentile(ts, 50)), 4),
+                           "p99_ms": round(float(np.percentile(ts, 99)), 4), "reps": len(ts)}
+    log(f"latency (ms, p50/p99): " + ", ".join(f"{b}: {x['p50_ms']}/{x['p99_ms']}" for b, x in latency.items()))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle   # the CPU baseline: the oracle timed on this host
@@ -263,6 +285,14 @@ def main():
                "sample": f"first {m} of the {nq} queries x {reps} passes, oracle index of the same "
                          f"seed, {el:.2f}s wall on {nth} host threads"}
         log(f"oracle: {m * reps / el:.1f} queries/s ({reps} passes)")
+        # the same oracle on one host thread, over a prefix sized to about 3 s
+        m1 = max(1, min(nq, int(3.0 * m * reps / el / nth)))
+        t0 = time.perf_counter()
+        oracle.query(orc, Q[:m1], k, v, nthreads=1)
+        el1 = time.perf_counter() - t0
+        cpu["one_core"] = {"value": round(m1 / el1, 1), "unit": "queries/s", "cores": 1,
+                           "sample": f"first {m1} queries, one pass, {el1:.2f}s wall on 1 host thread"}
+        log(f"oracle on one thread: {m1 / el1:.1f} queries/s")
 
     rec = {
         "metric": METRIC,
@@ -308,6 +338,7 @@ def main():
                   "projection_fma": int(w.n) * nnz,
                   "note": "device: projection kernel + per-level segmented sort; host: threads over trees"},
         "recall_sample": len(rs),
+        "latency": latency,
     }
     ix.close()
     print(json.dumps(rec), flush=True)

@@ -11,6 +11,7 @@ for them with the stated shapes and value distributions:
   sift-like    : n=1,000,000, d=128 8-bit descriptors, Gamma(0.5, 40) marginals,
                  intrinsic dimension about 10
   gist-like    : n=1,000,000, d=960 sigmoid of a Gaussian mixture (GIST shape)
+  random       : n=50,000, d=4,096 unit-norm Gaussian (the paper's own Random set)
   batched      : 16 Gaussian-mixture indexes of uneven size (n log-uniform in
                  [10k, 500k], d in {128, 256, 784}) and a stream of 50,000
                  queries in batches of 1..4096, each batch for one index
@@ -148,7 +149,19 @@ def _gen_gist_like(w: Workload, rng, m, center_seed):
     return out
 
 
+def _gen_random_unit(w: Workload, rng, m, center_seed):
+    """Gaussian vectors scaled to unit Euclidean norm (the paper's Random set)."""
+    out = np.empty((m, w.d), dtype=np.float32)
+    step = 4096
+    for s in range(0, m, step):
+        b = min(step, m - s)
+        z = rng.standard_normal((b, w.d))
+        out[s:s + b] = z / np.linalg.norm(z, axis=1, keepdims=True)
+    return out
+
+
 _GEN = {
+    "random_unit": _gen_random_unit,
     "mixture128": _gen_mixture128,
     "mnist_like": _gen_mnist_like,
     "sift_like": _gen_sift_like,
@@ -175,7 +188,11 @@ SIFT_LIKE = Workload("sift-like (n=1M, d=128)", 1_000_000, 128, 10_000, 100, 12,
                      {"latent_dim": 10, "noise": 0.2})
 GIST_LIKE = Workload("gist-like (n=1M, d=960)", 1_000_000, 960, 10_000, 200, 10, 10, 5, "gist_like", 104, 204, 304)
 
-ALL = {"mixture128": MIXTURE_128, "mnist_like": MNIST_LIKE, "sift_like": SIFT_LIKE, "gist_like": GIST_LIKE}
+# the paper's own synthetic set (Sec. IV): 50,000 unit-norm Gaussian vectors in 4,096 dimensions
+RANDOM = Workload("random (n=50k, d=4096)", 50_000, 4096, 1_000, 50, 8, 10, 2, "random_unit", 107, 207, 307)
+
+ALL = {"mixture128": MIXTURE_128, "mnist_like": MNIST_LIKE, "sift_like": SIFT_LIKE, "gist_like": GIST_LIKE,
+       "random": RANDOM}
 
 
 # ---------------------------------------------------------------------------
