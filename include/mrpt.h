@@ -112,9 +112,15 @@ typedef struct {
                               and takes scratch device memory of about n*(4*depth + 16) bytes
                               per tree of a group (groups sized to MRPT_BUILD_LIMIT bytes,
                               default 8 GiB). */
+    int32_t exact_nnz;     /* 0 (default): each entry of a projection vector is nonzero with
+                              probability a (Sec. II-B).  1: every vector has exactly
+                              m = ceil(a*d) nonzeros (the variant of the Sec. II-D footnote):
+                              the m features whose selection uniform is smallest, ties by
+                              feature; values as in the default mode.  With a = 1 both
+                              modes give the same vectors. */
 } mrpt_build_opts;
 
-/* Default build options (on_device = 1). */
+/* Default build options (on_device = 1, exact_nnz = 0). */
 void mrpt_default_build_opts(mrpt_build_opts* opts);
 
 /* mrpt_build with options (opts = NULL: the defaults). */

@@ -21,6 +21,8 @@
  *   - the generator is Philox4x64-10 (Salmon et al., SC'11) keyed by
  *     (seed, 0) with counter (i, level, tree, 0); word 0 decides the
  *     Bernoulli(a) draw, words 1 and 2 feed a Box-Muller normal in double;
+ *   - exact-count mode (footnote of Sec. II-D): the ceil(a d) features with
+ *     the smallest word-0 uniforms (ties by feature) are the nonzeros;
  *   - projections are float32, one fused multiply-add per nonzero in
  *     ascending feature order starting from +0;
  *   - ties in a node are broken by point id (sort key (projection, id)); the
@@ -93,6 +95,66 @@ void oracle_random_matrix(int32_t d, int32_t T, int32_t depth, float a, uint64_t
                 }
                 R[((int64_t)t * depth + lv) * d + i] = r;
             }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact-count variant (the footnote of Sec. II-D): every vector has exactly   */
+/* m = ceil(a d) nonzero entries instead of a Bernoulli(a) count.  Reading:    */
+/* the m features with the smallest selection uniforms u_i (word 0 of entry    */
+/* i's block, ties by i) carry their entry's normal (words 1 and 2), so a      */
+/* uniformly random m-subset of the features.  With a = 1 it is the Bernoulli */
+/* form (every u_i < 1).  m is ceil of a*d in double, clamped to [1, d].      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double u;
+    int32_t i;
+} oracle_sel_key;
+
+static int oracle_sel_cmp(const void *x, const void *y)
+{
+    const oracle_sel_key *p = (const oracle_sel_key *)x, *q = (const oracle_sel_key *)y;
+    if (p->u < q->u) return -1;
+    if (p->u > q->u) return 1;
+    return (p->i > q->i) - (p->i < q->i);
+}
+
+int32_t oracle_exact_nnz(int32_t d, float a)
+{
+    double m = ceil((double)a * (double)d);
+    if (m < 1.0) m = 1.0;
+    if (m > (double)d) m = (double)d;
+    return (int32_t)m;
+}
+
+void oracle_random_matrix_exact(int32_t d, int32_t T, int32_t depth, float a, uint64_t seed, float *R)
+{
+    const double two_pow_m53 = 1.0 / 9007199254740992.0;
+    const uint64_t key[2] = {seed, 0};
+    const int32_t m = oracle_exact_nnz(d, a);
+    oracle_sel_key *keys = (oracle_sel_key *)malloc(sizeof(oracle_sel_key) * (size_t)d);
+    for (int32_t t = 0; t < T; t++)
+        for (int32_t lv = 0; lv < depth; lv++) {
+            float *row = R + ((int64_t)t * depth + lv) * d;
+            for (int32_t i = 0; i < d; i++) {
+                uint64_t ctr[4] = {(uint64_t)i, (uint64_t)lv, (uint64_t)t, 0};
+                uint64_t w[4];
+                oracle_philox4x64_10(ctr, key, w);
+                keys[i].u = (double)(w[0] >> 11) * two_pow_m53;
+                keys[i].i = i;
+                row[i] = 0.0f;
+            }
+            qsort(keys, (size_t)d, sizeof(oracle_sel_key), oracle_sel_cmp);
+            for (int32_t r = 0; r < m; r++) {
+                const int32_t i = keys[r].i;
+                uint64_t ctr[4] = {(uint64_t)i, (uint64_t)lv, (uint64_t)t, 0};
+                uint64_t w[4];
+                oracle_philox4x64_10(ctr, key, w);
+                double u1 = (double)((w[1] >> 11) + 1) * two_pow_m53; /* (0,1]  */
+                double u2 = (double)(w[2] >> 11) * two_pow_m53;       /* [0,1)  */
+                row[i] = (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+            }
+        }
+    free(keys);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -233,9 +295,11 @@ static void *build_worker(void *arg)
 /* grow_trees (Alg. 1).  R_out: (T*depth) x d dense; splits: T x (2^depth-1);
  * perm: T x n.  Trees are independent, so they are spread over threads. */
 void oracle_build(const float *X, int64_t n, int32_t d, int32_t T, int32_t depth, float a,
-                  uint64_t seed, float *R_out, float *splits, int32_t *perm, int32_t nthreads)
+                  uint64_t seed, int32_t exact_nnz, float *R_out, float *splits, int32_t *perm,
+                  int32_t nthreads)
 {
-    oracle_random_matrix(d, T, depth, a, seed, R_out);
+    if (exact_nnz) oracle_random_matrix_exact(d, T, depth, a, seed, R_out);
+    else oracle_random_matrix(d, T, depth, a, seed, R_out);
     if (nthreads < 1) nthreads = 1;
     if (nthreads > T) nthreads = T;
     pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);

@@ -9,7 +9,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "load", "philox4x64_10", "random_matrix", "project", "leaf_offsets", "build_index",
+    "load", "philox4x64_10", "random_matrix", "exact_nnz_count", "project", "leaf_offsets", "build_index",
     "route", "query", "bruteforce", "distance", "OracleIndex", "default_threads",
 ]
 
@@ -46,9 +46,12 @@ def load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
     lib.oracle_random_matrix.argtypes = [_i32, _i32, _i32, ctypes.c_float, ctypes.c_uint64, _f32p]
+    lib.oracle_random_matrix_exact.argtypes = [_i32, _i32, _i32, ctypes.c_float, ctypes.c_uint64, _f32p]
+    lib.oracle_exact_nnz.argtypes = [_i32, ctypes.c_float]
+    lib.oracle_exact_nnz.restype = _i32
     lib.oracle_project.argtypes = [_f32p, _i64, _i32, _f32p, _i32, _f32p]
     lib.oracle_leaf_offsets.argtypes = [_i64, _i32, _i64p]
-    lib.oracle_build.argtypes = [_f32p, _i64, _i32, _i32, _i32, ctypes.c_float, ctypes.c_uint64,
+    lib.oracle_build.argtypes = [_f32p, _i64, _i32, _i32, _i32, ctypes.c_float, ctypes.c_uint64, _i32,
                                  _f32p, _f32p, _i32p, _i32]
     lib.oracle_route.argtypes = [_f32p, _i64, _i32, _f32p, _i32, _i32, _f32p, _i32p]
     lib.oracle_distance.argtypes = [_f32p, _f32p, _i32]
@@ -71,12 +74,19 @@ def philox4x64_10(counter, key):
     return out
 
 
-def random_matrix(d, T, depth, a, seed):
-    """Sparse Gaussian projection vectors, Sec. II-B / Alg. 1; dense (T*depth, d)."""
+def random_matrix(d, T, depth, a, seed, exact_nnz=False):
+    """Sparse Gaussian projection vectors, Sec. II-B / Alg. 1; dense (T*depth, d).
+    exact_nnz: exactly ceil(a d) nonzeros per vector (footnote of Sec. II-D)."""
     R = np.zeros((T * depth, d), dtype=np.float32)
     if T * depth > 0:
-        load().oracle_random_matrix(d, T, depth, float(a), int(seed) & (2**64 - 1), R)
+        fn = load().oracle_random_matrix_exact if exact_nnz else load().oracle_random_matrix
+        fn(d, T, depth, float(a), int(seed) & (2**64 - 1), R)
     return R
+
+
+def exact_nnz_count(d, a):
+    """m = ceil(a d) in double, clamped to [1, d] (the exact-count mode's nonzeros per vector)."""
+    return int(load().oracle_exact_nnz(int(d), float(a)))
 
 
 def project(X, R):
@@ -115,8 +125,9 @@ class OracleIndex:
         return self.perm[t, self.off[L]:self.off[L + 1]]
 
 
-def build_index(X, T, depth, a, seed, nthreads=None):
-    """grow_trees (Alg. 1) calling grow_tree (Alg. 2) for every tree."""
+def build_index(X, T, depth, a, seed, nthreads=None, exact_nnz=False):
+    """grow_trees (Alg. 1) calling grow_tree (Alg. 2) for every tree
+    (exact_nnz: projection vectors with exactly ceil(a d) nonzeros)."""
     X = _c(X, np.float32)
     n, d = X.shape
     nsplit = (1 << depth) - 1
@@ -124,8 +135,8 @@ def build_index(X, T, depth, a, seed, nthreads=None):
     splits = np.zeros((T, nsplit), dtype=np.float32)
     perm = np.zeros((T, n), dtype=np.int32)
     sp = splits if nsplit > 0 else np.zeros((T, 1), dtype=np.float32)
-    load().oracle_build(X, n, d, T, depth, float(a), int(seed) & (2**64 - 1), R, sp, perm,
-                        nthreads or default_threads())
+    load().oracle_build(X, n, d, T, depth, float(a), int(seed) & (2**64 - 1), 1 if exact_nnz else 0, R, sp,
+                        perm, nthreads or default_threads())
     return OracleIndex(X, T, depth, a, seed, R, splits, perm, leaf_offsets(n, depth))
 
 

@@ -301,6 +301,7 @@ void mrpt_default_opts(mrpt_query_opts* o) {
 void mrpt_default_build_opts(mrpt_build_opts* o) {
     if (!o) return;
     o->on_device = 1;
+    o->exact_nnz = 0;
 }
 
 mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32_t depth, float a, uint64_t seed,
@@ -363,7 +364,7 @@ mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, in
         if (h) return fail(MRPT_ENONFINITE, "data holds NaN or Inf");
     }
 
-    generate_projection(d, T, depth, a, seed, ix->h_rowptr, ix->h_col, ix->h_val);
+    generate_projection(d, T, depth, a, seed, bo.exact_nnz != 0, ix->h_rowptr, ix->h_col, ix->h_val);
     for (int32_t t = 0; t < T; ++t)
         ix->max_tree_nnz = std::max(ix->max_tree_nnz, ix->h_rowptr[(size_t)(t + 1) * depth] -
                                                         ix->h_rowptr[(size_t)t * depth]);

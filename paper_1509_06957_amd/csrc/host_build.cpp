@@ -43,24 +43,32 @@ struct Philox4x64 {
 
 // The entry for (tree t, level lv, feature i) is a pure function of these
 // four numbers and the seed: counter (i, lv, t, 0), key (seed, 0).  Word 0
-// gives a 53-bit uniform for the Bernoulli(a) choice; words 1 and 2 give the
-// two uniforms of a Box-Muller standard normal evaluated in double.
-inline float draw_entry(uint64_t seed, int32_t t, int32_t lv, int32_t i, double a) {
+// gives a 53-bit uniform that selects the entry (Bernoulli(a), or by rank in
+// the exact-count mode); words 1 and 2 give the two uniforms of a Box-Muller
+// standard normal evaluated in double.
+struct EntryDraw {
+    double select;   // [0, 1)
+    float normal;
+};
+
+inline EntryDraw draw_entry(uint64_t seed, int32_t t, int32_t lv, int32_t i) {
     uint64_t x[4] = {(uint64_t)i, (uint64_t)lv, (uint64_t)t, 0};
     Philox4x64::block(x, seed, 0);
     constexpr double kInv53 = 1.0 / 9007199254740992.0;  // 2^-53
-    const double u = (double)(x[0] >> 11) * kInv53;
-    if (!(u < a)) return 0.0f;
     const double u1 = (double)((x[1] >> 11) + 1) * kInv53;  // (0, 1]
     const double u2 = (double)(x[2] >> 11) * kInv53;        // [0, 1)
     const double r = std::sqrt(-2.0 * std::log(u1));
-    const double z = r * std::cos(6.283185307179586 * u2);
-    return (float)z;
+    return {(double)(x[0] >> 11) * kInv53, (float)(r * std::cos(6.283185307179586 * u2))};
 }
 
 }  // namespace
 
-void generate_projection(int32_t d, int32_t T, int32_t depth, float a, uint64_t seed,
+int32_t exact_nnz_count(int32_t d, float a) {
+    const double m = std::ceil((double)a * (double)d);
+    return (int32_t)std::min<double>(std::max(m, 1.0), (double)d);
+}
+
+void generate_projection(int32_t d, int32_t T, int32_t depth, float a, uint64_t seed, bool exact,
                          std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
                          std::vector<float>& val) {
     const int64_t rows = (int64_t)T * depth;
@@ -68,13 +76,33 @@ void generate_projection(int32_t d, int32_t T, int32_t depth, float a, uint64_t 
     col.clear();
     val.clear();
     const double ad = (double)a;
+    const int32_t m = exact_nnz_count(d, a);
+    std::vector<EntryDraw> e((size_t)d);
+    std::vector<int32_t> pick((size_t)d);
     for (int32_t t = 0; t < T; ++t)
         for (int32_t lv = 0; lv < depth; ++lv) {
-            for (int32_t i = 0; i < d; ++i) {
-                const float r = draw_entry(seed, t, lv, i, ad);
-                if (r != 0.0f) {
-                    col.push_back(i);
-                    val.push_back(r);
+            for (int32_t i = 0; i < d; ++i) e[i] = draw_entry(seed, t, lv, i);
+            if (exact) {
+                // the m features of smallest (select, feature): a uniformly
+                // random m-subset (Sec. II-D footnote), then ascending features
+                for (int32_t i = 0; i < d; ++i) pick[i] = i;
+                std::nth_element(pick.begin(), pick.begin() + (m - 1), pick.end(), [&](int32_t x, int32_t y) {
+                    return e[x].select < e[y].select || (e[x].select == e[y].select && x < y);
+                });
+                std::sort(pick.begin(), pick.begin() + m);
+                for (int32_t j = 0; j < m; ++j) {
+                    const int32_t i = pick[j];
+                    if (e[i].normal != 0.0f) {
+                        col.push_back(i);
+                        val.push_back(e[i].normal);
+                    }
+                }
+            } else {
+                for (int32_t i = 0; i < d; ++i) {
+                    if (e[i].select < ad && e[i].normal != 0.0f) {
+                        col.push_back(i);
+                        val.push_back(e[i].normal);
+                    }
                 }
             }
             rowptr[(int64_t)t * depth + lv + 1] = (int32_t)col.size();

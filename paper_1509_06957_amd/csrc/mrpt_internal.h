@@ -106,9 +106,12 @@ struct HostTrees {
     std::vector<int32_t> perm;   // T x n
     std::vector<int64_t> off;    // 2^depth + 1
 };
-void generate_projection(int32_t d, int32_t T, int32_t depth, float a, uint64_t seed,
+// projection vectors as CSR rows (tree * depth + level), features ascending;
+// exact: ceil(a d) nonzeros per vector instead of Bernoulli(a) entries
+void generate_projection(int32_t d, int32_t T, int32_t depth, float a, uint64_t seed, bool exact,
                          std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
                          std::vector<float>& val);
+int32_t exact_nnz_count(int32_t d, float a);
 void leaf_offsets(int64_t n, int32_t depth, std::vector<int64_t>& off);
 void grow_trees_host(const float* X, int64_t n, int32_t d, int32_t T, int32_t depth,
                      const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,

@@ -33,7 +33,7 @@ class mrpt_query_opts(ctypes.Structure):
 
 
 class mrpt_build_opts(ctypes.Structure):
-    _fields_ = [("on_device", ctypes.c_int32)]
+    _fields_ = [("on_device", ctypes.c_int32), ("exact_nnz", ctypes.c_int32)]
 
 
 class mrpt_index_desc(ctypes.Structure):
@@ -302,9 +302,11 @@ class Plan:
 class Index:
     """Owning wrapper of an index handle (frees it on close / garbage collection)."""
 
-    def __init__(self, data, T: int, depth: int, a: float, seed: int, on_device: bool = True):
+    def __init__(self, data, T: int, depth: int, a: float, seed: int, on_device: bool = True,
+                 exact_nnz: bool = False):
         opts = mrpt_default_build_opts()
         opts.on_device = 1 if on_device else 0
+        opts.exact_nnz = 1 if exact_nnz else 0
         self.handle = mrpt_build_ex(data, T, depth, a, seed, opts)
         self.info = mrpt_index_info(self.handle)
 

@@ -10,7 +10,9 @@ set is every point).  One JSON line per configuration is printed, then a
 summary: for each recall target the fastest configuration reaching it, for
 MRPT (all v), MRPT with v = 1 (voting disabled, the paper's second column)
 and dense random projection trees (a = 1, v = 1, the third column; on a
-smaller grid, since dense vectors are projected on the host).
+smaller grid, since dense vectors are projected on the host).  Last, an
+ablation at the workload's (T, depth): Bernoulli(a) projection entries
+against exactly ceil(a d) nonzeros per vector, for every v.
 
 Usage: python -m paper_1509_06957_amd.sweep [--workload sift_like] [--quick]
 """
@@ -100,6 +102,24 @@ def main():
                     print(json.dumps(row), flush=True)
                 ix.close()
 
+    # ablation of the projection vectors: Bernoulli(a) entries against exactly
+    # ceil(a d) nonzeros per vector (footnote of Sec. II-D), at the workload's
+    # own (T, depth), every v
+    ablation = []
+    for exact in (False, True):
+        ix = mrpt.Index(Xd, w.T, w.depth, w.a, w.index_seed, exact_nnz=exact)
+        for v in vs:
+            if v > w.T:
+                continue
+            s_count = torch.zeros(nq, dtype=torch.int32, device="cuda")
+            ix.query(Qd, k, v, s_count=s_count)
+            qps32, ids = timed(ix, v, mrpt.MRPT_FP32)
+            row = {"exact_nnz": exact, "T": w.T, "depth": w.depth, "v": v, "recall": round(recall_of(ids), 4),
+                   "qps_fp32": round(qps32, 1), "s_mean": round(float(s_count.float().mean()), 1)}
+            ablation.append(row)
+            print(json.dumps(row), flush=True)
+        ix.close()
+
     targets = (0.8, 0.9, 0.95, 0.99)
 
     def best(sel, key):
@@ -119,6 +139,10 @@ def main():
         "mrpt_bf16": best(lambda x: x["a"] == "sparse", "qps_bf16"),
         "mrpt_v1_fp32": best(lambda x: x["a"] == "sparse" and x["v"] == 1, "qps_fp32"),
         "rp_trees_dense_fp32": best(lambda x: x["a"] == "dense", "qps_fp32"),
+        "exact_nnz_ablation": [{"v": b["v"], "recall": b["recall"], "recall_exact": e["recall"],
+                                "qps": b["qps_fp32"], "qps_exact": e["qps_fp32"]}
+                               for b in ablation if not b["exact_nnz"]
+                               for e in ablation if e["exact_nnz"] and e["v"] == b["v"]],
     }
     print(json.dumps({"summary": summary}), flush=True)
 

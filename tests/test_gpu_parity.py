@@ -384,3 +384,37 @@ def test_fp8_arm_gist_like_shape(k):
         overlap.append(len(set(real.tolist()) & set(pi[q][:nreal].tolist())) / max(nreal, 1))
     print(f"[fp8] gist-like shape k={k}: mean overlap with the fp32 arm {np.mean(overlap):.4f}", flush=True)
     g.close()
+
+
+@pytest.mark.parametrize("on_device", [True, False])
+def test_exact_nnz_mode_parity(on_device):
+    """Exactly ceil(a d) nonzeros per projection vector (footnote of Sec. II-D):
+    vectors, trees, leaves, votes and k-NN against the oracle's exact mode."""
+    w = W.MIXTURE_128.scaled(nq=200)
+    _print_case(f"exact_nnz mixture128 on_device={on_device}")
+    X, Q = W.data(w), W.queries(w)
+    orc = oracle.build_index(X, w.T, w.depth, w.a, w.index_seed, exact_nnz=True)
+    gpu = mrpt.Index(dev(X), w.T, w.depth, w.a, w.index_seed, on_device=on_device, exact_nnz=True)
+    try:
+        rowptr, col, val = mrpt.mrpt_export_projection(gpu.handle)
+        R = np.zeros_like(orc.R)
+        for r in range(R.shape[0]):
+            R[r, col[rowptr[r]:rowptr[r + 1]]] = val[rowptr[r]:rowptr[r + 1]]
+        assert np.array_equal(R.view(np.uint32), orc.R.view(np.uint32))
+        assert np.all(np.diff(rowptr) == oracle.exact_nnz_count(w.d, w.a))
+        for t in range(w.T):
+            splits, perm = mrpt.mrpt_export_tree(gpu.handle, t)
+            assert np.array_equal(splits.view(np.uint32), orc.splits[t].view(np.uint32)), f"tree {t}"
+            assert np.array_equal(perm, orc.perm[t]), f"tree {t}"
+        Qd = dev(Q)
+        assert np.array_equal(leaves(gpu, Qd), oracle.route(orc, Q))
+        for v in (1, 3):
+            ref = oracle.query(orc, Q, w.k, v, want_sets=True)
+            ids, cnt = votes(gpu, Qd, v)
+            for q in range(len(Q)):
+                assert np.array_equal(ids[q], ref["s_ids"][q]) and np.array_equal(cnt[q], ref["s_votes"][q])
+            gi, gd, _ = query(gpu, Qd, w.k, v)
+            check_knn(X, Q, gi, gd, ref["idx"], ref["dist"], exact_ids=False,
+                      S=[set(s.tolist()) for s in ref["s_ids"]])
+    finally:
+        gpu.close()

@@ -143,3 +143,14 @@ def test_depth_zero_single_leaf():
     idx = oracle.build_index(X, 2, 0, 0.5, seed=1)
     assert idx.splits.shape == (2, 0)
     assert np.array_equal(idx.perm, np.tile(np.arange(50, dtype=np.int32), (2, 1)))
+
+
+def test_exact_nnz_mode_trees():
+    # the exact-count projection mode changes only the vectors: every tree
+    # still satisfies the median-split characterisation
+    w = W.MIXTURE_128.scaled(n=2500)
+    X = W.data(w)
+    idx = oracle.build_index(X, 3, w.depth, w.a, w.index_seed, exact_nnz=True)
+    assert np.all((idx.R != 0).sum(axis=1) == oracle.exact_nnz_count(w.d, w.a))
+    for t in range(3):
+        check_tree_characterisation(X, idx, t)

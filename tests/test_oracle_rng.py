@@ -103,3 +103,74 @@ def test_levels_not_correlated():
 def test_seed_full_width(seed):
     R = oracle.random_matrix(32, 2, 3, 0.5, seed=seed)
     assert np.all(np.isfinite(R))
+
+
+# ---------------------------------------------------------------------------
+# exact-count mode (the footnote of Sec. II-D): exactly ceil(a d) nonzeros per
+# vector, the features with the smallest selection uniforms
+# ---------------------------------------------------------------------------
+def _uniforms_numpy(d, T, depth, seed):
+    """Word 0 of every entry's block from numpy's Philox (pinned equal to the
+    published generator above), as the 53-bit uniform, shape (T*depth, d)."""
+    U = np.zeros((T * depth, d))
+    for t in range(T):
+        for lv in range(depth):
+            for i in range(d):
+                # numpy emits the block of counter c + 1 first: start one below
+                # (i, lv, t, 0), read as a 256-bit number with word 0 lowest
+                c = (i + (lv << 64) + (t << 128)) - 1
+                words = [(c >> (64 * j)) & (2**64 - 1) for j in range(4)]
+                bg = np.random.Philox(key=np.array([seed, 0], np.uint64), counter=np.array(words, np.uint64))
+                U[t * depth + lv, i] = float(bg.random_raw(1)[0] >> np.uint64(11)) / 2.0**53
+    return U
+
+
+@pytest.mark.parametrize("d,a", [(128, 1 / np.sqrt(128)), (100, 0.05), (64, 0.5), (7, 0.3), (33, 1 / 33)])
+def test_exact_mode_count(d, a):
+    a = float(np.float32(a))
+    R = oracle.random_matrix(d, 6, 5, a, seed=21, exact_nnz=True)
+    m = min(d, max(1, int(np.ceil(np.float64(a) * d))))
+    assert oracle.exact_nnz_count(d, a) == m
+    assert np.all((R != 0).sum(axis=1) == m)
+
+
+def test_exact_mode_selects_smallest_uniforms():
+    d, T, depth, seed = 24, 3, 2, 77
+    a = 0.2
+    m = int(np.ceil(a * d))
+    U = _uniforms_numpy(d, T, depth, seed)
+    R = oracle.random_matrix(d, T, depth, a, seed, exact_nnz=True)
+    for r in range(T * depth):
+        want = set(np.lexsort((np.arange(d), U[r]))[:m].tolist())
+        assert set(np.nonzero(R[r])[0].tolist()) == want
+
+
+def test_exact_mode_nested_with_bernoulli():
+    # the exact set is the m smallest uniforms, so for every threshold b the
+    # Bernoulli set {u < b} either contains it or is contained in it
+    d, T, depth, seed = 96, 4, 4, 5
+    a = float(np.float32(1 / np.sqrt(d)))
+    E = oracle.random_matrix(d, T, depth, a, seed, exact_nnz=True) != 0
+    for b in (0.02, 0.05, 0.08, a, 0.12, 0.2, 0.5):
+        B = oracle.random_matrix(d, T, depth, b, seed) != 0
+        for r in range(T * depth):
+            e, s = set(np.nonzero(E[r])[0]), set(np.nonzero(B[r])[0])
+            assert e <= s or s <= e, (b, r)
+
+
+def test_exact_mode_values_and_dense_case():
+    d, T, depth, seed = 40, 3, 3, 9
+    full = oracle.random_matrix(d, T, depth, 1.0, seed)
+    assert np.array_equal(oracle.random_matrix(d, T, depth, 1.0, seed, exact_nnz=True), full)
+    E = oracle.random_matrix(d, T, depth, 0.25, seed, exact_nnz=True)
+    nz = E != 0
+    assert np.array_equal(E[nz], full[nz])
+
+
+def test_exact_mode_positions_uniform():
+    # each feature is chosen with probability m / d, independently of its index
+    d, T, depth = 50, 200, 10
+    a = 0.1
+    E = oracle.random_matrix(d, T, depth, a, seed=3, exact_nnz=True) != 0
+    counts = E.sum(axis=0)
+    assert stats.chisquare(counts).pvalue > 1e-3
