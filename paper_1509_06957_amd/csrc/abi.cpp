@@ -40,7 +40,7 @@ hipError_t dev_alloc(T** p, size_t count, int64_t* tally) {
 
 void dev_release(mrpt_index* ix) {
     void* ptrs[] = {ix->X, ix->Xb, ix->xnorm, ix->X8, ix->scale8, ix->norm8, ix->rowptr, ix->col, ix->val,
-                    ix->splits, ix->perm, ix->off, ix->ws.base};
+                    ix->splits, ix->perm, ix->off, ix->vdir, ix->ws.base};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (ix->ws.done) (void)hipEventDestroy(ix->ws.done);
@@ -434,6 +434,7 @@ mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, in
     if (on_device) MRPT_TRY(build_trees_on_device(ix.get()));
     MRPT_HIP_TRY(launch_quantize_bf16(ix->X, n, d, ix->Xb, ix->xnorm, nullptr));
     if (fp8) MRPT_HIP_TRY(launch_quantize_fp8(ix->X, n, d, ix->X8, ix->scale8, ix->norm8, nullptr));
+    if ((e = build_vote_directory(ix.get(), &ix->device_bytes)) != hipSuccess) return oom(e, "leaf directory");
     MRPT_HIP_TRY(hipDeviceSynchronize());
 
     guard.p = nullptr;

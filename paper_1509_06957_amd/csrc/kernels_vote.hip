@@ -182,6 +182,34 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
 }
 
 // ---------------------------------------------------------------------------
+// multi-pass form with a leaf directory
+// ---------------------------------------------------------------------------
+// A leaf's ids are ascending, so the ids of one pass [lo, hi) are one slice
+// of it.  The directory holds, for tree t, leaf L and boundary j, the position
+// of the leaf's first id >= min(j * grain, n); passes start and end on
+// boundaries, so every pass reads exactly its slice of each of the query's T
+// leaves and each id is read once per query instead of once per pass.
+__global__ void vote_dir_build_kernel(const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
+                                      int64_t n, int64_t ld, int32_t nleaf, int32_t nb, int32_t grain, int64_t total,
+                                      int32_t* __restrict__ dir) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= total) return;
+    const int32_t j = (int32_t)(x % nb);
+    const int64_t tl = x / nb;
+    const int32_t L = (int32_t)(tl % nleaf);
+    const int64_t t = tl / nleaf;
+    const int32_t* ids = perm + t * ld + off[L];
+    const int64_t target = (int64_t)j * grain < n ? (int64_t)j * grain : n;
+    int32_t lo = 0, hi = off[L + 1] - off[L];   // first position whose id >= target
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (ids[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    dir[x] = lo;
+}
+
+// ---------------------------------------------------------------------------
 // single-pass form (n < 2^24 and the id map fits LDS; windows in registers)
 // ---------------------------------------------------------------------------
 // A 1-bit map over the ids answers "seen before?" with one LDS atomic OR per
@@ -300,6 +328,101 @@ __device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int32_t* _
         asm volatile("" : "+v"(pad));
         const int idx = lane < avail ? first + lane : pad;
         dst[s] = perm[(uint32_t)idx];
+    }
+}
+
+// One workgroup per query (queries blockIdx.x, + gridDim.x, ...); 8-bit
+// counters over passes of `chunk` ids (a multiple of the grain), cleared in
+// full before each pass.  A count never exceeds T <= 255, so one atomic add
+// per id suffices: the id is elected by the add that finds v - 1.  Wave w
+// takes trees w, w + 16, ... and reads each slice in 64-id windows,
+// kDirWindows in flight, whose atomics are then issued together; their
+// elections are stored from one reservation.  The loads need no bounds
+// branch: a window reaches at most 63 entries past its slice, which stay
+// inside the tree's perm row (n ids, then padding).  With redo_only set, only
+// queries whose count is -1 are processed.
+constexpr int kDirWindows = 16;
+
+__global__ __launch_bounds__(kVoteBlock) void vote_dir_kernel(
+    const int32_t* __restrict__ leaf, const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
+    const int32_t* __restrict__ dir, int32_t nleaf, int32_t nb, int32_t grain, int64_t n, int64_t ld, int32_t T,
+    int32_t v, int64_t nq, int32_t chunk, int32_t* __restrict__ s_ids, int64_t cap, int32_t* __restrict__ s_count,
+    int32_t redo_only) {
+    extern __shared__ uint32_t vote_cnt[];   // chunk / 4 words, one byte per id
+    __shared__ int64_t tbase[kMaxT];         // perm index of the leaf's first id
+    __shared__ int64_t tslice[kMaxT];        // this pass: perm index of the slice, its length
+    __shared__ int32_t tlen[kMaxT];
+    __shared__ int nsel;
+    __shared__ int spare[kWave];             // targets of the reservations' idle lanes
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id();
+    const int w = uniform(tid >> 6);
+    const int words = chunk >> 2;
+    const uint32_t hit = (uint32_t)(v - 1);
+    const uint32_t cap32 = (uint32_t)(cap < INT32_MAX ? cap : INT32_MAX);
+    for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        if (redo_only && s_count[q] >= 0) continue;
+        // thread t < T follows tree t's slice boundaries, one pass ahead: a
+        // pass's slice starts where the previous one ended
+        int64_t row = 0;
+        int32_t cut_lo = 0, cut_hi = 0;
+        if (tid < T) {
+            const int L = leaf[q * T + tid];
+            tbase[tid] = (int64_t)tid * ld + off[L];
+            row = ((int64_t)tid * nleaf + L) * nb;
+            const int64_t hi0 = chunk < n ? chunk : n;
+            cut_lo = dir[row];
+            cut_hi = dir[row + (hi0 == n ? nb - 1 : (int)(hi0 / grain))];
+        }
+        if (tid == 0) nsel = 0;
+        int32_t* out = s_ids + q * cap;
+        for (int64_t lo = 0; lo < n; lo += chunk) {
+            const int64_t hi = lo + chunk < n ? lo + chunk : n;
+            __syncthreads();                 // the previous pass is done with the counters
+            for (int i = tid; i < (words >> 2); i += kVoteBlock)
+                reinterpret_cast<uint4*>(vote_cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (tid < T) {
+                tslice[tid] = tbase[tid] + cut_lo;
+                tlen[tid] = cut_hi - cut_lo;
+                cut_lo = cut_hi;
+                if (hi < n) {                // the next pass's end, loaded during this pass
+                    const int64_t hi2 = hi + chunk < n ? hi + chunk : n;
+                    cut_hi = dir[row + (hi2 == n ? nb - 1 : (int)(hi2 / grain))];
+                }
+            }
+            __syncthreads();
+            for (int j2 = w, u2 = 0; j2 < T;) {   // wave-uniform: every lane takes part
+                int32_t sid[kDirWindows];
+#pragma unroll
+                for (int b = 0; b < kDirWindows; ++b) {
+                    sid[b] = -1;
+                    if (j2 < T) {
+                        const int len = uniform(tlen[j2]);
+                        const int e = u2 * kWave + lane;
+                        const int32_t x = perm[tslice[j2] + e];
+                        if (e < len) sid[b] = x;
+                        ++u2;
+                        if (u2 * kWave >= len) { u2 = 0; j2 += kVoteWaves; }
+                    }
+                }
+                uint32_t ob[kDirWindows];    // nonzero: this occurrence is the v-th
+#pragma unroll
+                for (int b = 0; b < kDirWindows; ++b) {
+                    // (every id of a slice lies in [lo, hi); the bound keeps the
+                    // counter index inside the array regardless)
+                    const uint32_t rel = (uint32_t)(sid[b] - lo);
+                    ob[b] = 0u;
+                    if (sid[b] >= 0 && rel < (uint32_t)chunk) {
+                        const uint32_t sh = (rel & 3u) * 8u;
+                        ob[b] = ((atomicAdd(&vote_cnt[rel >> 2], 1u << sh) >> sh) & 0xffu) == hit ? 1u : 0u;
+                    }
+                }
+                append_batch<true, kDirWindows>(ob, sid, INT32_MAX, &nsel, spare, out, cap32);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_count[q] = nsel < cap ? nsel : (int32_t)cap;
+        __syncthreads();                     // shared state is reused by the next query
     }
 }
 
@@ -505,9 +628,41 @@ __global__ void copy_counts_kernel(const int32_t* __restrict__ src, int64_t nq, 
 
 // MRPT_VOTE_KERNEL=0 forces the multi-pass kernel (tuning and tests); by
 // default the single-pass kernel runs wherever it fits
-bool single_pass_allowed() {
+// MRPT_VOTE_KERNEL: unset, automatic; 0, the multi-pass kernel (with the
+// leaf directory when the index has one; set at build time it also makes the
+// build create the directory); 1, the multi-pass kernel without directory
+int vote_kernel_override() {
     const char* env = std::getenv("MRPT_VOTE_KERNEL");
-    return !(env && *env && std::atoi(env) == 0);
+    if (!env || !*env) return -1;
+    const int x = std::atoi(env);
+    return x == 0 || x == 1 ? x : -1;
+}
+
+size_t vote_lds_limit() { return (size_t)std::min(lds_per_block_limit(), 160 * 1024); }
+
+// single-pass geometry: map words (ids 0 .. n + 2047: real ids, then the
+// empty lanes' ids n + 32 lane + s), the repeat queue in what LDS has left
+struct SingleGeometry {
+    bool ok;
+    int32_t wpl;
+    int64_t slots, map_words, qcap;
+    size_t lds;
+};
+
+constexpr size_t kMapTail = sizeof(int2) * kPosBufs * kMaxT + 16 + 4 * kWave;   // positions, flags, spare
+
+SingleGeometry single_geometry(const mrpt_index* ix, bool queued) {
+    SingleGeometry g;
+    const size_t limit = vote_lds_limit();
+    g.wpl = (ix->max_leaf + kWave - 1) / kWave;
+    g.slots = ((int64_t)ix->T * g.wpl + kVoteWaves - 1) / kVoteWaves;
+    g.map_words = ((ix->n + kVoteSlots * kWave) / 32 + 1 + 3) / 4 * 4;
+    const int64_t room = ((int64_t)limit - (int64_t)kMapTail - g.map_words * 4) / 4;
+    g.qcap = queued ? std::min<int64_t>(room, (int64_t)ix->T * ix->max_leaf) / 4 * 4 : 0;
+    g.ok = g.slots <= kVoteSlots && ix->n < (int64_t(1) << 24) &&
+           (int64_t)ix->T * ix->perm_ld < (int64_t(1) << 31) && room >= 0 && (!queued || g.qcap >= 1024);
+    g.lds = (size_t)(g.map_words + g.qcap) * 4 + kMapTail;
+    return g;
 }
 
 int device_cus() {
@@ -525,34 +680,15 @@ template <int B>
 hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
                          int64_t cap, int32_t* s_count, hipStream_t s) {
     constexpr int per = 32 / B;
-    const size_t limit = (size_t)std::min(lds_per_block_limit(), 160 * 1024);
-    // multi-pass geometry for `fixed` bytes of static LDS: ids per pass, a
-    // multiple of 4 words' worth of ids, and the number of passes
-    auto geometry = [&](size_t fixed, int64_t& chunk, int64_t& passes) {
-        chunk = (int64_t)((limit - fixed) / 16) * 4 * per;
-        const int64_t padded = (ix->n + 4 * per - 1) / (4 * per) * (4 * per);
-        if (chunk > padded) chunk = padded;
-        passes = (ix->n + chunk - 1) / chunk;   // same passes, smaller array
-        chunk = ((ix->n + passes - 1) / passes + 4 * per - 1) / (4 * per) * (4 * per);
-    };
-    int64_t chunk = 0, passes = 0;
-    geometry(kMaxT * 8 + kMaxT * 4 + 16, chunk, passes);
-    const size_t multi_lds = (size_t)(chunk / per) * 4;
-
-    // single-pass geometry: map words (ids 0 .. n + 2047: real ids, then the
-    // empty lanes' ids n + 32 lane + s), the repeat queue in what LDS has left
+    const size_t limit = vote_lds_limit();
+    const int mode = vote_kernel_override();
     const bool queued = v >= 2;   // repeats are queued and rerun
-    const int wpl = (ix->max_leaf + kWave - 1) / kWave;
-    const int64_t slots = ((int64_t)ix->T * wpl + kVoteWaves - 1) / kVoteWaves;
-    const int64_t map_words = ((ix->n + kVoteSlots * kWave) / 32 + 1 + 3) / 4 * 4;
-    constexpr size_t kTail = sizeof(int2) * kPosBufs * kMaxT + 16 + 4 * kWave;   // positions, flags, spare
-    const int64_t room = ((int64_t)limit - (int64_t)kTail - map_words * 4) / 4;
-    const int64_t qcap = queued ? std::min<int64_t>(room, (int64_t)ix->T * ix->max_leaf) / 4 * 4 : 0;
-    const bool single = single_pass_allowed() && slots <= kVoteSlots && ix->n < (int64_t(1) << 24) &&
-                        (int64_t)ix->T * ix->perm_ld < (int64_t(1) << 31) && room >= 0 &&
-                        (!queued || qcap >= 1024);
+    const SingleGeometry sg = single_geometry(ix, queued);
+    const bool single = mode < 0 && sg.ok;
     if (single) {
-        const size_t lds = (size_t)(map_words + qcap) * 4 + kTail;
+        const int wpl = sg.wpl;
+        const int64_t slots = sg.slots, map_words = sg.map_words, qcap = sg.qcap;
+        const size_t lds = sg.lds;
         const int64_t grid = std::min<int64_t>(nq, device_cus());
 #define MRPT_MAP(SS, H)                                                                                          \
     do {                                                                                                         \
@@ -584,10 +720,38 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         if (qcap >= most) return e;
         // queries whose queue overflowed (count -1) are counted again, multi-pass
     }
-    (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)multi_lds);
     // a recount visits every query but counts few: a small grid loops over them
     const int64_t grid = single ? std::min<int64_t>(nq, 4 * device_cus()) : nq;
+
+    if (ix->vdir && mode != 1) {
+        // passes on directory boundaries, a multiple of the grain each; one
+        // byte per id
+        constexpr size_t fixed = kMaxT * (8 + 8 + 4) + 16 + 4 * kWave + 256;   // static LDS, aligned
+        const int64_t most = (int64_t)((limit - fixed) / 16) * 4 * 4;
+        int64_t chunk = most / kDirGrain * kDirGrain;
+        if (chunk >= kDirGrain) {
+            const int64_t passes = (ix->n + chunk - 1) / chunk;
+            chunk = ((ix->n + passes - 1) / passes + kDirGrain - 1) / kDirGrain * kDirGrain;
+            const size_t lds = (size_t)chunk;
+            (void)hipFuncSetAttribute((const void*)vote_dir_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+            hipLaunchKernelGGL(vote_dir_kernel, dim3((unsigned)grid), dim3(kVoteBlock), lds, s, leaf, ix->perm,
+                               ix->off, ix->vdir, ix->nleaf, ix->vdir_nb, kDirGrain, ix->n, ix->perm_ld, ix->T, v,
+                               nq, (int32_t)chunk, s_ids, cap, s_count, single ? 1 : 0);
+            return hipGetLastError();
+        }
+    }
+    // multi-pass geometry for `fixed` bytes of static LDS: ids per pass, a
+    // multiple of 4 words' worth of ids, and the number of passes
+    constexpr size_t fixed = kMaxT * 8 + kMaxT * 4 + 16;
+    int64_t chunk = (int64_t)((limit - fixed) / 16) * 4 * per;
+    const int64_t padded = (ix->n + 4 * per - 1) / (4 * per) * (4 * per);
+    if (chunk > padded) chunk = padded;
+    const int64_t passes = (ix->n + chunk - 1) / chunk;   // same passes, smaller array
+    chunk = ((ix->n + passes - 1) / passes + 4 * per - 1) / (4 * per) * (4 * per);
+    const size_t multi_lds = (size_t)(chunk / per) * 4;
+    (void)hipFuncSetAttribute((const void*)vote_kernel<B>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)multi_lds);
     hipLaunchKernelGGL(vote_kernel<B>, dim3((unsigned)grid), dim3(kVoteBlock), multi_lds, s, leaf, ix->perm, ix->off,
                        ix->n, ix->perm_ld, ix->T, v, nq, (int32_t)chunk, s_ids, cap, s_count, single ? 1 : 0);
     return hipGetLastError();
@@ -602,6 +766,27 @@ hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, in
     if (v <= 3) return launch_vote_b<2>(ix, leaf, nq, v, s_ids, cap, s_count, s);
     if (v <= 15) return launch_vote_b<4>(ix, leaf, nq, v, s_ids, cap, s_count, s);
     return launch_vote_b<8>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+}
+
+hipError_t build_vote_directory(mrpt_index* ix, int64_t* tally) {
+    // the multi-pass kernels serve this index when the single-pass one cannot
+    // (or when the multi-pass kernel is forced); one pass needs no directory
+    const bool multi = vote_kernel_override() == 0 || !single_geometry(ix, false).ok ||
+                       !single_geometry(ix, true).ok;
+    if (!multi || ix->n <= kDirGrain) return hipSuccess;
+    const int32_t nb = (int32_t)((ix->n + kDirGrain - 1) / kDirGrain + 1);
+    const int64_t total = (int64_t)ix->T * ix->nleaf * nb;
+    hipError_t e = hipMalloc((void**)&ix->vdir, (size_t)total * sizeof(int32_t));
+    if (e != hipSuccess) {
+        ix->vdir = nullptr;
+        return e;
+    }
+    if (tally) *tally += total * (int64_t)sizeof(int32_t);
+    ix->vdir_nb = nb;
+    const unsigned threads = 256;
+    hipLaunchKernelGGL(vote_dir_build_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0,
+                       nullptr, ix->perm, ix->off, ix->n, ix->perm_ld, ix->nleaf, nb, kDirGrain, total, ix->vdir);
+    return hipGetLastError();
 }
 
 hipError_t launch_vote_counts(const mrpt_index* ix, const int32_t* leaf, int64_t nq, const int32_t* s_ids,

@@ -39,6 +39,9 @@ constexpr int kMaxRerank = 512;     // rerank_factor * k
 // ...: a vote kernel reads an empty lane of a window from there instead of
 // branching around the load, so every slot issues exactly one load.
 constexpr int kPermPad = 2048;
+// leaf directory grain: the multi-pass vote kernel's passes start on
+// multiples of it, and the directory holds each leaf's position of them
+constexpr int kDirGrain = 32768;
 
 // ---------------------------------------------------------------- index
 struct DeviceBuf {
@@ -89,6 +92,8 @@ struct mrpt_index {
     int32_t* col = nullptr;      // nnz
     float* val = nullptr;        // nnz
     float* splits = nullptr;     // T x (2^depth - 1)
+    int32_t* vdir = nullptr;     // leaf directory (T x 2^depth x vdir_nb), or null
+    int32_t vdir_nb = 0;         // boundaries per leaf: ceil(n / kDirGrain) + 1
     int32_t* perm = nullptr;     // T rows of perm_ld: the tree's ids, then kPermPad entries n + j
     int64_t perm_ld = 0;         // n + kPermPad
     int32_t* off = nullptr;      // 2^depth + 1
@@ -143,6 +148,9 @@ hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_
                         hipStream_t s);
 hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v,
                        int32_t* s_ids, int64_t cap, int32_t* s_count, hipStream_t s);
+// the leaf directory of the multi-pass vote kernel, when the index needs one
+// (after perm and the leaf offsets are on the device); adds its bytes to *tally
+hipError_t build_vote_directory(mrpt_index* ix, int64_t* tally);
 hipError_t launch_vote_counts(const mrpt_index* ix, const int32_t* leaf, int64_t nq,
                               const int32_t* s_ids, int64_t cap, const int32_t* s_count,
                               uint8_t* s_votes, hipStream_t s);

@@ -274,10 +274,12 @@ def ctypes_build_host_pointer(X):
                           ctypes.byref(h))
 
 
-@pytest.mark.parametrize("kernel", ["0", "default"])
+@pytest.mark.parametrize("kernel", ["0", "1", "default"])
 def test_vote_kernel_variants_agree(kernel, monkeypatch):
-    # the multi-pass vote kernel (MRPT_VOTE_KERNEL=0) and the default
-    # single-pass one (id map + hash, persistent) compute the same candidate
+    # the multi-pass vote kernel with its leaf directory (MRPT_VOTE_KERNEL=0,
+    # which also makes the build create the directory), the multi-pass kernel
+    # without it (1) and the default choice (single-pass id map + repeat queue
+    # where it fits) compute the same candidate
     # sets.  700 queries give every persistent workgroup several queries; the
     # depth-1 case with v = 2 overflows the single-pass kernel's hash table
     # (its queries are redone multi-pass) and, like the 140-tree case, has
