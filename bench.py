@@ -150,7 +150,7 @@ def main():
     rerank_rows = int(np.minimum(S, kp).sum())
     bytes_search = {
         "fp32": nq * 4 + sum_s * 4 + sum_s * w.d * 4 + nq * w.d * 4 + nq * k * 8,
-        "bf16": nq * 4 + sum_s * 4 + sum_s * (w.d * 2 + 4) + rerank_rows * w.d * 4 + nq * w.d * 4 + nq * k * 8,
+        "bf16": nq * 4 + sum_s * 4 + sum_s * (w.d * 2) + rerank_rows * w.d * 4 + nq * w.d * 4 + nq * k * 8,
         "fp8": nq * 4 + sum_s * 4 + sum_s * (w.d + 8) + rerank_rows * w.d * 4 + nq * w.d * 4 + nq * k * 8,
     }
 

@@ -1,5 +1,5 @@
-// Build-time and utility kernels: finiteness scan, bfloat16 copy of the data
-// with float32 squared norms (inputs of the bfloat16 prefilter).
+// Build-time and utility kernels: finiteness scan, and the bfloat16 and fp8
+// copies of the data that the prefilter arms read.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -28,23 +28,13 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
 
 // one wave per row: lanes over columns
 __global__ __launch_bounds__(256) void quantize_bf16_kernel(const float* __restrict__ X, int64_t n, int32_t d,
-                                                            uint16_t* __restrict__ Xb,
-                                                            float* __restrict__ xnorm) {
+                                                            uint16_t* __restrict__ Xb) {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < n; row += waves) {
         const float* xr = X + row * d;
         uint16_t* br = Xb + row * d;
-        float acc = 0.0f;
-        for (int i = lane; i < d; i += 64) {
-            const uint16_t h = to_bf16(xr[i]);
-            br[i] = h;
-            const float f = __builtin_bit_cast(float, (uint32_t)h << 16);
-            acc = __builtin_fmaf(f, f, acc);
-        }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) xnorm[row] = acc;
+        for (int i = lane; i < d; i += 64) br[i] = to_bf16(xr[i]);
     }
 }
 
@@ -62,7 +52,9 @@ hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hip
 // codes are x / scale rounded to nearest by the hardware conversion (|x /
 // scale| <= 240 is finite in both e4m3 encodings), and norm = scale^2 *
 // sum(decode(code)^2) in float32, so that the prefilter's ||x^||^2 is the
-// squared norm of exactly the row it decodes.  One wave per row, d % 4 == 0.
+// squared norm of exactly the row it decodes (stored: recomputing it per
+// candidate costs the fp8 prefilter more than the load).  One wave per row,
+// d % 4 == 0.
 __global__ __launch_bounds__(256) void quantize_fp8_kernel(const float* __restrict__ X, int64_t n, int32_t d,
                                                            uint8_t* __restrict__ X8, float* __restrict__ scale8,
                                                            float* __restrict__ norm8) {
@@ -111,11 +103,11 @@ hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8
     return hipGetLastError();
 }
 
-hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, float* xnorm, hipStream_t s) {
+hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, hipStream_t s) {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 3) / 4;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(quantize_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, Xb, xnorm);
+    hipLaunchKernelGGL(quantize_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, Xb);
     return hipGetLastError();
 }
 

@@ -213,7 +213,7 @@ template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
 __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __restrict__ X,
                                                              const uint8_t* __restrict__ Xq,
                                                              const float* __restrict__ xscale,
-                                                             const float* __restrict__ xnorm, int32_t d,
+                                                             const float* __restrict__ norm8, int32_t d,
                                                         const float* __restrict__ Q,
                                                         const int32_t* __restrict__ s_ids, int64_t cap,
                                                         const int32_t* __restrict__ s_count, int32_t k,
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
 #pragma unroll
         for (int u = 0; u < U; ++u) cid[u] = slot(b0, u) < ns ? craw[u] : -1;
         uint4 xv[U][NVB];
-        float xn[U], xs[U];
+        float xs[U], xn[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = cid[u] < 0 ? 0 : cid[u];
@@ -293,18 +293,21 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
                 const int vi = gl + i * GB;
                 xv[u][i] = xr[vi < nv8 ? vi : 0];
             }
-            xn[u] = xnorm[row];
             xs[u] = FMT == kFmtFp8 ? xscale[row] : 1.0f;
+            xn[u] = FMT == kFmtFp8 ? norm8[row] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int ci = slot(b0 + kStep, u);
             craw[u] = S[ci < ns ? ci : 0];
         }
+        // the dot product q.x~; the bfloat16 row's squared norm is accumulated
+        // beside it from the row in registers (no norm load), the fp8 row's
+        // (scale^2 * sum decode^2, stored at build) is loaded with the scale
         float s[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            float a = 0.0f;
+            float a = 0.0f, r2 = 0.0f;
 #pragma unroll
             for (int i = 0; i < NVB; ++i) {
                 const bool in = gl + i * GB < nv8;
@@ -313,8 +316,11 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if constexpr (FMT == kFmtBf16) {
-                        a = __builtin_fmaf(qf[i][2 * j], bf16_lo(wv[j]), a);
-                        a = __builtin_fmaf(qf[i][2 * j + 1], bf16_hi(wv[j]), a);
+                        const float x0 = bf16_lo(wv[j]), x1 = bf16_hi(wv[j]);
+                        a = __builtin_fmaf(qf[i][2 * j], x0, a);
+                        a = __builtin_fmaf(qf[i][2 * j + 1], x1, a);
+                        r2 = __builtin_fmaf(x0, x0, r2);
+                        r2 = __builtin_fmaf(x1, x1, r2);
                     } else {
                         const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], false);
                         const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], true);
@@ -326,7 +332,8 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
                 }
             }
             const float dot = group_sum<GB>(a);
-            s[u] = (qn + xn[u]) - 2.0f * (xs[u] * dot);
+            if constexpr (FMT == kFmtBf16) s[u] = (qn + group_sum<GB>(r2)) - 2.0f * dot;
+            else s[u] = (qn + xn[u]) - 2.0f * (xs[u] * dot);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -541,10 +548,9 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
     const int RB = kp <= 64 ? 1 : kp <= 128 ? 2 : kp <= 256 ? 4 : 8;
     dim3 grid((unsigned)nq), block(256);
     const uint8_t* Xq = fp8 ? ix->X8 : reinterpret_cast<const uint8_t*>(ix->Xb);
-    const float* norm = fp8 ? ix->norm8 : ix->xnorm;
 #define MRPT_PF(F, GB, NVB, RR, G2, NV2)                                                                           \
     hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, RR, G2, NV2>), grid, block, 0, s, ix->X, Xq, ix->scale8, \
-                       norm, d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
+                       ix->norm8, d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
 #define MRPT_PF_R(F, GB, NVB, G2, NV2)                  \
     switch (RB) {                                       \
         case 1: MRPT_PF(F, GB, NVB, 1, G2, NV2); break; \

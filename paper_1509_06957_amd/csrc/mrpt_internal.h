@@ -84,7 +84,6 @@ struct mrpt_index {
     // device arrays
     float* X = nullptr;          // n x d
     uint16_t* Xb = nullptr;      // n x d bfloat16 bits (round to nearest even)
-    float* xnorm = nullptr;      // n: squared norm of the bfloat16 row, float32
     uint8_t* X8 = nullptr;       // n x d fp8 (e4m3) codes (d % 16 == 0 and d <= 1024, else unset)
     float* scale8 = nullptr;     // n: per-row scale of the fp8 codes
     float* norm8 = nullptr;      // n: squared norm of the decoded fp8 row
@@ -163,8 +162,7 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
                                  int32_t* out_idx, float* out_dist, hipStream_t s);
 hipError_t launch_copy_counts(const int32_t* src, int64_t nq, int32_t* dst, hipStream_t s);
 hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hipStream_t s);
-hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, float* xnorm,
-                                hipStream_t s);
+hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8, float* scale8, float* norm8,
                                hipStream_t s);
 
