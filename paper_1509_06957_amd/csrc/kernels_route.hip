@@ -75,6 +75,35 @@ __device__ __forceinline__ void stage_query_tile(const float* __restrict__ Q, in
     }
 }
 
+// features [c0, c0 + cw) of the 64-query tile starting at q0 into LDS as
+// qt[(feature - c0) * 65 + query]; rows past nq read as zero
+__device__ __forceinline__ void stage_query_chunk(const float* __restrict__ Q, int64_t q0, int64_t nq, int d, int c0,
+                                                  int cw, float* qt) {
+    const int tid = (int)threadIdx.x, nthreads = (int)blockDim.x;
+    const int total = kWave * cw;
+    const int step_q = nthreads / cw, step_f = nthreads - step_q * cw;
+    int qq = tid / cw, f = tid - qq * cw;
+    const float* src = Q + q0 * d + c0;
+    const int64_t rows_left = nq - q0;
+    for (int e0 = tid; e0 < total; e0 += kStageUnroll * nthreads) {
+        float r[kStageUnroll];
+        int rq[kStageUnroll], rf[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int e = e0 + u * nthreads;
+            rq[u] = qq;
+            rf[u] = f;
+            r[u] = (e < total && qq < rows_left) ? src[(int64_t)qq * d + f] : 0.0f;
+            qq += step_q;
+            f += step_f;
+            if (f >= cw) { f -= cw; ++qq; }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u)
+            if (e0 + u * nthreads < total) qt[rf[u] * kQStride + rq[u]] = r[u];
+    }
+}
+
 template <int MAXL, bool CSR_LDS, bool SPLITS_LDS>
 __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q, int64_t nq, int32_t d,
                                                     const int32_t* __restrict__ rowptr,
@@ -302,18 +331,20 @@ __global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict
 // ---------------------------------------------------------------------------
 constexpr int kProjWaves = 8;
 
-// where the query tile is read from: LDS ([feature][query] tile staged by the
-// workgroup), Q row-major in global memory, or its transpose QT (feature-major,
-// QT[c * nq + q]: lanes, one query each, read consecutive words)
-constexpr int kQLds = 0, kQRows = 1, kQTransposed = 2;
+// The workgroup's 64-query tile is staged in LDS as [feature][query], in
+// chunks of at most kProjChunk features when d is wider.  A vector's
+// nonzeros are in ascending feature order, so those of one chunk are a
+// contiguous run of its list (found by a ballot): every fused multiply-add
+// chain still runs over the features in ascending order, chunk after chunk.
+constexpr int kProjChunk = (64 * 1024) / (kQStride * 4);   // 252 features: 64 KB of LDS
 
-template <int RPW, int QMODE>
+template <int RPW>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
                                                                      int32_t d, const int32_t* __restrict__ rowptr,
                                                                      const int32_t* __restrict__ col,
                                                                      const float* __restrict__ val, int32_t nrows,
                                                                      float* __restrict__ Pq) {
-    extern __shared__ float proj_smem[];   // [d][65] when QMODE == kQLds
+    extern __shared__ float proj_smem[];   // [min(d, kProjChunk)][65]
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
     const int64_t q0 = (int64_t)blockIdx.x * kWave;
@@ -321,12 +352,13 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
     int len[RPW];
     int colr[RPW];
     float valr[RPW];
-    int maxlen = 0;
+    int kb[RPW];                         // first entry of the current chunk, per row
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
         len[i] = 0;
         colr[i] = 0;
         valr[i] = 0.0f;
+        kb[i] = 0;
         if (r0 + i < nrows) {
             const int b = uniform(rowptr[r0 + i]);
             len[i] = uniform(rowptr[r0 + i + 1]) - b;
@@ -334,33 +366,39 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
                 colr[i] = col[b + lane];
                 valr[i] = val[b + lane];
             }
-            maxlen = len[i] > maxlen ? len[i] : maxlen;
         }
     }
-    if constexpr (QMODE == kQLds) {
-        stage_query_tile(Q, q0, nq, d, proj_smem);
-        __syncthreads();
-    }
-    const int64_t q = q0 + lane;
-    const int64_t qc = q < nq ? q : nq - 1;
-    const float* qrow = Q + qc * d;
     float acc[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) acc[i] = 0.0f;
-    for (int k = 0; k < maxlen; ++k) {
+    for (int c0 = 0; c0 < d; c0 += kProjChunk) {
+        const int cw = d - c0 < kProjChunk ? d - c0 : kProjChunk;
+        if (c0 > 0) __syncthreads();     // every wave is done with the previous chunk
+        stage_query_chunk(Q, q0, nq, d, c0, cw, proj_smem);
+        __syncthreads();
+        // entries of row i in this chunk: [kb[i], ke[i]), a prefix count of
+        // the entries below the chunk's end
+        int ke[RPW];
+        int span = 0;
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
-            if (k < len[i]) {
-                const int c = read_lane_i(colr[i], k);
-                const float v = read_lane_f(valr[i], k);
-                float x;
-                if constexpr (QMODE == kQLds) x = proj_smem[c * kQStride + lane];
-                else if constexpr (QMODE == kQRows) x = qrow[c];
-                else x = Q[(int64_t)c * nq + qc];
-                acc[i] = __builtin_fmaf(x, v, acc[i]);
+            ke[i] = (int)__popcll(__builtin_amdgcn_ballot_w64(lane < len[i] && colr[i] < c0 + cw));
+            span = ke[i] - kb[i] > span ? ke[i] - kb[i] : span;
+        }
+        for (int k = 0; k < span; ++k) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                if (kb[i] + k < ke[i]) {
+                    const int c = read_lane_i(colr[i], kb[i] + k);
+                    const float v = read_lane_f(valr[i], kb[i] + k);
+                    acc[i] = __builtin_fmaf(proj_smem[(c - c0) * kQStride + lane], v, acc[i]);
+                }
             }
         }
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) kb[i] = ke[i];
     }
+    const int64_t q = q0 + lane;
     if (q < nq) {
 #pragma unroll
         for (int i = 0; i < RPW; ++i)
@@ -463,59 +501,17 @@ constexpr int kProjRows = 16;   // rows per wave in project_kernel
 
 }  // namespace
 
-bool project_tile_fits_lds(int32_t d) { return (size_t)d * kQStride * 4 <= 64 * 1024; }
-
 hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32_t row0, int32_t nrows, float* P,
-                          hipStream_t s, const float* AT) {
+                          hipStream_t s) {
     if (m == 0 || nrows == 0) return hipSuccess;
     const int d = ix->d;
-    const bool qlds = project_tile_fits_lds(d);
-    const size_t lds = qlds ? (size_t)d * kQStride * 4 : 0;
+    const size_t lds = (size_t)std::min(d, kProjChunk) * kQStride * 4;
     dim3 grid((unsigned)((m + kWave - 1) / kWave),
               (unsigned)((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)));
-    if (qlds) {
-        (void)hipFuncSetAttribute((const void*)project_kernel<kProjRows, kQLds>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((project_kernel<kProjRows, kQLds>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,
-                           ix->rowptr + row0, ix->col, ix->val, nrows, P);
-    } else if (AT) {
-        hipLaunchKernelGGL((project_kernel<kProjRows, kQTransposed>), grid, dim3(kProjWaves * kWave), 0, s, AT, m,
-                           d, ix->rowptr + row0, ix->col, ix->val, nrows, P);
-    } else {
-        hipLaunchKernelGGL((project_kernel<kProjRows, kQRows>), grid, dim3(kProjWaves * kWave), 0, s, A, m, d,
-                           ix->rowptr + row0, ix->col, ix->val, nrows, P);
-    }
-    return hipGetLastError();
-}
-
-namespace {
-
-// AT[c * m + i] = A[i * d + c] through 64 x 64 LDS tiles (padded rows)
-__global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ A, int64_t m, int32_t d,
-                                                        float* __restrict__ AT) {
-    __shared__ float tile[64][65];
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int c0 = (int)blockIdx.y * 64;
-    const int tx = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);
-    for (int r = ty; r < 64; r += 4) {
-        const int64_t i = i0 + r;
-        const int c = c0 + tx;
-        tile[r][tx] = (i < m && c < d) ? A[i * d + c] : 0.0f;
-    }
-    __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int c = c0 + r;
-        const int64_t i = i0 + tx;
-        if (c < d && i < m) AT[(int64_t)c * m + i] = tile[tx][r];
-    }
-}
-
-}  // namespace
-
-hipError_t launch_transpose(const float* A, int64_t m, int32_t d, float* AT, hipStream_t s) {
-    if (m == 0) return hipSuccess;
-    dim3 grid((unsigned)((m + 63) / 64), (unsigned)((d + 63) / 64));
-    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, A, m, d, AT);
+    (void)hipFuncSetAttribute((const void*)project_kernel<kProjRows>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL((project_kernel<kProjRows>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,
+                       ix->rowptr + row0, ix->col, ix->val, nrows, P);
     return hipGetLastError();
 }
 
@@ -525,15 +521,7 @@ hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, in
                             hipStream_t s) {
     const int depth = ix->depth;
     {
-        // a query tile too wide for LDS is read from a transposed copy (after
-        // the projections in the workspace)
-        float* qt = nullptr;
-        if (!project_tile_fits_lds(ix->d) && ix->T * depth > 0) {
-            qt = pq + (size_t)nq * ix->T * depth;
-            hipError_t e = launch_transpose(Q, nq, ix->d, qt, s);
-            if (e != hipSuccess) return e;
-        }
-        hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s, qt);
+        hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s);
         if (e != hipSuccess) return e;
     }
     const int nsplit = (1 << depth) - 1;
@@ -566,8 +554,7 @@ hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, in
 
 size_t route_workspace_floats(const mrpt_index* ix, int64_t nq) {
     if (ix->max_row_nnz > kWave) return 0;
-    // projections, then (wide queries) the transposed query batch
-    return (size_t)nq * ix->T * ix->depth + (project_tile_fits_lds(ix->d) ? 0 : (size_t)nq * ix->d);
+    return (size_t)nq * ix->T * ix->depth;   // the projections
 }
 
 hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,

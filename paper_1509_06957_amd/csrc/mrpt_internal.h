@@ -134,12 +134,8 @@ hipError_t grow_trees_device(mrpt_index* ix, int32_t t0, int32_t g,
 // kernel launchers (kernels_route/vote/search/misc.hip); all asynchronous
 // projections of the m rows of A onto vectors row0 .. row0 + nrows - 1:
 // P[r * m + i] (the float32 fused multiply-add chain of Sec. II-C)
-// (AT: optional transposed copy of A, AT[c * m + i], read when a 64-row tile
-// of A does not fit LDS)
 hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32_t row0, int32_t nrows, float* P,
-                          hipStream_t s, const float* AT = nullptr);
-bool project_tile_fits_lds(int32_t d);
-hipError_t launch_transpose(const float* A, int64_t m, int32_t d, float* AT, hipStream_t s);
+                          hipStream_t s);
 // pq: scratch of route_workspace_floats(ix, nq) floats for the projections
 // (nullptr selects the fused single-kernel form)
 size_t route_workspace_floats(const mrpt_index* ix, int64_t nq);
