@@ -262,106 +262,113 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
     }
     const float qn = read_lane_f(group_sum<GB>(qn_part), 0);
 
-    WaveTopK<RB> top;
-    top.init(kPadId + w * kWave * RB);
-    float tau_d;
-    int32_t tau_i;
-    top.get(kp - 1, tau_d, tau_i);
+    if (ns > kp) {
+        WaveTopK<RB> top;
+        top.init(kPadId + w * kWave * RB);
+        float tau_d;
+        int32_t tau_i;
+        top.get(kp - 1, tau_d, tau_i);
 
-    // as in dist_fp32: the next step's candidate ids are loaded while this
-    // step's rows arrive, and every load is unconditional (clamped, masked)
-    constexpr int kStep = kDistWaves * GPW * U;
-    auto slot = [&](int b, int u) { return b + (u * kDistWaves + w) * GPW + g; };
-    int32_t craw[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int ci = slot(0, u);
-        craw[u] = S[ci < ns ? ci : 0];
-    }
-    for (int b0 = 0; b0 < ns; b0 += kStep) {
-        int32_t cid[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) cid[u] = slot(b0, u) < ns ? craw[u] : -1;
-        uint4 xv[U][NVB];
-        float xs[U], xn[U];
-#pragma unroll
+        // as in dist_fp32: the next step's candidate ids are loaded while this
+        // step's rows arrive, and every load is unconditional (clamped, masked)
+        constexpr int kStep = kDistWaves * GPW * U;
+        auto slot = [&](int b, int u) { return b + (u * kDistWaves + w) * GPW + g; };
+        int32_t craw[U];
+    #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t row = cid[u] < 0 ? 0 : cid[u];
-            const uint4* xr = reinterpret_cast<const uint4*>(Xq + row * d * ROWB);
-#pragma unroll
-            for (int i = 0; i < NVB; ++i) {
-                const int vi = gl + i * GB;
-                xv[u][i] = xr[vi < nv8 ? vi : 0];
-            }
-            xs[u] = FMT == kFmtFp8 ? xscale[row] : 1.0f;
-            xn[u] = FMT == kFmtFp8 ? norm8[row] : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int ci = slot(b0 + kStep, u);
+            const int ci = slot(0, u);
             craw[u] = S[ci < ns ? ci : 0];
         }
-        // the dot product q.x~; the bfloat16 row's squared norm is accumulated
-        // beside it from the row in registers (no norm load), the fp8 row's
-        // (scale^2 * sum decode^2, stored at build) is loaded with the scale
-        float s[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            float a = 0.0f, r2 = 0.0f;
-#pragma unroll
-            for (int i = 0; i < NVB; ++i) {
-                const bool in = gl + i * GB < nv8;
-                const uint32_t wv[4] = {in ? xv[u][i].x : 0u, in ? xv[u][i].y : 0u, in ? xv[u][i].z : 0u,
-                                        in ? xv[u][i].w : 0u};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if constexpr (FMT == kFmtBf16) {
-                        const float x0 = bf16_lo(wv[j]), x1 = bf16_hi(wv[j]);
-                        a = __builtin_fmaf(qf[i][2 * j], x0, a);
-                        a = __builtin_fmaf(qf[i][2 * j + 1], x1, a);
-                        r2 = __builtin_fmaf(x0, x0, r2);
-                        r2 = __builtin_fmaf(x1, x1, r2);
-                    } else {
-                        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], false);
-                        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], true);
-                        a = __builtin_fmaf(qf[i][4 * j], lo[0], a);
-                        a = __builtin_fmaf(qf[i][4 * j + 1], lo[1], a);
-                        a = __builtin_fmaf(qf[i][4 * j + 2], hi[0], a);
-                        a = __builtin_fmaf(qf[i][4 * j + 3], hi[1], a);
+        for (int b0 = 0; b0 < ns; b0 += kStep) {
+            int32_t cid[U];
+    #pragma unroll
+            for (int u = 0; u < U; ++u) cid[u] = slot(b0, u) < ns ? craw[u] : -1;
+            uint4 xv[U][NVB];
+            float xs[U], xn[U];
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = cid[u] < 0 ? 0 : cid[u];
+                const uint4* xr = reinterpret_cast<const uint4*>(Xq + row * d * ROWB);
+    #pragma unroll
+                for (int i = 0; i < NVB; ++i) {
+                    const int vi = gl + i * GB;
+                    xv[u][i] = xr[vi < nv8 ? vi : 0];
+                }
+                xs[u] = FMT == kFmtFp8 ? xscale[row] : 1.0f;
+                xn[u] = FMT == kFmtFp8 ? norm8[row] : 0.0f;
+            }
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ci = slot(b0 + kStep, u);
+                craw[u] = S[ci < ns ? ci : 0];
+            }
+            // the dot product q.x~; the bfloat16 row's squared norm is accumulated
+            // beside it from the row in registers (no norm load), the fp8 row's
+            // (scale^2 * sum decode^2, stored at build) is loaded with the scale
+            float s[U];
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float a = 0.0f, r2 = 0.0f;
+    #pragma unroll
+                for (int i = 0; i < NVB; ++i) {
+                    const bool in = gl + i * GB < nv8;
+                    const uint32_t wv[4] = {in ? xv[u][i].x : 0u, in ? xv[u][i].y : 0u, in ? xv[u][i].z : 0u,
+                                            in ? xv[u][i].w : 0u};
+    #pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if constexpr (FMT == kFmtBf16) {
+                            const float x0 = bf16_lo(wv[j]), x1 = bf16_hi(wv[j]);
+                            a = __builtin_fmaf(qf[i][2 * j], x0, a);
+                            a = __builtin_fmaf(qf[i][2 * j + 1], x1, a);
+                            r2 = __builtin_fmaf(x0, x0, r2);
+                            r2 = __builtin_fmaf(x1, x1, r2);
+                        } else {
+                            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], false);
+                            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], true);
+                            a = __builtin_fmaf(qf[i][4 * j], lo[0], a);
+                            a = __builtin_fmaf(qf[i][4 * j + 1], lo[1], a);
+                            a = __builtin_fmaf(qf[i][4 * j + 2], hi[0], a);
+                            a = __builtin_fmaf(qf[i][4 * j + 3], hi[1], a);
+                        }
+                    }
+                }
+                const float dot = group_sum<GB>(a);
+                if constexpr (FMT == kFmtBf16) s[u] = (qn + group_sum<GB>(r2)) - 2.0f * dot;
+                else s[u] = (qn + xn[u]) - 2.0f * (xs[u] * dot);
+            }
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+    #pragma unroll
+                for (int gg = 0; gg < GPW; ++gg) {
+                    const int32_t ci = read_lane_i(cid[u], gg * GB);
+                    const float cd = read_lane_f(s[u], gg * GB);
+                    if (ci >= 0 && key_less(cd, ci, tau_d, tau_i)) {
+                        top.insert(cd, ci);
+                        top.get(kp - 1, tau_d, tau_i);
                     }
                 }
             }
-            const float dot = group_sum<GB>(a);
-            if constexpr (FMT == kFmtBf16) s[u] = (qn + group_sum<GB>(r2)) - 2.0f * dot;
-            else s[u] = (qn + xn[u]) - 2.0f * (xs[u] * dot);
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int gg = 0; gg < GPW; ++gg) {
-                const int32_t ci = read_lane_i(cid[u], gg * GB);
-                const float cd = read_lane_f(s[u], gg * GB);
-                if (ci >= 0 && key_less(cd, ci, tau_d, tau_i)) {
-                    top.insert(cd, ci);
-                    top.get(kp - 1, tau_d, tau_i);
-                }
-            }
-        }
-    }
 
-    // merge the wave lists: the best kp of the prefilter, in rank order
-    top.store(md[w], mi[w], kp);
-    __syncthreads();
-    for (int e = (int)threadIdx.x; e < kDistWaves * kp; e += (int)blockDim.x) {
-        const int ww = e / kp, pos = e - ww * kp;
-        const float kd = md[ww][pos];
-        const int32_t ki = mi[ww][pos];
-        int rank = pos;
-        for (int o = 0; o < kDistWaves; ++o)
-            if (o != ww) rank += count_less(md[o], mi[o], kp, kd, ki);
-        if (rank < kp) cand[rank] = kd < INFINITY ? ki : -1;
+        // merge the wave lists: the best kp of the prefilter, in rank order
+        top.store(md[w], mi[w], kp);
+        __syncthreads();
+        for (int e = (int)threadIdx.x; e < kDistWaves * kp; e += (int)blockDim.x) {
+            const int ww = e / kp, pos = e - ww * kp;
+            const float kd = md[ww][pos];
+            const int32_t ki = mi[ww][pos];
+            int rank = pos;
+            for (int o = 0; o < kDistWaves; ++o)
+                if (o != ww) rank += count_less(md[o], mi[o], kp, kd, ki);
+            if (rank < kp) cand[rank] = kd < INFINITY ? ki : -1;
+        }
+        __syncthreads();
+    } else {
+        // every candidate survives the prefilter: phase 2 takes S as it is
+        // (it orders by float32 distance and id, whatever the slot order)
+        for (int c = (int)threadIdx.x; c < kp; c += (int)blockDim.x) cand[c] = c < ns ? S[c] : -1;
+        __syncthreads();
     }
-    __syncthreads();
 
     // phase 2: float32 direct distances of the survivors, gathered as in
     // dist_fp32 (same lanes per row, same summation order, U2 rows per group

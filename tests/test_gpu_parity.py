@@ -339,13 +339,15 @@ def test_gist_like_shape_full_parity(k, precision):
     _full_compare(X, Q, w.T, w.depth, w.a, w.index_seed, k, w.v, precision=prec)
 
 
-def test_fp8_arm_exact_when_rerank_covers_s():
-    # fp8 prefilter + float32 rerank + float64 recheck: when rerank_factor * k
-    # is at least |S| every candidate is reranked, so the arm must return the
-    # oracle's k nearest of S whatever the fp8 rounding did
-    _print_case("fp8 arm, rerank covering S")
+@pytest.mark.parametrize("precision", [mrpt.MRPT_FP8_RERANK, mrpt.MRPT_BF16_RERANK])
+def test_prefilter_arm_exact_when_rerank_covers_s(precision):
+    # fp8 / bf16 prefilter + float32 rerank + float64 recheck: when
+    # rerank_factor * k is at least |S| every candidate is reranked (the
+    # prefilter ranking is skipped), so the arm must return the oracle's k
+    # nearest of S whatever the low-precision rounding did
+    _print_case(f"prefilter arm {precision}, rerank covering S")
     X, Q = _small(6000, 32, 8, 5, seed=41, nq=70)
-    opts = dict(precision=mrpt.MRPT_FP8_RERANK, rerank_factor=100)
+    opts = dict(precision=precision, rerank_factor=100)
     gi, gd, ref = _full_compare(X, Q, 8, 5, 0.5, 5, 5, 4, precision=None)
     g = build(X, 8, 5, 0.5, 5)
     assert int(ref["s_count"].max()) <= 5 * 100
