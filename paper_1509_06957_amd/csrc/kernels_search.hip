@@ -372,7 +372,9 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
 
     // phase 2: float32 direct distances of the survivors, gathered as in
     // dist_fp32 (same lanes per row, same summation order, U2 rows per group
-    // in flight)
+    // in flight).  Slots past the kq = min(|S|, kp) survivors are empty (id
+    // -1, distance +inf): they keep their slot as their rank.
+    const int kq = ns < kp ? ns : kp;
     {
         const int g2 = lane / G2, gl2 = lane - g2 * G2;
         const int nvec = d >> 2;
@@ -383,12 +385,12 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
             q2[i] = vi < nvec ? reinterpret_cast<const float4*>(qs)[vi] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         constexpr int kStep2 = kDistWaves * GPW2 * U2;
-        for (int c0 = 0; c0 < kp; c0 += kStep2) {
+        for (int c0 = 0; c0 < kq; c0 += kStep2) {
             int32_t id[U2];
 #pragma unroll
             for (int u = 0; u < U2; ++u) {
                 const int c = c0 + (u * kDistWaves + w) * GPW2 + g2;
-                id[u] = c < kp ? cand[c] : -1;
+                id[u] = c < kq ? cand[c] : -1;
             }
             float4 xv2[U2][NV2];
 #pragma unroll
@@ -416,17 +418,22 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
                 }
                 const float r = group_sum<G2>(a);
                 const int c = c0 + (u * kDistWaves + w) * GPW2 + g2;
-                if (gl2 == 0 && c < kp) d32[c] = id[u] >= 0 ? r : INFINITY;
+                if (gl2 == 0 && c < kq) d32[c] = id[u] >= 0 ? r : INFINITY;
             }
         }
+        for (int c = kq + (int)threadIdx.x; c < kp; c += (int)blockDim.x) d32[c] = INFINITY;
     }
     __syncthreads();
     // order by (d32, id); empty slots (id -1, +inf) go last in slot order
     for (int c = (int)threadIdx.x; c < kp; c += (int)blockDim.x) {
+        if (c >= kq) {
+            order[c] = c;
+            continue;
+        }
         const float kd = d32[c];
         const int32_t ki = cand[c] < 0 ? kPadId + c : cand[c];
         int rank = 0;
-        for (int o = 0; o < kp; ++o) {
+        for (int o = 0; o < kq; ++o) {
             const int32_t oi = cand[o] < 0 ? kPadId + o : cand[o];
             rank += key_less(d32[o], oi, kd, ki) ? 1 : 0;
         }
