@@ -338,7 +338,7 @@ constexpr int kProjWaves = 8;
 // chain still runs over the features in ascending order, chunk after chunk.
 constexpr int kProjChunk = (64 * 1024) / (kQStride * 4);   // 252 features: 64 KB of LDS
 
-template <int RPW>
+template <int RPW, bool CHUNKED>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
                                                                      int32_t d, const int32_t* __restrict__ rowptr,
                                                                      const int32_t* __restrict__ col,
@@ -353,6 +353,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
     int colr[RPW];
     float valr[RPW];
     int kb[RPW];                         // first entry of the current chunk, per row
+    int maxlen = 0;
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
         len[i] = 0;
@@ -366,11 +367,27 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
                 colr[i] = col[b + lane];
                 valr[i] = val[b + lane];
             }
+            maxlen = len[i] > maxlen ? len[i] : maxlen;
         }
     }
     float acc[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) acc[i] = 0.0f;
+    if constexpr (!CHUNKED) {
+        // the whole tile fits: one staging, entries in order
+        stage_query_chunk(Q, q0, nq, d, 0, d, proj_smem);
+        __syncthreads();
+        for (int k = 0; k < maxlen; ++k) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                if (k < len[i]) {
+                    const int c = read_lane_i(colr[i], k);
+                    const float v = read_lane_f(valr[i], k);
+                    acc[i] = __builtin_fmaf(proj_smem[c * kQStride + lane], v, acc[i]);
+                }
+            }
+        }
+    } else
     for (int c0 = 0; c0 < d; c0 += kProjChunk) {
         const int cw = d - c0 < kProjChunk ? d - c0 : kProjChunk;
         if (c0 > 0) __syncthreads();     // every wave is done with the previous chunk
@@ -506,12 +523,27 @@ hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32
     if (m == 0 || nrows == 0) return hipSuccess;
     const int d = ix->d;
     const size_t lds = (size_t)std::min(d, kProjChunk) * kQStride * 4;
-    dim3 grid((unsigned)((m + kWave - 1) / kWave),
-              (unsigned)((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)));
-    (void)hipFuncSetAttribute((const void*)project_kernel<kProjRows>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL((project_kernel<kProjRows>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,
-                       ix->rowptr + row0, ix->col, ix->val, nrows, P);
+    const int64_t tiles = (m + kWave - 1) / kWave;
+    // a small batch gets 4 rows per wave: four times the waves, each with a
+    // shorter serial chain (the per-row arithmetic is the same)
+    const bool small = tiles * ((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)) < 512;
+#define MRPT_PROJ(RPW, CH)                                                                                     \
+    do {                                                                                                      \
+        dim3 grid((unsigned)tiles, (unsigned)((nrows + kProjWaves * (RPW) - 1) / (kProjWaves * (RPW))));      \
+        (void)hipFuncSetAttribute((const void*)project_kernel<RPW, CH>,                                       \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                      \
+        hipLaunchKernelGGL((project_kernel<RPW, CH>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,         \
+                           ix->rowptr + row0, ix->col, ix->val, nrows, P);                                    \
+    } while (0)
+    const bool chunked = d > kProjChunk;
+    if (small) {
+        if (chunked) MRPT_PROJ(4, true);
+        else MRPT_PROJ(4, false);
+    } else {
+        if (chunked) MRPT_PROJ(kProjRows, true);
+        else MRPT_PROJ(kProjRows, false);
+    }
+#undef MRPT_PROJ
     return hipGetLastError();
 }
 
