@@ -42,7 +42,7 @@ def parse():
     p.add_argument("--workload", default="sift_like")
     p.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     p.add_argument("--recall-sample", type=int, default=500)
-    p.add_argument("--latency-reps", type=int, default=50, help="timed calls per batch size")
+    p.add_argument("--latency-reps", type=int, default=50, help="timed calls per batch size (0: none)")
     p.add_argument("--cpu-sample", type=int, default=10000)
     p.add_argument("--no-host-build", action="store_true", help="skip timing the host build of the index")
     return p.parse_args()
@@ -250,7 +250,7 @@ def main():
     # host clock around the call and a synchronisation, inputs resident
     latency = {}
     for b in (1, 16, 256, 4096):
-        if b > nq:
+        if b > nq or args.latency_reps <= 0:
             continue
         ob = (torch.empty((b, k), dtype=torch.int32, device="cuda"),
               torch.empty((b, k), dtype=torch.float32, device="cuda"))

@@ -44,6 +44,27 @@ __device__ __forceinline__ void append(bool elect, int32_t id, int* nsel, int32_
     }
 }
 
+// The queries a multi-pass workgroup counts.  Counting all queries: q =
+// blockIdx.x, + gridDim.x, ... .  Recounting (redo_only): the workgroup owns
+// queries [blockIdx.x * 1024, + 1024), reads their counts in one coalesced
+// load and keeps those marked -1 (queue overflow) in `list`.  Returns how
+// many queries the workgroup takes; query `it` is redo_query(...).
+__device__ __forceinline__ int64_t redo_select(bool redo_only, int64_t nq, const int32_t* __restrict__ s_count,
+                                               int32_t* list, int* n) {
+    if (!redo_only) return blockIdx.x < nq ? (nq - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+    const int tid = (int)threadIdx.x;
+    if (tid == 0) *n = 0;
+    __syncthreads();
+    const int64_t qq = (int64_t)blockIdx.x * blockDim.x + tid;
+    if (qq < nq && s_count[qq] < 0) list[atomicAdd(n, 1)] = tid;
+    __syncthreads();
+    return *n;
+}
+
+__device__ __forceinline__ int64_t redo_query(bool redo_only, int64_t it, const int32_t* list) {
+    return redo_only ? (int64_t)blockIdx.x * blockDim.x + list[it] : (int64_t)blockIdx.x + it * gridDim.x;
+}
+
 // ---------------------------------------------------------------------------
 // multi-pass form
 // ---------------------------------------------------------------------------
@@ -98,8 +119,11 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
     const int lane = lane_id();
     const int w = uniform(tid >> 6);
     const int words = chunk / per;
-    for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
-    if (redo_only && s_count[q] >= 0) continue;
+    __shared__ int32_t redo_list[kVoteBlock];
+    __shared__ int redo_n;
+    const int64_t nwork = redo_select(redo_only != 0, nq, s_count, redo_list, &redo_n);
+    for (int64_t it = 0; it < nwork; ++it) {
+    const int64_t q = redo_query(redo_only != 0, it, redo_list);
 
     if (tid < T) {
         const int L = leaf[q * T + tid];
@@ -360,8 +384,11 @@ __global__ __launch_bounds__(kVoteBlock) void vote_dir_kernel(
     const int words = chunk >> 2;
     const uint32_t hit = (uint32_t)(v - 1);
     const uint32_t cap32 = (uint32_t)(cap < INT32_MAX ? cap : INT32_MAX);
-    for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
-        if (redo_only && s_count[q] >= 0) continue;
+    __shared__ int32_t redo_list[kVoteBlock];
+    __shared__ int redo_n;
+    const int64_t nwork = redo_select(redo_only != 0, nq, s_count, redo_list, &redo_n);
+    for (int64_t it = 0; it < nwork; ++it) {
+        const int64_t q = redo_query(redo_only != 0, it, redo_list);
         // thread t < T follows tree t's slice boundaries, one pass ahead: a
         // pass's slice starts where the previous one ended
         int64_t row = 0;
@@ -706,7 +733,7 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         if (queued) MRPT_MAP(SS, true);                                                                          \
         else MRPT_MAP(SS, false);                                                                                \
     } else
-        MRPT_MAP_S(8) MRPT_MAP_S(13) MRPT_MAP_S(16) MRPT_MAP_S(20) MRPT_MAP_S(25) MRPT_MAP_S(28) {
+        MRPT_MAP_S(4) MRPT_MAP_S(8) MRPT_MAP_S(13) MRPT_MAP_S(16) MRPT_MAP_S(20) MRPT_MAP_S(25) MRPT_MAP_S(28) {
             if (queued) MRPT_MAP(kVoteSlots, true);
             else MRPT_MAP(kVoteSlots, false);
         }
@@ -720,13 +747,14 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         if (qcap >= most) return e;
         // queries whose queue overflowed (count -1) are counted again, multi-pass
     }
-    // a recount visits every query but counts few: a small grid loops over them
-    const int64_t grid = single ? std::min<int64_t>(nq, 4 * device_cus()) : nq;
+    // a recount workgroup checks 1024 queries' counts at once and counts the
+    // few that overflowed
+    const int64_t grid = single ? (nq + kVoteBlock - 1) / kVoteBlock : nq;
 
     if (ix->vdir && mode != 1) {
         // passes on directory boundaries, a multiple of the grain each; one
         // byte per id
-        constexpr size_t fixed = kMaxT * (8 + 8 + 4) + 16 + 4 * kWave + 256;   // static LDS, aligned
+        constexpr size_t fixed = kMaxT * (8 + 8 + 4) + 16 + 4 * kWave + 4 * kVoteBlock + 256;   // static LDS
         const int64_t most = (int64_t)((limit - fixed) / 16) * 4 * 4;
         int64_t chunk = most / kDirGrain * kDirGrain;
         if (chunk >= kDirGrain) {
@@ -743,7 +771,7 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     }
     // multi-pass geometry for `fixed` bytes of static LDS: ids per pass, a
     // multiple of 4 words' worth of ids, and the number of passes
-    constexpr size_t fixed = kMaxT * 8 + kMaxT * 4 + 16;
+    constexpr size_t fixed = kMaxT * 8 + kMaxT * 4 + 16 + 4 * kVoteBlock + 256;   // static LDS, aligned
     int64_t chunk = (int64_t)((limit - fixed) / 16) * 4 * per;
     const int64_t padded = (ix->n + 4 * per - 1) / (4 * per) * (4 * per);
     if (chunk > padded) chunk = padded;
