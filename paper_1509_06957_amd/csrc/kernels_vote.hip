@@ -686,6 +686,11 @@ SingleGeometry single_geometry(const mrpt_index* ix, bool queued) {
     g.map_words = ((ix->n + kVoteSlots * kWave) / 32 + 1 + 3) / 4 * 4;
     const int64_t room = ((int64_t)limit - (int64_t)kMapTail - g.map_words * 4) / 4;
     g.qcap = queued ? std::min<int64_t>(room, (int64_t)ix->T * ix->max_leaf) / 4 * 4 : 0;
+    // MRPT_VOTE_QUEUE_CAP lowers the queue capacity (tests: queries then
+    // overflow and are recounted by a multi-pass kernel)
+    const char* cap_env = std::getenv("MRPT_VOTE_QUEUE_CAP");
+    if (queued && cap_env && *cap_env && std::atoll(cap_env) > 0)
+        g.qcap = std::min<int64_t>(g.qcap, std::atoll(cap_env) / 4 * 4);
     g.ok = g.slots <= kVoteSlots && ix->n < (int64_t(1) << 24) &&
            (int64_t)ix->T * ix->perm_ld < (int64_t(1) << 31) && room >= 0 && (!queued || g.qcap >= 1024);
     g.lds = (size_t)(g.map_words + g.qcap) * 4 + kMapTail;

@@ -281,9 +281,8 @@ def test_vote_kernel_variants_agree(kernel, monkeypatch):
     # without it (1) and the default choice (single-pass id map + repeat queue
     # where it fits) compute the same candidate
     # sets.  700 queries give every persistent workgroup several queries; the
-    # depth-1 case with v = 2 overflows the single-pass kernel's hash table
-    # (its queries are redone multi-pass) and, like the 140-tree case, has
-    # more windows than the single-pass kernel holds in registers
+    # depth-1 and the 140-tree cases have more windows than the single-pass
+    # kernel holds in registers
     _print_case(f"vote kernel {kernel}")
     if kernel == "default":
         monkeypatch.delenv("MRPT_VOTE_KERNEL", raising=False)
@@ -422,3 +421,34 @@ def test_exact_nnz_mode_parity(on_device):
                       S=[set(s.tolist()) for s in ref["s_ids"]])
     finally:
         gpu.close()
+
+
+@pytest.mark.parametrize("directory", [False, True])
+def test_vote_queue_overflow_is_recounted(directory, monkeypatch):
+    # a repeat queue capped at 1024 entries overflows for these queries; the
+    # single-pass kernel marks them and a multi-pass kernel recounts them (the
+    # one with the leaf directory when the index has one: built here by
+    # forcing the multi-pass choice at build time, then lifting it)
+    _print_case(f"vote queue overflow, recount with directory={directory}")
+    n, d, T, depth, v = 100_000, 8, 24, 7, 2
+    X, Q = _small(n, d, T, depth, seed=5, nq=300)
+    orc = oracle.build_index(X, T, depth, 0.5, 3)
+    if directory:
+        monkeypatch.setenv("MRPT_VOTE_KERNEL", "0")
+    g = build(X, T, depth, 0.5, 3)
+    monkeypatch.delenv("MRPT_VOTE_KERNEL", raising=False)
+    monkeypatch.setenv("MRPT_VOTE_QUEUE_CAP", "1024")
+    try:
+        ref = oracle.query(orc, Q, 5, v, want_sets=True)
+        leafsz = np.diff(orc.off)
+        repeats = np.array([leafsz[ref["leaf"][q]].sum() for q in range(len(Q))]) - \
+            oracle.query(orc, Q, 5, 1)["s_count"]
+        assert (repeats > 1024).mean() > 0.5          # most queries do overflow
+        ids, cnt = votes(g, dev(Q), v)
+        for q in range(len(Q)):
+            assert np.array_equal(ids[q], ref["s_ids"][q]), f"query {q}"
+            assert np.array_equal(cnt[q], ref["s_votes"][q])
+        gi, gd, sc = query(g, dev(Q), 5, v)
+        assert np.array_equal(sc, ref["s_count"])
+    finally:
+        g.close()
