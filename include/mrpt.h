@@ -163,11 +163,15 @@ mrpt_status mrpt_index_info(const mrpt_index* ix, mrpt_index_desc* out);
  * search of Sec. III (Alg. 3-4) exactly as mrpt_query_ex runs it, with the same
  * kernels, so a batch's results equal mrpt_query_ex's for the same arguments.
  *
- * A plan owns a workspace per batch, so batches do not wait for each other:
- * they are dealt over `branches` independent chains of the graph (balanced by
- * estimated work), and the GPU may run the chains concurrently.  The plan
- * keeps the pointers it was given: each launch reads the current contents of
- * every batch's Q and overwrites its outputs, in the launch stream's order.
+ * Batches with the same (index, k, v) are searched as one query call: their
+ * queries are gathered into a staging array and the results scattered back
+ * (every step works per query, so the results are the per-batch ones).  A
+ * plan owns the workspace and staging memory of every such group, so groups
+ * do not wait for each other: they are dealt over `branches` independent
+ * chains of the graph (balanced by estimated work), and the GPU may run the
+ * chains concurrently.  The plan keeps the pointers it was given: each launch
+ * reads the current contents of every batch's Q and overwrites its outputs,
+ * in the launch stream's order.
  * The indexes must outlive the plan.  Launches of one plan must not overlap
  * (they share the workspaces): order them on one stream or synchronise.
  */
@@ -203,7 +207,7 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
  * NULL = the null stream).  Asynchronous. */
 mrpt_status mrpt_plan_launch(mrpt_plan* plan, void* stream);
 
-/* Bytes of device memory the plan holds (its workspaces). */
+/* Bytes of device memory the plan holds (workspaces, staging arrays, copy tables). */
 int64_t mrpt_plan_device_bytes(const mrpt_plan* plan);
 
 /* Releases the plan (after its last launch has completed).  NULL is a no-op. */

@@ -578,11 +578,7 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
     int dev = 0;
     MRPT_HIP_TRY(hipGetDevice(&dev));
 
-    // every batch checked as a query call would be; workspace offsets
-    std::vector<int64_t> cap((size_t)nbatch);
-    std::vector<size_t> off((size_t)nbatch);
-    std::vector<double> work((size_t)nbatch);
-    size_t total = 0;
+    // every batch checked as a query call would be
     for (int32_t i = 0; i < nbatch; ++i) {
         const mrpt_batch& b = batches[i];
         mrpt_status st = check_query_args(b.index, b.Q, b.nq, b.k, b.v, b.out_idx, b.out_dist);
@@ -594,13 +590,59 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
             const std::string why = g_error;
             return fail(st, "batch %d: %s", i, why.c_str());
         }
-        cap[i] = candidate_cap(b.index, b.v);
-        off[i] = total;
-        total += workspace_layout(b.index, b.nq, cap[i], nullptr, nullptr);
+    }
+
+    // batches of one (index, k, v) form a group, searched as one query call:
+    // a multi-batch group gathers its queries into a staging array and
+    // scatters the results back (every kernel works per query, so the results
+    // are the per-batch ones).  Layout of the plan's allocation, per group:
+    // workspace | staged queries, results | gather jobs | scatter jobs.
+    struct Group {
+        const mrpt_index* ix;
+        int32_t k, v;
+        std::vector<int32_t> members;
+        int64_t rows = 0, cap = 0;
+        size_t ws_off = 0, q_off = 0, oi_off = 0, od_off = 0, gj_off = 0, sj_off = 0;
+        double work = 0.0;
+        bool staged() const { return members.size() > 1; }
+    };
+    std::vector<Group> groups;
+    for (int32_t i = 0; i < nbatch; ++i) {
+        const mrpt_batch& b = batches[i];
+        size_t gi = 0;
+        while (gi < groups.size() && !(groups[gi].ix == b.index && groups[gi].k == b.k && groups[gi].v == b.v)) ++gi;
+        if (gi == groups.size()) {
+            Group g;
+            g.ix = b.index;
+            g.k = b.k;
+            g.v = b.v;
+            groups.push_back(g);
+        }
+        groups[gi].members.push_back(i);
+        groups[gi].rows += b.nq;
+    }
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t total = 0;
+    for (Group& g : groups) {
+        g.cap = candidate_cap(g.ix, g.v);
+        g.ws_off = total;
+        total += align(workspace_layout(g.ix, g.rows, g.cap, nullptr, nullptr));
+        if (g.staged()) {
+            g.q_off = total;
+            total += align((size_t)g.rows * g.ix->d * sizeof(float));
+            g.oi_off = total;
+            total += align((size_t)g.rows * g.k * sizeof(int32_t));
+            g.od_off = total;
+            total += align((size_t)g.rows * g.k * sizeof(float));
+            g.gj_off = total;
+            total += align(g.members.size() * sizeof(CopyJob));
+            g.sj_off = total;
+            total += align(2 * g.members.size() * sizeof(CopyJob));
+        }
         // estimated bytes moved: leaf id lists, and candidate rows (about
         // T * leaf / v of them)
-        const double ids = (double)b.index->T * b.index->max_leaf;
-        work[i] = (double)b.nq * (4.0 * ids + 4.0 * b.index->d * ids / b.v);
+        const double ids = (double)g.ix->T * g.ix->max_leaf;
+        g.work = (double)g.rows * (4.0 * ids + 4.0 * g.ix->d * ids / g.v);
     }
 
     std::unique_ptr<mrpt_plan> plan;
@@ -616,22 +658,47 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
         return fail(MRPT_ENOMEM, "plan workspaces of %zu bytes", total);
     }
     plan->ws_bytes = total;
+    char* base = (char*)plan->ws_base;
 
-    // batches dealt to branches, largest first, each to the least loaded
-    std::vector<int32_t> order((size_t)nbatch);
-    for (int32_t i = 0; i < nbatch; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
-    const int nbr = std::min<int>(po.branches, nbatch);
+    // gather / scatter job tables of the staged groups
+    for (Group& g : groups) {
+        if (!g.staged()) continue;
+        std::vector<CopyJob> gather, scatter;
+        int64_t row = 0;
+        const int d = g.ix->d;
+        for (int32_t i : g.members) {
+            const mrpt_batch& b = batches[i];
+            gather.push_back({reinterpret_cast<const int32_t*>(b.Q),
+                              reinterpret_cast<int32_t*>(base + g.q_off) + row * d, b.nq * d});
+            scatter.push_back({reinterpret_cast<const int32_t*>(base + g.oi_off) + row * g.k, b.out_idx,
+                               b.nq * g.k});
+            scatter.push_back({reinterpret_cast<const int32_t*>(base + g.od_off) + row * g.k,
+                               reinterpret_cast<int32_t*>(b.out_dist), b.nq * g.k});
+            row += b.nq;
+        }
+        MRPT_HIP_TRY(hipMemcpy(base + g.gj_off, gather.data(), gather.size() * sizeof(CopyJob),
+                               hipMemcpyHostToDevice));
+        MRPT_HIP_TRY(hipMemcpy(base + g.sj_off, scatter.data(), scatter.size() * sizeof(CopyJob),
+                               hipMemcpyHostToDevice));
+    }
+
+    // groups dealt to branches, largest first, each to the least loaded
+    const int ng = (int)groups.size();
+    std::vector<int32_t> order((size_t)ng);
+    for (int32_t i = 0; i < ng; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return groups[x].work > groups[y].work; });
+    const int nbr = std::min<int>(po.branches, ng);
     std::vector<double> load((size_t)nbr, 0.0);
     std::vector<std::vector<int32_t>> chain((size_t)nbr);
     for (int32_t i : order) {
         const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[b] += work[i];
+        load[b] += groups[i].work;
         chain[b].push_back(i);
     }
 
     // record: fork from an origin stream to one stream per branch, every
-    // branch's batches in sequence, join back
+    // branch's groups in sequence (gather, search, scatter), join back
     std::vector<hipStream_t> bs((size_t)nbr, nullptr);
     std::vector<hipEvent_t> ev((size_t)nbr + 1, nullptr);
     hipStream_t origin = nullptr;
@@ -646,12 +713,28 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
     if (e == hipSuccess) e = hipEventRecord(ev[nbr], origin);
     for (int b = 0; b < nbr && e == hipSuccess; ++b) e = hipStreamWaitEvent(bs[b], ev[nbr], 0);
     for (int b = 0; b < nbr && e == hipSuccess; ++b) {
-        for (int32_t i : chain[b]) {
-            const mrpt_batch& bt = batches[i];
+        for (int32_t gi : chain[b]) {
+            const Group& g = groups[gi];
             Workspace ws;
-            (void)workspace_layout(bt.index, bt.nq, cap[i], (char*)plan->ws_base + off[i], &ws);
-            e = enqueue_batch(bt.index, ws, bt.Q, bt.nq, bt.k, bt.v, cap[i], o, bt.out_idx, bt.out_dist, bs[b],
-                              false);
+            (void)workspace_layout(g.ix, g.rows, g.cap, base + g.ws_off, &ws);
+            if (g.staged()) {
+                int64_t most = 0;
+                for (int32_t i : g.members) most = std::max<int64_t>(most, batches[i].nq * g.ix->d);
+                e = launch_copy_jobs(reinterpret_cast<const CopyJob*>(base + g.gj_off), (int32_t)g.members.size(),
+                                     most, bs[b]);
+                if (e == hipSuccess)
+                    e = enqueue_batch(g.ix, ws, reinterpret_cast<const float*>(base + g.q_off), g.rows, g.k, g.v,
+                                      g.cap, o, reinterpret_cast<int32_t*>(base + g.oi_off),
+                                      reinterpret_cast<float*>(base + g.od_off), bs[b], false);
+                most = 0;
+                for (int32_t i : g.members) most = std::max<int64_t>(most, batches[i].nq * g.k);
+                if (e == hipSuccess)
+                    e = launch_copy_jobs(reinterpret_cast<const CopyJob*>(base + g.sj_off),
+                                         2 * (int32_t)g.members.size(), most, bs[b]);
+            } else {
+                const mrpt_batch& bt = batches[g.members[0]];
+                e = enqueue_batch(g.ix, ws, bt.Q, bt.nq, g.k, g.v, g.cap, o, bt.out_idx, bt.out_dist, bs[b], false);
+            }
             if (e != hipSuccess) break;
         }
         if (e == hipSuccess) e = hipEventRecord(ev[b], bs[b]);

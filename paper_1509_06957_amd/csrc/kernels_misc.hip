@@ -103,6 +103,24 @@ hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8
     return hipGetLastError();
 }
 
+namespace {
+
+// job blockIdx.y: words [0, words) from src to dst, grid-stride over x
+__global__ __launch_bounds__(256) void copy_jobs_kernel(const CopyJob* __restrict__ jobs) {
+    const CopyJob j = jobs[blockIdx.y];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < j.words; i += stride) j.dst[i] = j.src[i];
+}
+
+}  // namespace
+
+hipError_t launch_copy_jobs(const CopyJob* jobs, int32_t njobs, int64_t max_words, hipStream_t s) {
+    if (njobs == 0 || max_words == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((max_words + 255) / 256, 128);
+    hipLaunchKernelGGL(copy_jobs_kernel, dim3((unsigned)blocks, (unsigned)njobs), dim3(256), 0, s, jobs);
+    return hipGetLastError();
+}
+
 hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, hipStream_t s) {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 3) / 4;

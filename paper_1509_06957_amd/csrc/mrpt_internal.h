@@ -159,6 +159,14 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
 hipError_t launch_copy_counts(const int32_t* src, int64_t nq, int32_t* dst, hipStream_t s);
 hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hipStream_t s);
 hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, hipStream_t s);
+// device-to-device copies of 4-byte words, one job per row of the grid
+// (jobs: device array; max_words: the largest job, sizes the grid)
+struct CopyJob {
+    const int32_t* src;
+    int32_t* dst;
+    int64_t words;
+};
+hipError_t launch_copy_jobs(const CopyJob* jobs, int32_t njobs, int64_t max_words, hipStream_t s);
 hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8, float* scale8, float* norm8,
                                hipStream_t s);
 
