@@ -190,6 +190,11 @@ typedef struct mrpt_plan_opts {
     int32_t rerank_factor;  /* as in mrpt_query_opts (default 4) */
     float recheck_rel;      /* as in mrpt_query_opts (default 1e-6) */
     int32_t branches;       /* independent chains, 1..64 (default 4) */
+    int32_t proj_rows;      /* projection vectors per wave: 0 (default) the launcher's choice
+                               (4 for launches under 512 workgroups, else 16), or 4, or 16 */
+    int32_t vote_kernel;    /* 0 (default) automatic; 1 the single-pass vote kernel wherever it
+                               fits; 2 the multi-pass one.  Neither knob changes a result; they
+                               are there for tuning the launches. */
 } mrpt_plan_opts;
 
 typedef struct mrpt_plan mrpt_plan;

@@ -3,9 +3,10 @@ stream of mixed query batches, searched by one query plan (one HIP graph
 launch per step).
 
 For every index of the workload the index is built on the GPU, the query
-batches are uploaded, and plans are recorded for a set of branch counts (the
-graph's independent chains).  A small autotuner times each candidate plan
-and keeps the fastest.  It reports:
+batches are uploaded, and plans are recorded for a grid of launch choices:
+the branch count (the graph's independent chains), the projection's vectors
+per wave and the vote kernel.  A small autotuner times each candidate plan
+and keeps the fastest (every choice gives the same results).  It reports:
   * plan_qps: queries/s of the tuned plan (all batches, one launch per step);
   * eager_qps: the same batches as one mrpt_query_ex call each, on one stream;
   * recall@k on a sample of queries against exact k-NN from the library's
@@ -33,6 +34,8 @@ def main():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--precision", default="bf16", choices=("fp32", "bf16"))
     p.add_argument("--branches", default="1,2,4,8,16")
+    p.add_argument("--proj-rows", default="0,16", help="projection vectors per wave to try (0: automatic)")
+    p.add_argument("--vote-kernels", default="0,2", help="vote kernels to try (0 automatic, 1 single-pass, 2 multi-pass)")
     p.add_argument("--recall-sample", type=int, default=2000)
     args = p.parse_args()
 
@@ -71,20 +74,23 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps * 1e3
 
-    # autotuner: the branch count of the recorded graph
+    # autotuner over the recorded graph's launch choices
     tuning = {}
     best = None
     for b in [int(x) for x in args.branches.split(",")]:
-        plan = mrpt.Plan(batches, precision=prec, branches=b)
-        ms = time_launches(plan.launch, max(2, args.steps // 2))
-        tuning[b] = round(ms, 4)
-        log(f"branches {b}: {ms:.3f} ms per step")
-        if best is None or ms < best[1]:
-            if best is not None:
-                best[2].close()
-            best = (b, ms, plan)
-        else:
-            plan.close()
+        for pr in [int(x) for x in args.proj_rows.split(",")]:
+            for vk in [int(x) for x in args.vote_kernels.split(",")]:
+                plan = mrpt.Plan(batches, precision=prec, branches=b, proj_rows=pr, vote_kernel=vk)
+                ms = time_launches(plan.launch, max(2, args.steps // 2))
+                key = f"branches={b},proj_rows={pr},vote_kernel={vk}"
+                tuning[key] = round(ms, 4)
+                log(f"{key}: {ms:.3f} ms per step")
+                if best is None or ms < best[1]:
+                    if best is not None:
+                        best[2].close()
+                    best = (key, ms, plan)
+                else:
+                    plan.close()
     b_best, _, plan = best
     plan_ms = time_launches(plan.launch, args.steps)
     out = plan.launch()
@@ -123,7 +129,7 @@ def main():
         "batches": len(stream), "queries": nq, "T": bw.T, "v": bw.v,
         "precision": "bf16+rerank" if prec == mrpt.MRPT_BF16_RERANK else "fp32",
         "plan_qps": round(nq / (plan_ms / 1e3), 1), "plan_ms_per_step": round(plan_ms, 4),
-        "branches": b_best, "tuning_ms": tuning,
+        "chosen": b_best, "tuning_ms": tuning,
         "eager_qps": round(nq / (eager_ms / 1e3), 1), "eager_ms_per_step": round(eager_ms, 4),
         "plan_equals_eager": bool(identical),
         "recall_at_k": round(hit / max(tot, 1), 4), "recall_sample_queries": taken,

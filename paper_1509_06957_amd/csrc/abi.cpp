@@ -196,16 +196,16 @@ mrpt_status check_arm(const mrpt_index* cix, int32_t k, const mrpt_query_opts& o
 // can record it.
 hipError_t enqueue_batch(const mrpt_index* ix, const Workspace& ws, const float* Qb, int64_t m, int32_t k,
                          int32_t v, int64_t cap, const mrpt_query_opts& o, int32_t* out_idx, float* out_dist,
-                         hipStream_t s, bool mark_stages) {
+                         hipStream_t s, bool mark_stages, const LaunchCfg& cfg = LaunchCfg()) {
     auto mark = [&](int i) -> hipError_t {
         if (!mark_stages || !o.stage_events || !o.stage_events[i]) return hipSuccess;
         return hipEventRecord((hipEvent_t)o.stage_events[i], s);
     };
     hipError_t e;
     if ((e = mark(0)) != hipSuccess) return e;
-    if ((e = launch_route(ix, Qb, m, ws.leaf, ws.pq, s)) != hipSuccess) return e;
+    if ((e = launch_route(ix, Qb, m, ws.leaf, ws.pq, s, cfg)) != hipSuccess) return e;
     if ((e = mark(1)) != hipSuccess) return e;
-    if ((e = launch_vote(ix, ws.leaf, m, v, ws.s_ids, cap, ws.s_count, s)) != hipSuccess) return e;
+    if ((e = launch_vote(ix, ws.leaf, m, v, ws.s_ids, cap, ws.s_count, s, cfg)) != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
     if (o.precision == MRPT_FP32)
         e = launch_dist_fp32(ix, Qb, m, ws.s_ids, cap, ws.s_count, k, out_idx, out_dist, s);
@@ -559,6 +559,8 @@ void mrpt_default_plan_opts(mrpt_plan_opts* o) {
     o->rerank_factor = 4;
     o->recheck_rel = 1e-6f;
     o->branches = 4;
+    o->proj_rows = 0;
+    o->vote_kernel = 0;
 }
 
 mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mrpt_plan_opts* opts,
@@ -570,6 +572,12 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
     mrpt_default_plan_opts(&po);
     if (opts) po = *opts;
     if (po.branches < 1 || po.branches > 64) return fail(MRPT_EINVAL, "branches = %d outside [1, 64]", po.branches);
+    if (po.proj_rows != 0 && po.proj_rows != 4 && po.proj_rows != 16)
+        return fail(MRPT_EINVAL, "proj_rows = %d is not 0, 4 or 16", po.proj_rows);
+    if (po.vote_kernel < 0 || po.vote_kernel > 2) return fail(MRPT_EINVAL, "vote_kernel = %d outside [0, 2]", po.vote_kernel);
+    LaunchCfg cfg;
+    cfg.proj_rows = po.proj_rows;
+    cfg.vote_kernel = po.vote_kernel;
     mrpt_query_opts o;
     mrpt_default_opts(&o);
     o.precision = (mrpt_precision)po.precision;
@@ -725,7 +733,7 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
                 if (e == hipSuccess)
                     e = enqueue_batch(g.ix, ws, reinterpret_cast<const float*>(base + g.q_off), g.rows, g.k, g.v,
                                       g.cap, o, reinterpret_cast<int32_t*>(base + g.oi_off),
-                                      reinterpret_cast<float*>(base + g.od_off), bs[b], false);
+                                      reinterpret_cast<float*>(base + g.od_off), bs[b], false, cfg);
                 most = 0;
                 for (int32_t i : g.members) most = std::max<int64_t>(most, batches[i].nq * g.k);
                 if (e == hipSuccess)
@@ -733,7 +741,8 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
                                          2 * (int32_t)g.members.size(), most, bs[b]);
             } else {
                 const mrpt_batch& bt = batches[g.members[0]];
-                e = enqueue_batch(g.ix, ws, bt.Q, bt.nq, g.k, g.v, g.cap, o, bt.out_idx, bt.out_dist, bs[b], false);
+                e = enqueue_batch(g.ix, ws, bt.Q, bt.nq, g.k, g.v, g.cap, o, bt.out_idx, bt.out_dist, bs[b], false,
+                                  cfg);
             }
             if (e != hipSuccess) break;
         }

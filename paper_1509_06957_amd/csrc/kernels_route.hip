@@ -519,14 +519,16 @@ constexpr int kProjRows = 16;   // rows per wave in project_kernel
 }  // namespace
 
 hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32_t row0, int32_t nrows, float* P,
-                          hipStream_t s) {
+                          hipStream_t s, int32_t rows_per_wave) {
     if (m == 0 || nrows == 0) return hipSuccess;
     const int d = ix->d;
     const size_t lds = (size_t)std::min(d, kProjChunk) * kQStride * 4;
     const int64_t tiles = (m + kWave - 1) / kWave;
     // a small batch gets 4 rows per wave: four times the waves, each with a
     // shorter serial chain (the per-row arithmetic is the same)
-    const bool small = tiles * ((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)) < 512;
+    const bool small = rows_per_wave == 4 ||
+                       (rows_per_wave != kProjRows &&
+                        tiles * ((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)) < 512);
 #define MRPT_PROJ(RPW, CH)                                                                                     \
     do {                                                                                                      \
         dim3 grid((unsigned)tiles, (unsigned)((nrows + kProjWaves * (RPW) - 1) / (kProjWaves * (RPW))));      \
@@ -550,10 +552,10 @@ hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32
 namespace {
 
 hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
-                            hipStream_t s) {
+                            hipStream_t s, const LaunchCfg& cfg) {
     const int depth = ix->depth;
     {
-        hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s);
+        hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s, cfg.proj_rows);
         if (e != hipSuccess) return e;
     }
     const int nsplit = (1 << depth) - 1;
@@ -590,10 +592,10 @@ size_t route_workspace_floats(const mrpt_index* ix, int64_t nq) {
 }
 
 hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
-                        hipStream_t s) {
+                        hipStream_t s, const LaunchCfg& cfg) {
     if (nq == 0) return hipSuccess;
     if (ix->max_row_nnz <= kWave) {
-        if (pq) return launch_route_two(ix, Q, nq, leaf, pq, s);
+        if (pq) return launch_route_two(ix, Q, nq, leaf, pq, s, cfg);
         return launch_route_fast(ix, Q, nq, leaf, s);
     }
     const int depth = ix->depth;

@@ -710,10 +710,12 @@ int device_cus() {
 
 template <int B>
 hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
-                         int64_t cap, int32_t* s_count, hipStream_t s) {
+                         int64_t cap, int32_t* s_count, hipStream_t s, const LaunchCfg& cfg) {
     constexpr int per = 32 / B;
     const size_t limit = vote_lds_limit();
-    const int mode = vote_kernel_override();
+    // a pinned choice first (multi-pass: with the directory when there is
+    // one), else the environment override, else automatic
+    const int mode = cfg.vote_kernel == 2 ? 0 : cfg.vote_kernel == 1 ? -1 : vote_kernel_override();
     const bool queued = v >= 2;   // repeats are queued and rerun
     const SingleGeometry sg = single_geometry(ix, queued);
     const bool single = mode < 0 && sg.ok;
@@ -793,12 +795,12 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
 }  // namespace
 
 hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
-                       int64_t cap, int32_t* s_count, hipStream_t s) {
+                       int64_t cap, int32_t* s_count, hipStream_t s, const LaunchCfg& cfg) {
     if (nq == 0) return hipSuccess;
-    if (v == 1) return launch_vote_b<1>(ix, leaf, nq, v, s_ids, cap, s_count, s);
-    if (v <= 3) return launch_vote_b<2>(ix, leaf, nq, v, s_ids, cap, s_count, s);
-    if (v <= 15) return launch_vote_b<4>(ix, leaf, nq, v, s_ids, cap, s_count, s);
-    return launch_vote_b<8>(ix, leaf, nq, v, s_ids, cap, s_count, s);
+    if (v == 1) return launch_vote_b<1>(ix, leaf, nq, v, s_ids, cap, s_count, s, cfg);
+    if (v <= 3) return launch_vote_b<2>(ix, leaf, nq, v, s_ids, cap, s_count, s, cfg);
+    if (v <= 15) return launch_vote_b<4>(ix, leaf, nq, v, s_ids, cap, s_count, s, cfg);
+    return launch_vote_b<8>(ix, leaf, nq, v, s_ids, cap, s_count, s, cfg);
 }
 
 hipError_t build_vote_directory(mrpt_index* ix, int64_t* tally) {

@@ -132,17 +132,25 @@ hipError_t grow_trees_device(mrpt_index* ix, int32_t t0, int32_t g,
                              int64_t* node_off, hipStream_t s);
 
 // kernel launchers (kernels_route/vote/search/misc.hip); all asynchronous
+// kernel variants a caller may pin (0 = the launcher's own choice); none of
+// them changes a result
+struct LaunchCfg {
+    int32_t proj_rows = 0;     // projection vectors per wave: 4 or 16
+    int32_t vote_kernel = 0;   // 1: single-pass where it fits, 2: multi-pass
+};
+
 // projections of the m rows of A onto vectors row0 .. row0 + nrows - 1:
 // P[r * m + i] (the float32 fused multiply-add chain of Sec. II-C)
 hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32_t row0, int32_t nrows, float* P,
-                          hipStream_t s);
+                          hipStream_t s, int32_t rows_per_wave = 0);
 // pq: scratch of route_workspace_floats(ix, nq) floats for the projections
 // (nullptr selects the fused single-kernel form)
 size_t route_workspace_floats(const mrpt_index* ix, int64_t nq);
 hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
-                        hipStream_t s);
+                        hipStream_t s, const LaunchCfg& cfg = LaunchCfg());
 hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v,
-                       int32_t* s_ids, int64_t cap, int32_t* s_count, hipStream_t s);
+                       int32_t* s_ids, int64_t cap, int32_t* s_count, hipStream_t s,
+                       const LaunchCfg& cfg = LaunchCfg());
 // the leaf directory of the multi-pass vote kernel, when the index needs one
 // (after perm and the leaf offsets are on the device); adds its bytes to *tally
 hipError_t build_vote_directory(mrpt_index* ix, int64_t* tally);

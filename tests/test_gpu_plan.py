@@ -126,3 +126,18 @@ def test_plan_rejects_bad_batch(setup):
             mrpt.Plan([(tiny, q, 1, 1)], precision=mrpt.MRPT_BF16_RERANK)
         finally:
             tiny.close()
+
+
+@pytest.mark.parametrize("proj_rows,vote_kernel", [(4, 0), (16, 0), (0, 1), (0, 2)])
+def test_plan_launch_choices_keep_results(setup, proj_rows, vote_kernel):
+    # the tunable launch choices (projection vectors per wave, single- or
+    # multi-pass voting) change no result
+    _, _, ixs, stream, _, Qs = setup
+    print(f"[case] plan proj_rows={proj_rows} vote_kernel={vote_kernel}", flush=True)
+    ref = eager(ixs, stream, Qs, mrpt.MRPT_BF16_RERANK)
+    plan = mrpt.Plan([(ixs[ix], Q, k, SMALL.v) for (_, ix, _, k), Q in zip(stream, Qs)],
+                     precision=mrpt.MRPT_BF16_RERANK, branches=3, proj_rows=proj_rows, vote_kernel=vote_kernel)
+    out = plan.launch()
+    torch.cuda.synchronize()
+    same(out, ref, f"proj_rows={proj_rows} vote_kernel={vote_kernel}")
+    plan.close()
