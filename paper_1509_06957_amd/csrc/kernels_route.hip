@@ -78,7 +78,7 @@ __device__ __forceinline__ void stage_query_tile(const float* __restrict__ Q, in
 // features [c0, c0 + cw) of the 64-query tile starting at q0 into LDS as
 // qt[(feature - c0) * 65 + query]; rows past nq read as zero
 __device__ __forceinline__ void stage_query_chunk(const float* __restrict__ Q, int64_t q0, int64_t nq, int d, int c0,
-                                                  int cw, float* qt) {
+                                                  int cw, float* qt, int fstride = kQStride) {
     const int tid = (int)threadIdx.x, nthreads = (int)blockDim.x;
     const int total = kWave * cw;
     const int step_q = nthreads / cw, step_f = nthreads - step_q * cw;
@@ -100,7 +100,7 @@ __device__ __forceinline__ void stage_query_chunk(const float* __restrict__ Q, i
         }
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u)
-            if (e0 + u * nthreads < total) qt[rf[u] * kQStride + rq[u]] = r[u];
+            if (e0 + u * nthreads < total) qt[rf[u] * fstride + rq[u]] = r[u];
     }
 }
 
@@ -317,11 +317,12 @@ __global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict
 // Two-kernel form (every projection vector has at most 64 nonzeros).
 //
 // project_kernel: Pq[r][q] = q . R_r for all T*depth rows r, i.e. the sparse
-// product of Sec. II-C for a batch of queries.  A workgroup takes a 64-query
-// tile (staged in LDS as [feature][query] when it fits) and 8 waves x RPW
-// rows; a wave keeps its RPW rows in registers (lane e holds entry e) and
-// advances them together, one nonzero per row per step, so RPW fused
-// multiply-add chains overlap while each runs in ascending feature order.
+// product of Sec. II-C for a batch of queries.  A workgroup takes a tile of
+// 64 * QPL queries (staged in LDS as [feature][query] when it fits) and
+// 8 waves x RPW rows; a wave keeps its RPW rows in registers (lane e holds
+// entry e) and advances them together, one nonzero per row per step, so
+// RPW * QPL fused multiply-add chains overlap while each runs in ascending
+// feature order.  The steps that every row has run without a branch.
 // Writes are coalesced along queries.
 //
 // route_pq_kernel: Alg. 3's descent for one tree and a range of queries, the
@@ -338,22 +339,23 @@ constexpr int kProjWaves = 8;
 // chain still runs over the features in ascending order, chunk after chunk.
 constexpr int kProjChunk = (64 * 1024) / (kQStride * 4);   // 252 features: 64 KB of LDS
 
-template <int RPW, bool CHUNKED>
+template <int RPW, bool CHUNKED, int QPL>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
                                                                      int32_t d, const int32_t* __restrict__ rowptr,
                                                                      const int32_t* __restrict__ col,
                                                                      const float* __restrict__ val, int32_t nrows,
                                                                      float* __restrict__ Pq) {
-    extern __shared__ float proj_smem[];   // [min(d, kProjChunk)][65]
+    static_assert(QPL == 1 || !CHUNKED, "two queries per lane only with the whole tile in LDS");
+    extern __shared__ float proj_smem[];   // [min(d, kProjChunk)][QPL][65]
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
-    const int64_t q0 = (int64_t)blockIdx.x * kWave;
+    const int64_t q0 = (int64_t)blockIdx.x * (kWave * QPL);
     const int r0 = uniform((int)blockIdx.y * (kProjWaves * RPW) + w * RPW);
     int len[RPW];
     int colr[RPW];
     float valr[RPW];
     int kb[RPW];                         // first entry of the current chunk, per row
-    int maxlen = 0;
+    int maxlen = 0, minlen = kWave;
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
         len[i] = 0;
@@ -369,21 +371,44 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
             }
             maxlen = len[i] > maxlen ? len[i] : maxlen;
         }
+        minlen = len[i] < minlen ? len[i] : minlen;
     }
-    float acc[RPW];
+    float acc[QPL][RPW];
 #pragma unroll
-    for (int i = 0; i < RPW; ++i) acc[i] = 0.0f;
+    for (int h = 0; h < QPL; ++h)
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) acc[h][i] = 0.0f;
     if constexpr (!CHUNKED) {
-        // the whole tile fits: one staging, entries in order
-        stage_query_chunk(Q, q0, nq, d, 0, d, proj_smem);
+        // the whole tile fits: one staging, entries in order; lane l holds
+        // queries q0 + l and q0 + 64 + l (QPL = 2), which share every
+        // nonzero taken from the row registers
+        constexpr int FS = QPL * kQStride;
+#pragma unroll
+        for (int h = 0; h < QPL; ++h)
+            stage_query_chunk(Q, q0 + h * kWave, nq, d, 0, d, proj_smem + h * kQStride, FS);
         __syncthreads();
-        for (int k = 0; k < maxlen; ++k) {
+        // entries every row has: no branch, so the LDS reads of all rows
+        // issue together; then the rows' remaining entries
+        int k = 0;
+        for (; k < minlen; ++k) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                const int c = read_lane_i(colr[i], k);
+                const float v = read_lane_f(valr[i], k);
+#pragma unroll
+                for (int h = 0; h < QPL; ++h)
+                    acc[h][i] = __builtin_fmaf(proj_smem[c * FS + h * kQStride + lane], v, acc[h][i]);
+            }
+        }
+        for (; k < maxlen; ++k) {
 #pragma unroll
             for (int i = 0; i < RPW; ++i) {
                 if (k < len[i]) {
                     const int c = read_lane_i(colr[i], k);
                     const float v = read_lane_f(valr[i], k);
-                    acc[i] = __builtin_fmaf(proj_smem[c * kQStride + lane], v, acc[i]);
+#pragma unroll
+                    for (int h = 0; h < QPL; ++h)
+                        acc[h][i] = __builtin_fmaf(proj_smem[c * FS + h * kQStride + lane], v, acc[h][i]);
                 }
             }
         }
@@ -396,30 +421,43 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
         // entries of row i in this chunk: [kb[i], ke[i]), a prefix count of
         // the entries below the chunk's end
         int ke[RPW];
-        int span = 0;
+        int span = 0, common = kWave;
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             ke[i] = (int)__popcll(__builtin_amdgcn_ballot_w64(lane < len[i] && colr[i] < c0 + cw));
             span = ke[i] - kb[i] > span ? ke[i] - kb[i] : span;
+            common = ke[i] - kb[i] < common ? ke[i] - kb[i] : common;
         }
-        for (int k = 0; k < span; ++k) {
+        int k = 0;
+        for (; k < common; ++k) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                const int c = read_lane_i(colr[i], kb[i] + k);
+                const float v = read_lane_f(valr[i], kb[i] + k);
+                acc[0][i] = __builtin_fmaf(proj_smem[(c - c0) * kQStride + lane], v, acc[0][i]);
+            }
+        }
+        for (; k < span; ++k) {
 #pragma unroll
             for (int i = 0; i < RPW; ++i) {
                 if (kb[i] + k < ke[i]) {
                     const int c = read_lane_i(colr[i], kb[i] + k);
                     const float v = read_lane_f(valr[i], kb[i] + k);
-                    acc[i] = __builtin_fmaf(proj_smem[(c - c0) * kQStride + lane], v, acc[i]);
+                    acc[0][i] = __builtin_fmaf(proj_smem[(c - c0) * kQStride + lane], v, acc[0][i]);
                 }
             }
         }
 #pragma unroll
         for (int i = 0; i < RPW; ++i) kb[i] = ke[i];
     }
-    const int64_t q = q0 + lane;
-    if (q < nq) {
 #pragma unroll
-        for (int i = 0; i < RPW; ++i)
-            if (r0 + i < nrows) Pq[(int64_t)(r0 + i) * nq + q] = acc[i];
+    for (int h = 0; h < QPL; ++h) {
+        const int64_t q = q0 + h * kWave + lane;
+        if (q < nq) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i)
+                if (r0 + i < nrows) Pq[(int64_t)(r0 + i) * nq + q] = acc[h][i];
+        }
     }
 }
 
@@ -514,7 +552,11 @@ hipError_t launch_route_fast(const mrpt_index* ix, const float* Q, int64_t nq, i
     return hipGetLastError();
 }
 
-constexpr int kProjRows = 16;   // rows per wave in project_kernel
+constexpr int kProjRows = 16;     // rows per wave in project_kernel
+// at most this d, a lane of a large batch takes two queries: the tile
+// (128 queries, 66.5 KB at d = 128) still leaves room for two workgroups
+// per CU, and each nonzero read out of the row registers serves both
+constexpr int kProjPairMaxD = 128;
 
 }  // namespace
 
@@ -522,28 +564,30 @@ hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32
                           hipStream_t s, int32_t rows_per_wave) {
     if (m == 0 || nrows == 0) return hipSuccess;
     const int d = ix->d;
-    const size_t lds = (size_t)std::min(d, kProjChunk) * kQStride * 4;
     const int64_t tiles = (m + kWave - 1) / kWave;
     // a small batch gets 4 rows per wave: four times the waves, each with a
     // shorter serial chain (the per-row arithmetic is the same)
     const bool small = rows_per_wave == 4 ||
                        (rows_per_wave != kProjRows &&
                         tiles * ((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)) < 512);
-#define MRPT_PROJ(RPW, CH)                                                                                     \
+#define MRPT_PROJ(RPW, CH, QPL)                                                                                \
     do {                                                                                                      \
-        dim3 grid((unsigned)tiles, (unsigned)((nrows + kProjWaves * (RPW) - 1) / (kProjWaves * (RPW))));      \
-        (void)hipFuncSetAttribute((const void*)project_kernel<RPW, CH>,                                       \
+        const size_t lds = (size_t)std::min(d, kProjChunk) * kQStride * 4 * (QPL);                           \
+        dim3 grid((unsigned)((m + kWave * (QPL) - 1) / (kWave * (QPL))),                                      \
+                  (unsigned)((nrows + kProjWaves * (RPW) - 1) / (kProjWaves * (RPW))));                       \
+        (void)hipFuncSetAttribute((const void*)project_kernel<RPW, CH, QPL>,                                  \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                      \
-        hipLaunchKernelGGL((project_kernel<RPW, CH>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,         \
+        hipLaunchKernelGGL((project_kernel<RPW, CH, QPL>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,    \
                            ix->rowptr + row0, ix->col, ix->val, nrows, P);                                    \
     } while (0)
     const bool chunked = d > kProjChunk;
     if (small) {
-        if (chunked) MRPT_PROJ(4, true);
-        else MRPT_PROJ(4, false);
+        if (chunked) MRPT_PROJ(4, true, 1);
+        else MRPT_PROJ(4, false, 1);
     } else {
-        if (chunked) MRPT_PROJ(kProjRows, true);
-        else MRPT_PROJ(kProjRows, false);
+        if (chunked) MRPT_PROJ(kProjRows, true, 1);
+        else if (d <= kProjPairMaxD) MRPT_PROJ(kProjRows, false, 2);
+        else MRPT_PROJ(kProjRows, false, 1);
     }
 #undef MRPT_PROJ
     return hipGetLastError();

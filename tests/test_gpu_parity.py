@@ -153,6 +153,22 @@ def test_ragged_query_tiles(nq):
     _full_compare(X, Q, 6, 5, 0.2, 11, 10, 2)
 
 
+@pytest.mark.parametrize("nq,d", [(8250, 128), (8300, 96), (8200, 129)])
+def test_large_batch_projection_tiles(nq, d):
+    """Batches large enough for the projection's large-batch form: 16 rows per
+    wave, with two queries per lane for d <= 128 (the last tile's second half
+    empty at nq = 8250, partly filled at 8300) and one above."""
+    _print_case(f"large-batch projection nq={nq} d={d}")
+    rng = np.random.default_rng(nq + d)
+    X = rng.standard_normal((20000, d)).astype(np.float32)
+    Q = rng.standard_normal((nq, d)).astype(np.float32)
+    T, depth, a, seed = 64, 8, 1 / np.sqrt(d), 31
+    orc = oracle.build_index(X, T, depth, a, seed)
+    g = build(X, T, depth, a, seed)
+    assert np.array_equal(leaves(g, dev(Q)), oracle.route(orc, Q))
+    g.close()
+
+
 @pytest.mark.parametrize("d", [1, 3, 4, 13, 36, 64, 200, 520])
 def test_dimensions_generic_and_vector_kernels(d):
     _print_case(f"dim d={d}")
