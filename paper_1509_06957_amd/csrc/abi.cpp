@@ -39,7 +39,7 @@ hipError_t dev_alloc(T** p, size_t count, int64_t* tally) {
 }
 
 void dev_release(mrpt_index* ix) {
-    void* ptrs[] = {ix->X, ix->Xb, ix->X8, ix->scale8, ix->norm8, ix->rowptr, ix->col, ix->val,
+    void* ptrs[] = {ix->X, ix->Xb, ix->X8, ix->sn8, ix->rowptr, ix->col, ix->val,
                     ix->splits, ix->perm, ix->off, ix->vdir, ix->ws.base};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -403,8 +403,7 @@ mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, in
     const bool fp8 = d % 16 == 0 && d <= 1024;
     if (fp8) {
         if ((e = dev_alloc(&ix->X8, nd, &ix->device_bytes)) != hipSuccess) return oom(e, "fp8 data");
-        if ((e = dev_alloc(&ix->scale8, (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "fp8 scales");
-        if ((e = dev_alloc(&ix->norm8, (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "fp8 norms");
+        if ((e = dev_alloc(&ix->sn8, (size_t)n, &ix->device_bytes)) != hipSuccess) return oom(e, "fp8 scales");
     }
 
     MRPT_HIP_TRY(hipMemcpy(ix->rowptr, ix->h_rowptr.data(), ix->h_rowptr.size() * sizeof(int32_t),
@@ -432,7 +431,7 @@ mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, in
     MRPT_HIP_TRY(hipMemcpy(ix->off, off32.data(), off32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (on_device) MRPT_TRY(build_trees_on_device(ix.get()));
     MRPT_HIP_TRY(launch_quantize_bf16(ix->X, n, d, ix->Xb, nullptr));
-    if (fp8) MRPT_HIP_TRY(launch_quantize_fp8(ix->X, n, d, ix->X8, ix->scale8, ix->norm8, nullptr));
+    if (fp8) MRPT_HIP_TRY(launch_quantize_fp8(ix->X, n, d, ix->X8, ix->sn8, nullptr));
     if ((e = build_vote_directory(ix.get(), &ix->device_bytes)) != hipSuccess) return oom(e, "leaf directory");
     MRPT_HIP_TRY(hipDeviceSynchronize());
 

@@ -53,11 +53,12 @@ hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hip
 // scale| <= 240 is finite in both e4m3 encodings), and norm = scale^2 *
 // sum(decode(code)^2) in float32, so that the prefilter's ||x^||^2 is the
 // squared norm of exactly the row it decodes (stored: recomputing it per
-// candidate costs the fp8 prefilter more than the load).  One wave per row,
+// candidate costs the fp8 prefilter more than the load).  Scale and norm sit
+// side by side (one float2 per row), so a candidate costs one 8-byte load
+// beyond its codes rather than two scattered 4-byte ones.  One wave per row,
 // d % 4 == 0.
 __global__ __launch_bounds__(256) void quantize_fp8_kernel(const float* __restrict__ X, int64_t n, int32_t d,
-                                                           uint8_t* __restrict__ X8, float* __restrict__ scale8,
-                                                           float* __restrict__ norm8) {
+                                                           uint8_t* __restrict__ X8, float2* __restrict__ sn8) {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < n; row += waves) {
@@ -87,19 +88,15 @@ __global__ __launch_bounds__(256) void quantize_fp8_kernel(const float* __restri
         }
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) {
-            scale8[row] = scale;
-            norm8[row] = (scale * scale) * acc;
-        }
+        if (lane == 0) sn8[row] = make_float2(scale, (scale * scale) * acc);
     }
 }
 
-hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8, float* scale8, float* norm8,
-                               hipStream_t s) {
+hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8, float2* sn8, hipStream_t s) {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 3) / 4;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(quantize_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, X8, scale8, norm8);
+    hipLaunchKernelGGL(quantize_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, X8, sn8);
     return hipGetLastError();
 }
 

@@ -212,8 +212,7 @@ constexpr int kFmtFp8 = 1;
 template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
 __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __restrict__ X,
                                                              const uint8_t* __restrict__ Xq,
-                                                             const float* __restrict__ xscale,
-                                                             const float* __restrict__ norm8, int32_t d,
+                                                             const float2* __restrict__ sn8, int32_t d,
                                                         const float* __restrict__ Q,
                                                         const int32_t* __restrict__ s_ids, int64_t cap,
                                                         const int32_t* __restrict__ s_count, int32_t k,
@@ -294,8 +293,9 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
                     const int vi = gl + i * GB;
                     xv[u][i] = xr[vi < nv8 ? vi : 0];
                 }
-                xs[u] = FMT == kFmtFp8 ? xscale[row] : 1.0f;
-                xn[u] = FMT == kFmtFp8 ? norm8[row] : 0.0f;
+                const float2 sn = FMT == kFmtFp8 ? sn8[row] : make_float2(1.0f, 0.0f);
+                xs[u] = sn.x;
+                xn[u] = sn.y;
             }
     #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -304,7 +304,8 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
             }
             // the dot product q.x~; the bfloat16 row's squared norm is accumulated
             // beside it from the row in registers (no norm load), the fp8 row's
-            // (scale^2 * sum decode^2, stored at build) is loaded with the scale
+            // (scale^2 * sum decode^2, stored at build) comes with the scale in
+            // one 8-byte load
             float s[U];
     #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -563,8 +564,8 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
     dim3 grid((unsigned)nq), block(256);
     const uint8_t* Xq = fp8 ? ix->X8 : reinterpret_cast<const uint8_t*>(ix->Xb);
 #define MRPT_PF(F, GB, NVB, RR, G2, NV2)                                                                           \
-    hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, RR, G2, NV2>), grid, block, 0, s, ix->X, Xq, ix->scale8, \
-                       ix->norm8, d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
+    hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, RR, G2, NV2>), grid, block, 0, s, ix->X, Xq, ix->sn8, d, \
+                       Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
 #define MRPT_PF_R(F, GB, NVB, G2, NV2)                  \
     switch (RB) {                                       \
         case 1: MRPT_PF(F, GB, NVB, 1, G2, NV2); break; \

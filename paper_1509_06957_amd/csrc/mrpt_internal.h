@@ -85,8 +85,7 @@ struct mrpt_index {
     float* X = nullptr;          // n x d
     uint16_t* Xb = nullptr;      // n x d bfloat16 bits (round to nearest even)
     uint8_t* X8 = nullptr;       // n x d fp8 (e4m3) codes (d % 16 == 0 and d <= 1024, else unset)
-    float* scale8 = nullptr;     // n: per-row scale of the fp8 codes
-    float* norm8 = nullptr;      // n: squared norm of the decoded fp8 row
+    float2* sn8 = nullptr;       // n: (per-row scale of the fp8 codes, squared norm of the decoded row)
     int32_t* rowptr = nullptr;   // T*depth + 1
     int32_t* col = nullptr;      // nnz
     float* val = nullptr;        // nnz
@@ -175,7 +174,6 @@ struct CopyJob {
     int64_t words;
 };
 hipError_t launch_copy_jobs(const CopyJob* jobs, int32_t njobs, int64_t max_words, hipStream_t s);
-hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8, float* scale8, float* norm8,
-                               hipStream_t s);
+hipError_t launch_quantize_fp8(const float* X, int64_t n, int32_t d, uint8_t* X8, float2* sn8, hipStream_t s);
 
 }  // namespace mrpt
