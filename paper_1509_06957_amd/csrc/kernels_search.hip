@@ -210,15 +210,13 @@ constexpr int kFmtBf16 = 0;
 constexpr int kFmtFp8 = 1;
 
 template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
-__global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __restrict__ X,
-                                                             const uint8_t* __restrict__ Xq,
-                                                             const float2* __restrict__ sn8, int32_t d,
-                                                        const float* __restrict__ Q,
-                                                        const int32_t* __restrict__ s_ids, int64_t cap,
-                                                        const int32_t* __restrict__ s_count, int32_t k,
-                                                        int32_t kp, float recheck_rel,
-                                                        int32_t* __restrict__ out_idx,
-                                                        float* __restrict__ out_dist) {
+__device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X, const uint8_t* __restrict__ Xq,
+                                                    const float2* __restrict__ sn8, int32_t d,
+                                                    const float* __restrict__ Q,
+                                                    const int32_t* __restrict__ s_ids, int64_t cap,
+                                                    const int32_t* __restrict__ s_count, int32_t k, int32_t kp,
+                                                    float recheck_rel, int32_t* __restrict__ out_idx,
+                                                    float* __restrict__ out_dist) {
     constexpr int GPW = kWave / GB;
     constexpr int U = 8 / NVB;
     constexpr int EPU = FMT == kFmtBf16 ? 8 : 16;      // row values per 16-byte load
@@ -507,6 +505,42 @@ __global__ __launch_bounds__(256) void dist_prefilter_kernel(const float* __rest
     }
 }
 
+#define MRPT_PF_PARAMS                                                                                          \
+    const float *__restrict__ X, const uint8_t *__restrict__ Xq, const float2 *__restrict__ sn8, int32_t d,    \
+        const float *__restrict__ Q, const int32_t *__restrict__ s_ids, int64_t cap,                           \
+        const int32_t *__restrict__ s_count, int32_t k, int32_t kp, float recheck_rel,                         \
+        int32_t *__restrict__ out_idx, float *__restrict__ out_dist
+#define MRPT_PF_ARGS X, Xq, sn8, d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist
+
+template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
+__global__ __launch_bounds__(256) void dist_prefilter_kernel(MRPT_PF_PARAMS) {
+    dist_prefilter_body<FMT, GB, NVB, RB, G2, NV2>(MRPT_PF_ARGS);
+}
+
+// The same kernel held to 72 registers, for seven waves per SIMD instead of
+// six.  Used where that costs no spill: bf16 rows of d <= 128 with kp <= 64
+// (the fp8 forms and larger kp spill heavily under the cap).
+template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void dist_prefilter_w7_kernel(
+    MRPT_PF_PARAMS) {
+    dist_prefilter_body<FMT, GB, NVB, RB, G2, NV2>(MRPT_PF_ARGS);
+}
+
+#undef MRPT_PF_ARGS
+#undef MRPT_PF_PARAMS
+
+template <int F, int GB, int NVB, int RR, int G2, int NV2>
+void launch_prefilter_form(dim3 grid, hipStream_t s, const float* X, const uint8_t* Xq, const float2* sn8, int32_t d,
+                           const float* Q, const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k,
+                           int32_t kp, float recheck_rel, int32_t* out_idx, float* out_dist) {
+    if constexpr (F == kFmtBf16 && GB == 16 && NVB == 1 && RR == 1)
+        hipLaunchKernelGGL((dist_prefilter_w7_kernel<F, GB, NVB, RR, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
+                           Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
+    else
+        hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, RR, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d, Q,
+                           s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
+}
+
 }  // namespace
 
 hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, int64_t nq, const int32_t* s_ids, int64_t cap,
@@ -561,11 +595,11 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
     const int d = ix->d;
     const int kp = k * rerank;
     const int RB = kp <= 64 ? 1 : kp <= 128 ? 2 : kp <= 256 ? 4 : 8;
-    dim3 grid((unsigned)nq), block(256);
+    dim3 grid((unsigned)nq);
     const uint8_t* Xq = fp8 ? ix->X8 : reinterpret_cast<const uint8_t*>(ix->Xb);
-#define MRPT_PF(F, GB, NVB, RR, G2, NV2)                                                                           \
-    hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, RR, G2, NV2>), grid, block, 0, s, ix->X, Xq, ix->sn8, d, \
-                       Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist)
+#define MRPT_PF(F, GB, NVB, RR, G2, NV2)                                                                        \
+    launch_prefilter_form<F, GB, NVB, RR, G2, NV2>(grid, s, ix->X, Xq, ix->sn8, d, Q, s_ids, cap, s_count, k, kp, \
+                                                   recheck_rel, out_idx, out_dist)
 #define MRPT_PF_R(F, GB, NVB, G2, NV2)                  \
     switch (RB) {                                       \
         case 1: MRPT_PF(F, GB, NVB, 1, G2, NV2); break; \
