@@ -221,6 +221,15 @@ def test_bf16_generic_shapes():
                                         precision=mrpt.MRPT_BF16_RERANK)
 
 
+@pytest.mark.parametrize("k", [16, 17, 30, 100])
+def test_bf16_rerank_widths_at_d128(k):
+    """bf16 + rerank at d = 128 for every width of the kept list: k * 4 = 64
+    (the seven-wave form), 68 and 120 (two registers per lane), 400 (eight)."""
+    _print_case(f"bf16 d=128 k={k}")
+    X, Q = _small(3000, 128, 6, 3, seed=k, integer=True)
+    _full_compare(X, Q, 6, 3, 2 / np.sqrt(128), 5, k, 1, exact_ids=True, precision=mrpt.MRPT_BF16_RERANK)
+
+
 def test_streams_and_nq_zero():
     _print_case("stream")
     X, Q = _small(2000, 32, 4, 4, seed=10)
