@@ -46,7 +46,9 @@ __device__ __forceinline__ void append(bool elect, int32_t id, int* nsel, int32_
 
 // The queries a multi-pass workgroup counts.  Counting all queries: q =
 // blockIdx.x, + gridDim.x, ... .  Recounting (redo_only): the workgroup owns
-// queries [blockIdx.x * 1024, + 1024), reads their counts in one coalesced
+// the per = ceil(nq / gridDim.x) <= 1024 queries from blockIdx.x * per (the
+// grid is at least ceil(nq / 1024) and about one workgroup per CU, so many
+// overflows still spread over the chip), reads their counts in one coalesced
 // load and keeps those marked -1 (queue overflow) in `list`.  Returns how
 // many queries the workgroup takes; query `it` is redo_query(...).
 __device__ __forceinline__ int64_t redo_select(bool redo_only, int64_t nq, const int32_t* __restrict__ s_count,
@@ -55,14 +57,16 @@ __device__ __forceinline__ int64_t redo_select(bool redo_only, int64_t nq, const
     const int tid = (int)threadIdx.x;
     if (tid == 0) *n = 0;
     __syncthreads();
-    const int64_t qq = (int64_t)blockIdx.x * blockDim.x + tid;
-    if (qq < nq && s_count[qq] < 0) list[atomicAdd(n, 1)] = tid;
+    const int64_t per = (nq + gridDim.x - 1) / gridDim.x;
+    const int64_t qq = (int64_t)blockIdx.x * per + tid;
+    if (tid < per && qq < nq && s_count[qq] < 0) list[atomicAdd(n, 1)] = tid;
     __syncthreads();
     return *n;
 }
 
-__device__ __forceinline__ int64_t redo_query(bool redo_only, int64_t it, const int32_t* list) {
-    return redo_only ? (int64_t)blockIdx.x * blockDim.x + list[it] : (int64_t)blockIdx.x + it * gridDim.x;
+__device__ __forceinline__ int64_t redo_query(bool redo_only, int64_t it, const int32_t* list, int64_t nq) {
+    return redo_only ? (int64_t)blockIdx.x * ((nq + gridDim.x - 1) / gridDim.x) + list[it]
+                     : (int64_t)blockIdx.x + it * gridDim.x;
 }
 
 // ---------------------------------------------------------------------------
@@ -123,7 +127,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_kernel(const int32_t* __restr
     __shared__ int redo_n;
     const int64_t nwork = redo_select(redo_only != 0, nq, s_count, redo_list, &redo_n);
     for (int64_t it = 0; it < nwork; ++it) {
-    const int64_t q = redo_query(redo_only != 0, it, redo_list);
+    const int64_t q = redo_query(redo_only != 0, it, redo_list, nq);
 
     if (tid < T) {
         const int L = leaf[q * T + tid];
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_dir_kernel(
     __shared__ int redo_n;
     const int64_t nwork = redo_select(redo_only != 0, nq, s_count, redo_list, &redo_n);
     for (int64_t it = 0; it < nwork; ++it) {
-        const int64_t q = redo_query(redo_only != 0, it, redo_list);
+        const int64_t q = redo_query(redo_only != 0, it, redo_list, nq);
         // thread t < T follows tree t's slice boundaries, one pass ahead: a
         // pass's slice starts where the previous one ended
         int64_t row = 0;
@@ -754,9 +758,10 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         if (qcap >= most) return e;
         // queries whose queue overflowed (count -1) are counted again, multi-pass
     }
-    // a recount workgroup checks 1024 queries' counts at once and counts the
-    // few that overflowed
-    const int64_t grid = single ? (nq + kVoteBlock - 1) / kVoteBlock : nq;
+    // a recount workgroup checks up to 1024 queries' counts at once and
+    // counts those that overflowed; about one workgroup per CU
+    const int64_t grid = single ? std::max<int64_t>((nq + kVoteBlock - 1) / kVoteBlock, std::min<int64_t>(nq, device_cus()))
+                                : nq;
 
     if (ix->vdir && mode != 1) {
         // passes on directory boundaries, a multiple of the grain each; one
