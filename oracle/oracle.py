@@ -10,8 +10,12 @@ import numpy as np
 
 __all__ = [
     "load", "philox4x64_10", "random_matrix", "exact_nnz_count", "project", "leaf_offsets", "build_index",
-    "route", "query", "bruteforce", "distance", "OracleIndex", "default_threads",
+    "route", "query", "bruteforce", "distance", "OracleIndex", "default_threads", "all_threads",
+    "bf16_round", "bf16_value", "e4m3_round", "e4m3_value", "fp8_rows", "query_prefilter",
+    "ARM_BF16", "ARM_FP8",
 ]
+
+ARM_BF16, ARM_FP8 = 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
@@ -27,13 +31,18 @@ _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
 
 
-def default_threads() -> int:
-    """Host threads the oracle uses: the cores this process may run on, at most 16."""
+def all_threads() -> int:
+    """Every core this process may run on (its CPU affinity set)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(16, n))
+    return max(1, n)
+
+
+def default_threads() -> int:
+    """Host threads the oracle uses in tests: the cores this process may run on, at most 16."""
+    return min(16, all_threads())
 
 
 def load():
@@ -59,6 +68,20 @@ def load():
     lib.oracle_query.argtypes = [_f32p, _i64, _i32, _i32, _i32, _f32p, _f32p, _i32p, _i64p,
                                  _f32p, _i64, _i32, _i32, _i32p, _f64p, _vp, _vp, _vp, _i64, _vp, _i32]
     lib.oracle_bruteforce.argtypes = [_f32p, _i64, _i32, _f32p, _i64, _i32, _i32p, _f64p, _i32]
+    lib.oracle_bf16_value.argtypes = [ctypes.c_uint16]
+    lib.oracle_bf16_value.restype = ctypes.c_double
+    lib.oracle_bf16_round.argtypes = [ctypes.c_float]
+    lib.oracle_bf16_round.restype = ctypes.c_uint16
+    lib.oracle_to_bf16.argtypes = [_f32p, _i64, np.ctypeslib.ndpointer(dtype=np.uint16, flags="C_CONTIGUOUS")]
+    lib.oracle_e4m3_value.argtypes = [ctypes.c_uint8]
+    lib.oracle_e4m3_value.restype = ctypes.c_double
+    lib.oracle_e4m3_round.argtypes = [ctypes.c_float]
+    lib.oracle_e4m3_round.restype = ctypes.c_uint8
+    lib.oracle_to_fp8_rows.argtypes = [_f32p, _i64, _i32, np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS"),
+                                       _f32p, _f64p]
+    lib.oracle_query_prefilter.argtypes = [_f32p, _i64, _i32, _i32, _i32, _f32p, _f32p, _i32p, _i64p,
+                                           _f32p, _i64, _i32, _i32, _i32, _i32, _i32p, _f64p, _i64p,
+                                           _i32p, _f64p, _i32p, _i32]
     _lib = lib
     return lib
 
@@ -202,3 +225,75 @@ def distance(q, x):
     q = _c(q, np.float32)
     x = _c(x, np.float32)
     return load().oracle_distance(q, x, q.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# precision arms (not in the paper): low-precision rows and the prefilter
+# ---------------------------------------------------------------------------
+def bf16_round(x):
+    """bfloat16 bit patterns (uint16) of float32 values: round to nearest, ties to even."""
+    x = _c(x, np.float32)
+    out = np.zeros(x.shape, dtype=np.uint16)
+    if x.size:
+        load().oracle_to_bf16(x.reshape(-1), x.size, out.reshape(-1))
+    return out
+
+
+def bf16_value(b):
+    """float64 values of bfloat16 bit patterns."""
+    lib = load()
+    b = np.asarray(b, dtype=np.uint16)
+    return np.array([lib.oracle_bf16_value(int(v)) for v in b.reshape(-1)], dtype=np.float64).reshape(b.shape)
+
+
+def e4m3_value(codes):
+    """float64 values of OCP E4M3 codes (NaN for 0x7f and 0xff)."""
+    lib = load()
+    c = np.asarray(codes, dtype=np.uint8)
+    return np.array([lib.oracle_e4m3_value(int(v)) for v in c.reshape(-1)], dtype=np.float64).reshape(c.shape)
+
+
+def e4m3_round(y):
+    """E4M3 codes of float32 values: round to nearest, ties to the even code."""
+    lib = load()
+    y = np.asarray(y, dtype=np.float32)
+    return np.array([lib.oracle_e4m3_round(float(v)) for v in y.reshape(-1)], dtype=np.uint8).reshape(y.shape)
+
+
+def fp8_rows(X):
+    """Per-row scaled E4M3 rows: (codes n x d uint8, scale n float32 = max|x|/240,
+    norm n float64 = squared norm of the decoded row)."""
+    X = _c(X, np.float32)
+    n, d = X.shape
+    codes = np.zeros((n, d), dtype=np.uint8)
+    scale = np.zeros(n, dtype=np.float32)
+    norm = np.zeros(n, dtype=np.float64)
+    if n:
+        load().oracle_to_fp8_rows(X, n, d, codes, scale, norm)
+    return codes, scale, norm
+
+
+def query_prefilter(index, Q, k, v, arm, kp, nthreads=None):
+    """The precision arm of a query batch (arm = ARM_BF16 or ARM_FP8): S as in
+    query(), ranked by the float64 squared distance to the decoded rows, the
+    first kp under (score, id) kept, then the exact k-NN of the kept.
+
+    Returns dict with idx (nq,k), dist (nq,k) float64, s_count (nq,),
+    keep_ids (nq,kp) in score order (-1 padded), keep_score (nq,kp) float64,
+    keep_count (nq,) = min(|S|, kp)."""
+    Q = _c(Q, np.float32)
+    nq = Q.shape[0]
+    idx = np.zeros((nq, k), dtype=np.int32)
+    dist = np.zeros((nq, k), dtype=np.float64)
+    s_count = np.zeros(nq, dtype=np.int64)
+    keep_ids = np.zeros((nq, kp), dtype=np.int32)
+    keep_score = np.zeros((nq, kp), dtype=np.float64)
+    keep_count = np.zeros(nq, dtype=np.int32)
+    sp = index.splits if index.splits.size else np.zeros((index.T, 1), dtype=np.float32)
+    R = index.R if index.R.size else np.zeros((1, index.d), np.float32)
+    if nq:
+        load().oracle_query_prefilter(index.X, index.n, index.d, index.T, index.depth, R, _c(sp, np.float32),
+                                      index.perm, index.off, Q, nq, k, v, int(arm), int(kp), idx, dist, s_count,
+                                      keep_ids, keep_score, keep_count, nthreads or default_threads())
+    return {"idx": idx, "dist": dist, "s_count": s_count, "keep_ids": keep_ids, "keep_score": keep_score,
+            "keep_count": keep_count}

@@ -1,17 +1,23 @@
-"""Compile libmrpt.so (HIP for gfx950 + host C++) in-tree with hipcc."""
+"""Compile libmrpt.so (HIP for gfx950 + host C++) in-tree with hipcc.
+
+Every source is compiled to an object of its own (in parallel, under
+paper_1509_06957_amd/_build/), then linked into the shared library.
+"""
 import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmrpt.so")
 SOURCES = ["abi.cpp", "host_build.cpp", "kernels_route.hip", "kernels_vote.hip", "kernels_search.hip",
            "kernels_misc.hip", "kernels_build.hip"]
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     "--offload-arch=gfx950",
     # no packed-fp32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -29,21 +35,34 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(os.path.dirname(HERE), "include")] + srcs + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed for libmrpt.so")
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
     if verbose:
         # hipcc's host pass does not know the packed-fp32 feature: drop that note
         noise = [ln for ln in res.stderr.splitlines() if ln.strip() and "packed-fp32-ops" not in ln]
         if noise:
             print("\n".join(noise))
+
+
+def build(verbose: bool = False, jobs: int = 8) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", os.path.join(os.path.dirname(HERE), "include")]
+    objs = []
+    cmds = []
+    for s in SOURCES:
+        obj = os.path.join(OBJ, os.path.splitext(s)[0] + ".o")
+        objs.append(obj)
+        cmds.append([hipcc()] + FLAGS + inc + ["-c", os.path.join(CSRC, s), "-o", obj])
+    with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(cmds)))) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run([hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-pthread"] + objs + ["-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 
