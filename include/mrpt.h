@@ -249,6 +249,33 @@ mrpt_status mrpt_debug_votes(const mrpt_index* ix, const float* Q, int64_t nq, i
                              int32_t* s_count, int32_t* s_ids, uint8_t* s_votes, int64_t cap,
                              void* stream);
 
+/* Debug: the kept list of a prefilter arm (opts->precision MRPT_BF16_RERANK or
+ * MRPT_FP8_RERANK), computed by the query path's own kernels up to the end of
+ * the prefilter ranking: S_q is formed as in mrpt_query_ex, ranked by the
+ * low-precision squared distance ||q||^2 + ||x~||^2 - 2 q.x~ (x~ the bfloat16
+ * row, or the fp8 row times its scale), and the best kp = rerank_factor*k under
+ * (score, id) are kept.
+ *   s_count  : device int32[nq]        |S_q|
+ *   keep_ids : device int32[nq*kp]     row q: the kept ids, best first; -1
+ *              past min(|S_q|, kp).  When |S_q| <= kp nothing is ranked and
+ *              the row holds S_q in no particular order.
+ * Arguments and errors as mrpt_query_ex (MRPT_EINVAL for the float32 arm).
+ * Asynchronous on `stream`. */
+mrpt_status mrpt_debug_prefilter(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v,
+                                 const mrpt_query_opts* opts, int32_t* s_count, int32_t* keep_ids,
+                                 void* stream);
+
+/* Debug: the index's low-precision copy of rows [row0, row0 + nrows) of X.
+ *   precision  : MRPT_BF16_RERANK: rows receives uint16 bfloat16 patterns
+ *                (round to nearest even of the float32 value), nrows*d of them;
+ *                MRPT_FP8_RERANK: rows receives uint8 E4M3 codes, nrows*d, and
+ *                scale_norm (may be NULL) float[2*nrows] pairs (scale =
+ *                max|x|/240, squared norm of scale*decode(codes)).
+ *   rows, scale_norm : device memory.  Asynchronous on `stream`.
+ * MRPT_EINVAL for a row range outside [0, n) or an index without fp8 rows. */
+mrpt_status mrpt_debug_lowp_rows(const mrpt_index* ix, int32_t precision, int64_t row0, int64_t nrows,
+                                 void* rows, float* scale_norm, void* stream);
+
 /* Upper bound used for the per-query candidate buffer: min(n, floor(T*max_leaf/v)). */
 int64_t mrpt_candidate_cap(const mrpt_index* ix, int32_t v);
 

@@ -387,159 +387,6 @@ static void knn_in_set(const float *q, const float *X, int32_t d, const int32_t 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Voting (Sec. III-A).  f_t(x; q) = 1 when x lies in the leaf of tree t that */
-/* q is routed to, else 0; F(x; q) = sum_t f_t(x; q); the candidate set is    */
-/* S = {x : F(x; q) >= v}.  F is first summed over every tree, then S is read */
-/* off the points with a nonzero F, in ascending id order.                    */
-/*   F      : n counters, all zero on entry and on return                     */
-/*   touched: scratch of T * max_leaf ids                                     */
-/*   S, FS  : receive the members of S (ascending) and their F; returns |S|   */
-/* ------------------------------------------------------------------------ */
-static int64_t vote_set(const float *qv, int32_t d, int32_t T, int32_t depth, const float *R,
-                        const float *splits, const int32_t *perm, int64_t n, const int64_t *off,
-                        int32_t v, int32_t *F, int32_t *touched, int32_t *S, int32_t *FS,
-                        int32_t *leaf_out)
-{
-    int64_t nsplit = ((int64_t)1 << depth) - 1;
-    int64_t nt = 0;
-    for (int32_t t = 0; t < T; t++) {
-        int32_t L = route_one(qv, d, R + (int64_t)t * depth * d, depth, splits + (int64_t)t * nsplit);
-        if (leaf_out) leaf_out[t] = L;
-        const int32_t *pts = perm + (int64_t)t * n;
-        for (int64_t s = off[L]; s < off[L + 1]; s++) {
-            int32_t x = pts[s];
-            if (F[x] == 0) touched[nt++] = x;
-            F[x] += 1;                                  /* f_t(x; q) = 1 */
-        }
-    }
-    qsort(touched, (size_t)nt, sizeof(int32_t), cmp_id);
-    int64_t ns = 0;
-    for (int64_t i = 0; i < nt; i++) {
-        int32_t x = touched[i];
-        if (F[x] >= v) {
-            S[ns] = x;
-            FS[ns] = F[x];
-            ns++;
-        }
-        F[x] = 0;
-    }
-    return ns;
-}
-
-/* ------------------------------------------------------------------------ */
-/* approximate_knn (Alg. 4) for a batch of queries.                           */
-/*   off: leaf offsets (2^depth + 1), perm: T x n leaf lists.                 */
-/*   s_count[q] = |S| (optional).  If s_ids is given, the candidate ids of    */
-/*   query q, ascending, go to s_ids[q*s_cap ...] with their vote counts in   */
-/*   s_votes (|S| must fit in s_cap).                                          */
-/* ------------------------------------------------------------------------ */
-typedef struct {
-    const float *X; int64_t n; int32_t d; int32_t T; int32_t depth;
-    const float *R; const float *splits; const int32_t *perm; const int64_t *off;
-    const float *Q; int64_t nq; int32_t k; int32_t v;
-    int32_t *out_idx; double *out_dist; int64_t *s_count;
-    int32_t *s_ids; int32_t *s_votes; int64_t s_cap; int32_t *leaf_out;
-    /* precision arm (0: none) and its kept list */
-    int32_t arm; const double *Xt; int32_t kp; int32_t *keep_ids; double *keep_score; int32_t *keep_count;
-    int64_t first, stride;
-} query_job;
-
-static int64_t max_leaf_size(const int64_t *off, int32_t depth)
-{
-    int64_t m = 0;
-    for (int64_t L = 0; L < ((int64_t)1 << depth); L++)
-        if (off[L + 1] - off[L] > m) m = off[L + 1] - off[L];
-    return m;
-}
-
-/* squared Euclidean distance in float64 between q and a decoded row */
-static double sq_dist_decoded(const float *q, const double *xt, int32_t d)
-{
-    double s = 0.0;
-    for (int32_t i = 0; i < d; i++) {
-        double diff = (double)q[i] - xt[i];
-        s += diff * diff;
-    }
-    return s;
-}
-
-static void *query_worker(void *arg)
-{
-    query_job *j = (query_job *)arg;
-    int64_t ml = max_leaf_size(j->off, j->depth);
-    int64_t tcap = (int64_t)j->T * ml;
-    int32_t *F = (int32_t *)calloc((size_t)j->n, sizeof(int32_t));
-    int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tcap > 0 ? tcap : 1));
-    int32_t *S = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tcap > 0 ? tcap : 1));
-    int32_t *FS = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tcap > 0 ? tcap : 1));
-    cand_t *scratch = (cand_t *)malloc(sizeof(cand_t) * (size_t)(tcap > 0 ? tcap : 1));
-    int32_t *kept = (int32_t *)malloc(sizeof(int32_t) * (size_t)(j->kp > 0 ? j->kp : 1));
-    for (int64_t q = j->first; q < j->nq; q += j->stride) {
-        const float *qv = j->Q + q * j->d;
-        int64_t ns = vote_set(qv, j->d, j->T, j->depth, j->R, j->splits, j->perm, j->n, j->off, j->v,
-                              F, touched, S, FS, j->leaf_out ? j->leaf_out + q * j->T : NULL);
-        if (j->s_count) j->s_count[q] = ns;
-        if (j->s_ids) {
-            int64_t m = ns < j->s_cap ? ns : j->s_cap;
-            memcpy(j->s_ids + q * j->s_cap, S, sizeof(int32_t) * (size_t)m);
-            if (j->s_votes) memcpy(j->s_votes + q * j->s_cap, FS, sizeof(int32_t) * (size_t)m);
-        }
-        if (j->arm == 0) {
-            knn_in_set(qv, j->X, j->d, S, ns, j->k, scratch, j->out_idx + q * j->k, j->out_dist + q * j->k);
-            continue;
-        }
-        /* precision arm: rank S by the squared distance to the decoded rows, */
-        /* keep the first kp under (score, id), then the exact k-NN of those. */
-        int64_t nk = ns < j->kp ? ns : j->kp;
-        for (int64_t s = 0; s < ns; s++) {
-            scratch[s].id = S[s];
-            scratch[s].dist = sq_dist_decoded(qv, j->Xt + (int64_t)S[s] * j->d, j->d);
-        }
-        qsort(scratch, (size_t)ns, sizeof(cand_t), cmp_cand);
-        for (int64_t r = 0; r < j->kp; r++) {
-            j->keep_ids[q * j->kp + r] = r < nk ? scratch[r].id : -1;
-            j->keep_score[q * j->kp + r] = r < nk ? scratch[r].dist : INFINITY;
-        }
-        j->keep_count[q] = (int32_t)nk;
-        for (int64_t r = 0; r < nk; r++) kept[r] = scratch[r].id;
-        knn_in_set(qv, j->X, j->d, kept, nk, j->k, scratch, j->out_idx + q * j->k, j->out_dist + q * j->k);
-    }
-    free(kept); free(scratch); free(FS); free(S); free(touched); free(F);
-    return NULL;
-}
-
-static void run_query_jobs(query_job base, int32_t nthreads)
-{
-    if (nthreads < 1) nthreads = 1;
-    if (nthreads > base.nq) nthreads = (int32_t)(base.nq > 0 ? base.nq : 1);
-    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
-    query_job *jobs = (query_job *)malloc(sizeof(query_job) * (size_t)nthreads);
-    for (int32_t w = 0; w < nthreads; w++) {
-        jobs[w] = base;
-        jobs[w].first = w;
-        jobs[w].stride = nthreads;
-        pthread_create(&th[w], NULL, query_worker, &jobs[w]);
-    }
-    for (int32_t w = 0; w < nthreads; w++) pthread_join(th[w], NULL);
-    free(jobs); free(th);
-}
-
-void oracle_query(const float *X, int64_t n, int32_t d, int32_t T, int32_t depth,
-                  const float *R, const float *splits, const int32_t *perm, const int64_t *off,
-                  const float *Q, int64_t nq, int32_t k, int32_t v,
-                  int32_t *out_idx, double *out_dist, int64_t *s_count,
-                  int32_t *s_ids, int32_t *s_votes, int64_t s_cap, int32_t *leaf_out,
-                  int32_t nthreads)
-{
-    query_job j;
-    memset(&j, 0, sizeof(j));
-    j.X = X; j.n = n; j.d = d; j.T = T; j.depth = depth; j.R = R; j.splits = splits; j.perm = perm;
-    j.off = off; j.Q = Q; j.nq = nq; j.k = k; j.v = v; j.out_idx = out_idx; j.out_dist = out_dist;
-    j.s_count = s_count; j.s_ids = s_ids; j.s_votes = s_votes; j.s_cap = s_cap; j.leaf_out = leaf_out;
-    run_query_jobs(j, nthreads);
-}
-
-/* ------------------------------------------------------------------------ */
 /* Low-precision copies of the rows for the prefilter arms.  These are not in */
 /* the paper: the arms rank S by an approximate distance, then take the exact */
 /* k-NN of the best kp (the stated readings are listed in the design notes).  */
@@ -597,21 +444,26 @@ double oracle_e4m3_value(uint8_t code)
 
 /* round to nearest, ties to the even code, for finite |y| <= 448 (beyond */
 /* that the code is NaN); the sign of y is kept (a negative value that    */
-/* rounds to zero gives -0).  Every non-negative finite code is compared.  */
+/* rounds to zero gives -0).  The non-negative finite codes 0x00 .. 0x7e   */
+/* decode to increasing values, so the two codes around |y| are found by  */
+/* bisection and the nearer one is taken.                                  */
 uint8_t oracle_e4m3_round(float y)
 {
     double a = fabs((double)y);
     uint8_t sign = signbit(y) ? 0x80u : 0u;
     if (!(a <= 448.0)) return (uint8_t)(sign | 0x7fu);
-    int best = 0;
-    double bd = a;                                      /* distance to code 0 */
-    for (int c = 1; c < 127; c++) {                     /* 0x7f is NaN */
-        double dist = fabs(oracle_e4m3_value((uint8_t)c) - a);
-        if (dist < bd || (dist == bd && (c & 1) == 0 && (best & 1) == 1)) {
-            bd = dist;
-            best = c;
-        }
+    int lo = 0, hi = 0x7e;                              /* value(lo) <= a <= value(hi) */
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (oracle_e4m3_value((uint8_t)mid) <= a) lo = mid;
+        else hi = mid;
     }
+    double dlo = a - oracle_e4m3_value((uint8_t)lo);
+    double dhi = oracle_e4m3_value((uint8_t)hi) - a;
+    int best;
+    if (dlo < dhi) best = lo;
+    else if (dhi < dlo) best = hi;
+    else best = (lo % 2 == 0) ? lo : hi;                /* tie: the even code */
     return (uint8_t)(sign | (uint8_t)best);
 }
 
@@ -619,27 +471,197 @@ uint8_t oracle_e4m3_round(float y)
 /* all-zero row), code_i = e4m3(x_i / scale) with the division in float32,  */
 /* decoded value scale * e4m3value(code_i); norm = sum of the decoded       */
 /* values squared, in float64.                                              */
+static float fp8_row(const float *x, int32_t d, uint8_t *codes, double *decoded)
+{
+    float mx = 0.0f;
+    for (int32_t i = 0; i < d; i++) {
+        float ax = fabsf(x[i]);
+        if (ax > mx) mx = ax;
+    }
+    float s = mx > 0.0f ? mx / 240.0f : 1.0f;
+    for (int32_t i = 0; i < d; i++) {
+        uint8_t c = oracle_e4m3_round(x[i] / s);
+        if (codes) codes[i] = c;
+        if (decoded) decoded[i] = (double)s * oracle_e4m3_value(c);
+    }
+    return s;
+}
+
 void oracle_to_fp8_rows(const float *X, int64_t n, int32_t d, uint8_t *codes, float *scale, double *norm)
 {
+    double *dec = (double *)malloc(sizeof(double) * (size_t)d);
     for (int64_t r = 0; r < n; r++) {
-        const float *x = X + r * d;
-        float mx = 0.0f;
-        for (int32_t i = 0; i < d; i++) {
-            float ax = fabsf(x[i]);
-            if (ax > mx) mx = ax;
-        }
-        float s = mx > 0.0f ? mx / 240.0f : 1.0f;
+        scale[r] = fp8_row(X + r * d, d, codes + r * d, dec);
         double nn = 0.0;
-        for (int32_t i = 0; i < d; i++) {
-            float y = x[i] / s;
-            uint8_t c = oracle_e4m3_round(y);
-            codes[r * d + i] = c;
-            double t = (double)s * oracle_e4m3_value(c);
-            nn += t * t;
-        }
-        scale[r] = s;
+        for (int32_t i = 0; i < d; i++) nn += dec[i] * dec[i];
         norm[r] = nn;
     }
+    free(dec);
+}
+
+/* the decoded low-precision copy of one row: arm 1 bfloat16, arm 2 fp8 */
+static void decode_row(int32_t arm, const float *x, int32_t d, double *out)
+{
+    if (arm == 1) {
+        for (int32_t i = 0; i < d; i++) out[i] = oracle_bf16_value(oracle_bf16_round(x[i]));
+    } else {
+        (void)fp8_row(x, d, NULL, out);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Voting (Sec. III-A).  f_t(x; q) = 1 when x lies in the leaf of tree t that */
+/* q is routed to, else 0; F(x; q) = sum_t f_t(x; q); the candidate set is    */
+/* S = {x : F(x; q) >= v}.  F is first summed over every tree, then S is read */
+/* off the points with a nonzero F, in ascending id order.                    */
+/*   F      : n counters, all zero on entry and on return                     */
+/*   touched: scratch of T * max_leaf ids                                     */
+/*   S, FS  : receive the members of S (ascending) and their F; returns |S|   */
+/* ------------------------------------------------------------------------ */
+static int64_t vote_set(const float *qv, int32_t d, int32_t T, int32_t depth, const float *R,
+                        const float *splits, const int32_t *perm, int64_t n, const int64_t *off,
+                        int32_t v, int32_t *F, int32_t *touched, int32_t *S, int32_t *FS,
+                        int32_t *leaf_out)
+{
+    int64_t nsplit = ((int64_t)1 << depth) - 1;
+    int64_t nt = 0;
+    for (int32_t t = 0; t < T; t++) {
+        int32_t L = route_one(qv, d, R + (int64_t)t * depth * d, depth, splits + (int64_t)t * nsplit);
+        if (leaf_out) leaf_out[t] = L;
+        const int32_t *pts = perm + (int64_t)t * n;
+        for (int64_t s = off[L]; s < off[L + 1]; s++) {
+            int32_t x = pts[s];
+            if (F[x] == 0) touched[nt++] = x;
+            F[x] += 1;                                  /* f_t(x; q) = 1 */
+        }
+    }
+    qsort(touched, (size_t)nt, sizeof(int32_t), cmp_id);
+    int64_t ns = 0;
+    for (int64_t i = 0; i < nt; i++) {
+        int32_t x = touched[i];
+        if (F[x] >= v) {
+            S[ns] = x;
+            FS[ns] = F[x];
+            ns++;
+        }
+        F[x] = 0;
+    }
+    return ns;
+}
+
+/* ------------------------------------------------------------------------ */
+/* approximate_knn (Alg. 4) for a batch of queries.                           */
+/*   off: leaf offsets (2^depth + 1), perm: T x n leaf lists.                 */
+/*   s_count[q] = |S| (optional).  If s_ids is given, the candidate ids of    */
+/*   query q, ascending, go to s_ids[q*s_cap ...] with their vote counts in   */
+/*   s_votes (|S| must fit in s_cap).                                          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const float *X; int64_t n; int32_t d; int32_t T; int32_t depth;
+    const float *R; const float *splits; const int32_t *perm; const int64_t *off;
+    const float *Q; int64_t nq; int32_t k; int32_t v;
+    int32_t *out_idx; double *out_dist; int64_t *s_count;
+    int32_t *s_ids; int32_t *s_votes; int64_t s_cap; int32_t *leaf_out;
+    /* precision arm (0: none) and its kept list */
+    int32_t arm; int32_t kp; int32_t *keep_ids; double *keep_score; int32_t *keep_count;
+    int64_t first, stride;
+} query_job;
+
+static int64_t max_leaf_size(const int64_t *off, int32_t depth)
+{
+    int64_t m = 0;
+    for (int64_t L = 0; L < ((int64_t)1 << depth); L++)
+        if (off[L + 1] - off[L] > m) m = off[L + 1] - off[L];
+    return m;
+}
+
+/* squared Euclidean distance in float64 between q and a decoded row */
+static double sq_dist_decoded(const float *q, const double *xt, int32_t d)
+{
+    double s = 0.0;
+    for (int32_t i = 0; i < d; i++) {
+        double diff = (double)q[i] - xt[i];
+        s += diff * diff;
+    }
+    return s;
+}
+
+static void *query_worker(void *arg)
+{
+    query_job *j = (query_job *)arg;
+    int64_t ml = max_leaf_size(j->off, j->depth);
+    int64_t tcap = (int64_t)j->T * ml;
+    int32_t *F = (int32_t *)calloc((size_t)j->n, sizeof(int32_t));
+    int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tcap > 0 ? tcap : 1));
+    int32_t *S = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tcap > 0 ? tcap : 1));
+    int32_t *FS = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tcap > 0 ? tcap : 1));
+    cand_t *scratch = (cand_t *)malloc(sizeof(cand_t) * (size_t)(tcap > 0 ? tcap : 1));
+    int32_t *kept = (int32_t *)malloc(sizeof(int32_t) * (size_t)(j->kp > 0 ? j->kp : 1));
+    double *rowbuf = (double *)malloc(sizeof(double) * (size_t)j->d);
+    for (int64_t q = j->first; q < j->nq; q += j->stride) {
+        const float *qv = j->Q + q * j->d;
+        int64_t ns = vote_set(qv, j->d, j->T, j->depth, j->R, j->splits, j->perm, j->n, j->off, j->v,
+                              F, touched, S, FS, j->leaf_out ? j->leaf_out + q * j->T : NULL);
+        if (j->s_count) j->s_count[q] = ns;
+        if (j->s_ids) {
+            int64_t m = ns < j->s_cap ? ns : j->s_cap;
+            memcpy(j->s_ids + q * j->s_cap, S, sizeof(int32_t) * (size_t)m);
+            if (j->s_votes) memcpy(j->s_votes + q * j->s_cap, FS, sizeof(int32_t) * (size_t)m);
+        }
+        if (j->arm == 0) {
+            knn_in_set(qv, j->X, j->d, S, ns, j->k, scratch, j->out_idx + q * j->k, j->out_dist + q * j->k);
+            continue;
+        }
+        /* precision arm: rank S by the squared distance to the decoded rows, */
+        /* keep the first kp under (score, id), then the exact k-NN of those. */
+        int64_t nk = ns < j->kp ? ns : j->kp;
+        for (int64_t s = 0; s < ns; s++) {
+            decode_row(j->arm, j->X + (int64_t)S[s] * j->d, j->d, rowbuf);
+            scratch[s].id = S[s];
+            scratch[s].dist = sq_dist_decoded(qv, rowbuf, j->d);
+        }
+        qsort(scratch, (size_t)ns, sizeof(cand_t), cmp_cand);
+        for (int64_t r = 0; r < j->kp; r++) {
+            j->keep_ids[q * j->kp + r] = r < nk ? scratch[r].id : -1;
+            j->keep_score[q * j->kp + r] = r < nk ? scratch[r].dist : INFINITY;
+        }
+        j->keep_count[q] = (int32_t)nk;
+        for (int64_t r = 0; r < nk; r++) kept[r] = scratch[r].id;
+        knn_in_set(qv, j->X, j->d, kept, nk, j->k, scratch, j->out_idx + q * j->k, j->out_dist + q * j->k);
+    }
+    free(rowbuf); free(kept); free(scratch); free(FS); free(S); free(touched); free(F);
+    return NULL;
+}
+
+static void run_query_jobs(query_job base, int32_t nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > base.nq) nthreads = (int32_t)(base.nq > 0 ? base.nq : 1);
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    query_job *jobs = (query_job *)malloc(sizeof(query_job) * (size_t)nthreads);
+    for (int32_t w = 0; w < nthreads; w++) {
+        jobs[w] = base;
+        jobs[w].first = w;
+        jobs[w].stride = nthreads;
+        pthread_create(&th[w], NULL, query_worker, &jobs[w]);
+    }
+    for (int32_t w = 0; w < nthreads; w++) pthread_join(th[w], NULL);
+    free(jobs); free(th);
+}
+
+void oracle_query(const float *X, int64_t n, int32_t d, int32_t T, int32_t depth,
+                  const float *R, const float *splits, const int32_t *perm, const int64_t *off,
+                  const float *Q, int64_t nq, int32_t k, int32_t v,
+                  int32_t *out_idx, double *out_dist, int64_t *s_count,
+                  int32_t *s_ids, int32_t *s_votes, int64_t s_cap, int32_t *leaf_out,
+                  int32_t nthreads)
+{
+    query_job j;
+    memset(&j, 0, sizeof(j));
+    j.X = X; j.n = n; j.d = d; j.T = T; j.depth = depth; j.R = R; j.splits = splits; j.perm = perm;
+    j.off = off; j.Q = Q; j.nq = nq; j.k = k; j.v = v; j.out_idx = out_idx; j.out_dist = out_dist;
+    j.s_count = s_count; j.s_ids = s_ids; j.s_votes = s_votes; j.s_cap = s_cap; j.leaf_out = leaf_out;
+    run_query_jobs(j, nthreads);
 }
 
 /* the precision arm of a query batch: arm 1 = bfloat16 rows, arm 2 = fp8  */
@@ -654,27 +676,13 @@ void oracle_query_prefilter(const float *X, int64_t n, int32_t d, int32_t T, int
                             int32_t *out_idx, double *out_dist, int64_t *s_count,
                             int32_t *keep_ids, double *keep_score, int32_t *keep_count, int32_t nthreads)
 {
-    double *Xt = (double *)malloc(sizeof(double) * (size_t)(n * d));
-    if (arm == 1) {
-        for (int64_t i = 0; i < n * d; i++) Xt[i] = oracle_bf16_value(oracle_bf16_round(X[i]));
-    } else {
-        uint8_t *codes = (uint8_t *)malloc((size_t)(n * d));
-        float *scale = (float *)malloc(sizeof(float) * (size_t)n);
-        double *norm = (double *)malloc(sizeof(double) * (size_t)n);
-        oracle_to_fp8_rows(X, n, d, codes, scale, norm);
-        for (int64_t r = 0; r < n; r++)
-            for (int32_t i = 0; i < d; i++)
-                Xt[r * d + i] = (double)scale[r] * oracle_e4m3_value(codes[r * d + i]);
-        free(norm); free(scale); free(codes);
-    }
     query_job j;
     memset(&j, 0, sizeof(j));
     j.X = X; j.n = n; j.d = d; j.T = T; j.depth = depth; j.R = R; j.splits = splits; j.perm = perm;
     j.off = off; j.Q = Q; j.nq = nq; j.k = k; j.v = v; j.out_idx = out_idx; j.out_dist = out_dist;
-    j.s_count = s_count; j.arm = arm; j.Xt = Xt; j.kp = kp; j.keep_ids = keep_ids;
+    j.s_count = s_count; j.arm = arm; j.kp = kp; j.keep_ids = keep_ids;
     j.keep_score = keep_score; j.keep_count = keep_count;
     run_query_jobs(j, nthreads);
-    free(Xt);
 }
 
 /* ------------------------------------------------------------------------ */

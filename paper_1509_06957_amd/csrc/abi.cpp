@@ -46,15 +46,20 @@ void dev_release(mrpt_index* ix) {
     if (ix->ws.done) (void)hipEventDestroy(ix->ws.done);
 }
 
-bool is_device_pointer(const void* p) {
+// the device that holds p (device or managed memory), or -1 for host memory
+// and pointers HIP does not know
+int pointer_device(const void* p) {
     hipPointerAttribute_t attr;
     std::memset(&attr, 0, sizeof(attr));
     if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
         (void)hipGetLastError();
-        return false;
+        return -1;
     }
-    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) return -1;
+    return attr.device;
 }
+
+bool is_device_pointer(const void* p) { return pointer_device(p) >= 0; }
 
 mrpt_status check_index(const mrpt_index* ix) {
     if (!ix) return fail(MRPT_EINVAL, "index is NULL");
@@ -69,6 +74,13 @@ mrpt_status check_query_args(const mrpt_index* ix, const float* Q, int64_t nq, i
         return fail(MRPT_EINVAL, "k = %d outside [1, min(n, %d)]", k, kMaxK);
     if (v < 1 || v > ix->T) return fail(MRPT_EINVAL, "v = %d outside [1, T = %d]", v, ix->T);
     if (nq > 0 && (!Q || !out_idx || !out_dist)) return fail(MRPT_EINVAL, "NULL query or output pointer");
+    if (nq > 0) {
+        const void* ptrs[] = {Q, out_idx, out_dist};
+        const char* names[] = {"Q", "out_idx", "out_dist"};
+        for (int i = 0; i < 3; ++i)
+            if (pointer_device(ptrs[i]) != ix->device)
+                return fail(MRPT_EINVAL, "%s must be device memory of the index's device %d", names[i], ix->device);
+    }
     return MRPT_OK;
 }
 
@@ -225,6 +237,8 @@ mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_
     if (opts) o = *opts;
     MRPT_TRY(check_arm(cix, k, o));
     if (nq == 0) return MRPT_OK;
+    if (o.s_count && pointer_device(o.s_count) != cix->device)
+        return fail(MRPT_EINVAL, "s_count must be device memory of the index's device %d", cix->device);
     mrpt_index* ix = const_cast<mrpt_index*>(cix);
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lock(ix->mu);
@@ -544,6 +558,68 @@ mrpt_status mrpt_debug_votes(const mrpt_index* cix, const float* Q, int64_t nq, 
     MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, nq, v, s_ids, cap, s_count, s));
     if (s_votes) MRPT_HIP_TRY(launch_vote_counts(ix, ix->ws.leaf, nq, s_ids, cap, s_count, s_votes, s));
     MRPT_HIP_TRY(hipEventRecord(ix->ws.done, s));
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_debug_prefilter(const mrpt_index* cix, const float* Q, int64_t nq, int32_t k, int32_t v,
+                                 const mrpt_query_opts* opts, int32_t* s_count, int32_t* keep_ids, void* stream) {
+    clear_error();
+    MRPT_TRY(check_query_args(cix, Q, nq, k, v, keep_ids, keep_ids));
+    mrpt_query_opts o;
+    mrpt_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.precision == MRPT_FP32) return fail(MRPT_EINVAL, "the prefilter hook needs a prefilter arm");
+    MRPT_TRY(check_arm(cix, k, o));
+    if (nq > 0 && !s_count) return fail(MRPT_EINVAL, "s_count is NULL");
+    if (nq == 0) return MRPT_OK;
+    mrpt_index* ix = const_cast<mrpt_index*>(cix);
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(ix->mu);
+    MRPT_HIP_TRY(hipSetDevice(ix->device));
+    const int64_t cap = candidate_cap(ix, v);
+    const int64_t nb = batch_size(ix, nq, cap);
+    MRPT_TRY(ensure_workspace(ix, nb, cap));
+    MRPT_HIP_TRY(hipStreamWaitEvent(s, ix->ws.done, 0));
+    const int32_t kp = o.rerank_factor * k;
+    for (int64_t q0 = 0; q0 < nq; q0 += nb) {
+        const int64_t m = std::min(nb, nq - q0);
+        const float* Qb = Q + q0 * ix->d;
+        MRPT_HIP_TRY(launch_route(ix, Qb, m, ix->ws.leaf, ix->ws.pq, s));
+        MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, m, v, ix->ws.s_ids, cap, ix->ws.s_count, s));
+        MRPT_HIP_TRY(launch_dist_prefilter(ix, o.precision == MRPT_FP8_RERANK ? 1 : 0, Qb, m, ix->ws.s_ids, cap,
+                                           ix->ws.s_count, k, o.rerank_factor, o.recheck_rel, nullptr, nullptr, s,
+                                           keep_ids + q0 * kp));
+        MRPT_HIP_TRY(launch_copy_counts(ix->ws.s_count, m, s_count + q0, s));
+    }
+    MRPT_HIP_TRY(hipEventRecord(ix->ws.done, s));
+    return MRPT_OK;
+}
+
+mrpt_status mrpt_debug_lowp_rows(const mrpt_index* ix, int32_t precision, int64_t row0, int64_t nrows, void* rows,
+                                 float* scale_norm, void* stream) {
+    clear_error();
+    MRPT_TRY(check_index(ix));
+    if (row0 < 0 || nrows < 0 || row0 + nrows > ix->n)
+        return fail(MRPT_EINVAL, "rows [%lld, %lld) outside [0, n = %lld)", (long long)row0,
+                    (long long)(row0 + nrows), (long long)ix->n);
+    if (precision != MRPT_BF16_RERANK && precision != MRPT_FP8_RERANK)
+        return fail(MRPT_EINVAL, "precision %d has no low-precision rows", precision);
+    if (precision == MRPT_FP8_RERANK && !ix->X8)
+        return fail(MRPT_EINVAL, "the index has no fp8 rows (d %% 16 != 0 or d > 1024)");
+    if (nrows == 0) return MRPT_OK;
+    if (!rows) return fail(MRPT_EINVAL, "rows is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    MRPT_HIP_TRY(hipSetDevice(ix->device));
+    const size_t nd = (size_t)nrows * (size_t)ix->d;
+    if (precision == MRPT_BF16_RERANK) {
+        MRPT_HIP_TRY(hipMemcpyAsync(rows, ix->Xb + (size_t)row0 * ix->d, nd * sizeof(uint16_t),
+                                    hipMemcpyDeviceToDevice, s));
+    } else {
+        MRPT_HIP_TRY(hipMemcpyAsync(rows, ix->X8 + (size_t)row0 * ix->d, nd, hipMemcpyDeviceToDevice, s));
+        if (scale_norm)
+            MRPT_HIP_TRY(hipMemcpyAsync(scale_norm, ix->sn8 + row0, (size_t)nrows * sizeof(float2),
+                                        hipMemcpyDeviceToDevice, s));
+    }
     return MRPT_OK;
 }
 

@@ -209,14 +209,18 @@ __device__ __forceinline__ float bf16_hi(uint32_t w) { return __builtin_bit_cast
 constexpr int kFmtBf16 = 0;
 constexpr int kFmtFp8 = 1;
 
-template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
+// KEEP: stop after phase 1 and write the kept list (ids in prefilter rank
+// order, -1 past min(|S|, kp); S in slot order when |S| <= kp) to
+// keep_out[q * kp ...] instead of the k-NN (the parity hook of the arm)
+template <int FMT, int GB, int NVB, int RB, int G2, int NV2, bool KEEP = false>
 __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X, const uint8_t* __restrict__ Xq,
                                                     const float2* __restrict__ sn8, int32_t d,
                                                     const float* __restrict__ Q,
                                                     const int32_t* __restrict__ s_ids, int64_t cap,
                                                     const int32_t* __restrict__ s_count, int32_t k, int32_t kp,
                                                     float recheck_rel, int32_t* __restrict__ out_idx,
-                                                    float* __restrict__ out_dist) {
+                                                    float* __restrict__ out_dist,
+                                                    int32_t* __restrict__ keep_out = nullptr) {
     constexpr int GPW = kWave / GB;
     constexpr int U = 8 / NVB;
     constexpr int EPU = FMT == kFmtBf16 ? 8 : 16;      // row values per 16-byte load
@@ -368,6 +372,10 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
         for (int c = (int)threadIdx.x; c < kp; c += (int)blockDim.x) cand[c] = c < ns ? S[c] : -1;
         __syncthreads();
     }
+    if constexpr (KEEP) {
+        for (int c = (int)threadIdx.x; c < kp; c += (int)blockDim.x) keep_out[q * kp + c] = cand[c];
+        return;
+    }
 
     // phase 2: float32 direct distances of the survivors, gathered as in
     // dist_fp32 (same lanes per row, same summation order, U2 rows per group
@@ -417,7 +425,9 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
                 }
                 const float r = group_sum<G2>(a);
                 const int c = c0 + (u * kDistWaves + w) * GPW2 + g2;
-                if (gl2 == 0 && c < kq) d32[c] = id[u] >= 0 ? r : INFINITY;
+                // a NaN distance (non-finite query) ranks as +inf, i.e. as an
+                // empty slot: the ordering below needs keys that compare
+                if (gl2 == 0 && c < kq) d32[c] = (id[u] >= 0 && !__builtin_isnan(r)) ? r : INFINITY;
             }
         }
         for (int c = kq + (int)threadIdx.x; c < kp; c += (int)blockDim.x) d32[c] = INFINITY;
@@ -526,14 +536,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void d
     dist_prefilter_body<FMT, GB, NVB, RB, G2, NV2>(MRPT_PF_ARGS);
 }
 
+// phase 1 only: the kept list of every query (parity hook)
+template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
+__global__ __launch_bounds__(256) void dist_prefilter_keep_kernel(MRPT_PF_PARAMS, int32_t* __restrict__ keep_out) {
+    dist_prefilter_body<FMT, GB, NVB, RB, G2, NV2, true>(MRPT_PF_ARGS, keep_out);
+}
+
 #undef MRPT_PF_ARGS
 #undef MRPT_PF_PARAMS
 
 template <int F, int GB, int NVB, int RR, int G2, int NV2>
 void launch_prefilter_form(dim3 grid, hipStream_t s, const float* X, const uint8_t* Xq, const float2* sn8, int32_t d,
                            const float* Q, const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k,
-                           int32_t kp, float recheck_rel, int32_t* out_idx, float* out_dist) {
-    if constexpr (F == kFmtBf16 && GB == 16 && NVB == 1 && RR == 1)
+                           int32_t kp, float recheck_rel, int32_t* out_idx, float* out_dist, int32_t* keep_out) {
+    if (keep_out)
+        hipLaunchKernelGGL((dist_prefilter_keep_kernel<F, GB, NVB, RR, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8,
+                           d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist, keep_out);
+    else if constexpr (F == kFmtBf16 && GB == 16 && NVB == 1 && RR == 1)
         hipLaunchKernelGGL((dist_prefilter_w7_kernel<F, GB, NVB, RR, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
                            Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
     else
@@ -590,7 +609,7 @@ hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, int64_t nq, co
 
 hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, int64_t nq, const int32_t* s_ids,
                                  int64_t cap, const int32_t* s_count, int32_t k, int32_t rerank, float recheck_rel,
-                                 int32_t* out_idx, float* out_dist, hipStream_t s) {
+                                 int32_t* out_idx, float* out_dist, hipStream_t s, int32_t* keep_out) {
     if (nq == 0) return hipSuccess;
     const int d = ix->d;
     const int kp = k * rerank;
@@ -599,7 +618,7 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
     const uint8_t* Xq = fp8 ? ix->X8 : reinterpret_cast<const uint8_t*>(ix->Xb);
 #define MRPT_PF(F, GB, NVB, RR, G2, NV2)                                                                        \
     launch_prefilter_form<F, GB, NVB, RR, G2, NV2>(grid, s, ix->X, Xq, ix->sn8, d, Q, s_ids, cap, s_count, k, kp, \
-                                                   recheck_rel, out_idx, out_dist)
+                                                   recheck_rel, out_idx, out_dist, keep_out)
 #define MRPT_PF_R(F, GB, NVB, G2, NV2)                  \
     switch (RB) {                                       \
         case 1: MRPT_PF(F, GB, NVB, 1, G2, NV2); break; \

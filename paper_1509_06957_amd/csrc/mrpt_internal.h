@@ -159,10 +159,12 @@ hipError_t launch_vote_counts(const mrpt_index* ix, const int32_t* leaf, int64_t
 hipError_t launch_dist_fp32(const mrpt_index* ix, const float* Q, int64_t nq,
                             const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k,
                             int32_t* out_idx, float* out_dist, hipStream_t s);
-// bf16 (fp8 = 0) or fp8 (fp8 = 1) prefilter, float32 rerank, float64 recheck
+// bf16 (fp8 = 0) or fp8 (fp8 = 1) prefilter, float32 rerank, float64 recheck;
+// keep_out (device int32[nq * k * rerank]) non-null: phase 1 only, the kept
+// list of every query instead of the k-NN
 hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, int64_t nq, const int32_t* s_ids,
                                  int64_t cap, const int32_t* s_count, int32_t k, int32_t rerank, float recheck_rel,
-                                 int32_t* out_idx, float* out_dist, hipStream_t s);
+                                 int32_t* out_idx, float* out_dist, hipStream_t s, int32_t* keep_out = nullptr);
 hipError_t launch_copy_counts(const int32_t* src, int64_t nq, int32_t* dst, hipStream_t s);
 hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hipStream_t s);
 hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, hipStream_t s);

@@ -57,7 +57,7 @@ _lib = None
 EXPORTED = [
     "mrpt_build", "mrpt_build_ex", "mrpt_default_build_opts", "mrpt_query", "mrpt_query_ex", "mrpt_default_opts", "mrpt_free", "mrpt_last_error",
     "mrpt_index_info", "mrpt_export_projection", "mrpt_export_tree", "mrpt_export_leaf_offsets",
-    "mrpt_debug_leaves", "mrpt_debug_votes", "mrpt_candidate_cap",
+    "mrpt_debug_leaves", "mrpt_debug_votes", "mrpt_debug_prefilter", "mrpt_debug_lowp_rows", "mrpt_candidate_cap",
     "mrpt_default_plan_opts", "mrpt_plan_create", "mrpt_plan_launch", "mrpt_plan_device_bytes", "mrpt_plan_free",
 ]
 
@@ -91,6 +91,8 @@ def load(path: str = LIB_PATH):
     lib.mrpt_export_leaf_offsets.argtypes = [vp, vp]
     lib.mrpt_debug_leaves.argtypes = [vp, vp, i64, vp, vp]
     lib.mrpt_debug_votes.argtypes = [vp, vp, i64, i32, vp, vp, vp, i64, vp]
+    lib.mrpt_debug_prefilter.argtypes = [vp, vp, i64, i32, i32, ctypes.POINTER(mrpt_query_opts), vp, vp, vp]
+    lib.mrpt_debug_lowp_rows.argtypes = [vp, i32, i64, i64, vp, vp, vp]
     lib.mrpt_candidate_cap.argtypes = [vp, i32]
     lib.mrpt_candidate_cap.restype = i64
     lib.mrpt_default_plan_opts.argtypes = [ctypes.POINTER(mrpt_plan_opts)]
@@ -131,6 +133,39 @@ def _dev(t, dtype_name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def check_query_tensors(d: int, Q, k: int, out_idx, out_dist, s_count=None):
+    """Shapes, dtypes and placement of a query call's tensors, checked before
+    anything reaches the library: Q is (nq, d) float32, out_idx (nq, k) int32,
+    out_dist (nq, k) float32, s_count (if given) int32 with at least nq
+    entries, all contiguous and on one device.  Raises ValueError/TypeError."""
+    import torch
+    ts = [("Q", Q), ("out_idx", out_idx), ("out_dist", out_dist)] + ([("s_count", s_count)] if s_count is not None
+                                                                      else [])
+    for name, t in ts:
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+    if Q.dim() != 2 or Q.shape[1] != d:
+        raise ValueError(f"Q has shape {tuple(Q.shape)}, expected (nq, {d})")
+    nq = Q.shape[0]
+    for name, t, dt in (("Q", Q, torch.float32), ("out_idx", out_idx, torch.int32),
+                        ("out_dist", out_dist, torch.float32)):
+        if t.dtype != dt:
+            raise TypeError(f"{name} is {t.dtype}, expected {dt}")
+    for name, t in (("out_idx", out_idx), ("out_dist", out_dist)):
+        if tuple(t.shape) != (nq, k):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected ({nq}, {k})")
+    if s_count is not None:
+        if s_count.dtype != torch.int32:
+            raise TypeError(f"s_count is {s_count.dtype}, expected torch.int32")
+        if s_count.numel() < nq:
+            raise ValueError(f"s_count holds {s_count.numel()} entries, fewer than nq = {nq}")
+    for name, t in ts:
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.device != Q.device:
+            raise ValueError(f"{name} is on {t.device}, Q on {Q.device}")
+
+
 def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -167,12 +202,16 @@ def mrpt_default_opts() -> mrpt_query_opts:
 
 
 def mrpt_query(ix, Q, k: int, v: int, out_idx, out_dist, stream=None):
+    check_query_tensors(mrpt_index_info(ix).d, Q, k, out_idx, out_dist)
     nq = Q.shape[0]
     _check(load().mrpt_query(ix, _dev(Q, "float32"), nq, k, v, _dev(out_idx, "int32"),
                              _dev(out_dist, "float32"), _stream(stream)))
 
 
-def mrpt_query_ex(ix, Q, k: int, v: int, out_idx, out_dist, opts: Optional[mrpt_query_opts] = None, stream=None):
+def mrpt_query_ex(ix, Q, k: int, v: int, out_idx, out_dist, opts: Optional[mrpt_query_opts] = None, stream=None,
+                  d: Optional[int] = None):
+    """d: the index's dimension when the caller knows it (else asked from the library)."""
+    check_query_tensors(mrpt_index_info(ix).d if d is None else d, Q, k, out_idx, out_dist)
     nq = Q.shape[0]
     _check(load().mrpt_query_ex(ix, _dev(Q, "float32"), nq, k, v, _dev(out_idx, "int32"),
                                 _dev(out_dist, "float32"), None if opts is None else ctypes.byref(opts),
@@ -227,6 +266,20 @@ def mrpt_debug_votes(ix, Q, v: int, s_count, s_ids, s_votes, cap: int, stream=No
                                    cap, _stream(stream)))
 
 
+def mrpt_debug_prefilter(ix, Q, k: int, v: int, opts: mrpt_query_opts, s_count, keep_ids, stream=None):
+    _check(load().mrpt_debug_prefilter(ix, _dev(Q, "float32"), Q.shape[0], k, v, ctypes.byref(opts),
+                                       _dev(s_count, "int32"), _dev(keep_ids, "int32"), _stream(stream)))
+
+
+def mrpt_debug_lowp_rows(ix, precision: int, row0: int, rows, scale_norm=None, stream=None):
+    """rows: CUDA tensor of nrows x d (int16 for MRPT_BF16_RERANK, uint8 for
+    MRPT_FP8_RERANK); scale_norm: optional float32 CUDA tensor of nrows x 2."""
+    want = "int16" if precision == MRPT_BF16_RERANK else "uint8"
+    _check(load().mrpt_debug_lowp_rows(ix, precision, row0, rows.shape[0], _dev(rows, want),
+                                       None if scale_norm is None else _dev(scale_norm, "float32"),
+                                       _stream(stream)))
+
+
 def mrpt_candidate_cap(ix, v: int) -> int:
     return int(load().mrpt_candidate_cap(ix, v))
 
@@ -242,6 +295,7 @@ def mrpt_plan_create(batches, opts: Optional[mrpt_plan_opts] = None) -> ctypes.c
     CUDA tensors; returns the plan handle.  The tensors must outlive the plan."""
     arr = (mrpt_batch * len(batches))()
     for i, (ix, Q, k, v, out_idx, out_dist) in enumerate(batches):
+        check_query_tensors(mrpt_index_info(ix).d, Q, k, out_idx, out_dist)
         arr[i] = mrpt_batch(ix, _dev(Q, "float32"), Q.shape[0], k, v, _dev(out_idx, "int32"),
                             _dev(out_dist, "float32"))
     h = ctypes.c_void_p()
@@ -314,16 +368,19 @@ class Index:
     def query(self, Q, k: int, v: int, precision: int = MRPT_FP32, rerank_factor: int = 4,
               recheck_rel: float = 1e-6, s_count=None, out=None, stream=None):
         import torch
+        if not isinstance(Q, torch.Tensor) or Q.dim() != 2:
+            raise ValueError("Q must be a 2-D torch tensor")
         nq = Q.shape[0]
         if out is None:
             out = (torch.empty((nq, k), dtype=torch.int32, device=Q.device),
                    torch.empty((nq, k), dtype=torch.float32, device=Q.device))
+        check_query_tensors(self.info.d, Q, k, out[0], out[1], s_count)
         o = mrpt_default_opts()
         o.precision = precision
         o.rerank_factor = rerank_factor
         o.recheck_rel = recheck_rel
-        o.s_count = None if s_count is None else s_count.data_ptr()
-        mrpt_query_ex(self.handle, Q, k, v, out[0], out[1], o, stream)
+        o.s_count = None if s_count is None else _dev(s_count, "int32").value
+        mrpt_query_ex(self.handle, Q, k, v, out[0], out[1], o, stream, d=self.info.d)
         return out
 
     def close(self):

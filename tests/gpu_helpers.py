@@ -11,6 +11,7 @@ Tolerances (float32 distance path against the float64 oracle):
 import numpy as np
 import torch
 
+import oracle
 from paper_1509_06957_amd import mrpt
 
 REL_DIST = 1e-5
@@ -95,3 +96,111 @@ def check_knn(X, Q, gi, gd, oi, od, exact_ids, queries=None, S=None):
 def recall(ids, true_ids):
     k = true_ids.shape[1]
     return float(np.mean([len(set(a.tolist()) & set(b.tolist())) / k for a, b in zip(ids, true_ids)]))
+
+
+# ---------------------------------------------------------------------------
+# precision arms: the float32 score bound, the kept lists and the answers
+# ---------------------------------------------------------------------------
+U32 = 2.0 ** -24
+ARM = {mrpt.MRPT_BF16_RERANK: oracle.ARM_BF16, mrpt.MRPT_FP8_RERANK: oracle.ARM_FP8}
+
+
+def gamma(m):
+    return m * U32 / (1 - m * U32)
+
+
+def gpu_rows(g, precision, n, d):
+    if precision == mrpt.MRPT_BF16_RERANK:
+        rows = torch.empty((n, d), dtype=torch.int16, device="cuda")
+        mrpt.mrpt_debug_lowp_rows(g.handle, precision, 0, rows)
+        torch.cuda.synchronize()
+        return rows.cpu().numpy().view(np.uint16), None
+    rows = torch.empty((n, d), dtype=torch.uint8, device="cuda")
+    sn = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    mrpt.mrpt_debug_lowp_rows(g.handle, precision, 0, rows, sn)
+    torch.cuda.synchronize()
+    return rows.cpu().numpy(), sn.cpu().numpy()
+
+
+def gpu_keep(g, Qd, k, v, precision, rerank_factor=4):
+    nq = Qd.shape[0]
+    kp = k * rerank_factor
+    o = mrpt.mrpt_default_opts()
+    o.precision, o.rerank_factor = precision, rerank_factor
+    sc = torch.zeros(nq, dtype=torch.int32, device="cuda")
+    keep = torch.full((nq, kp), -7, dtype=torch.int32, device="cuda")
+    mrpt.mrpt_debug_prefilter(g.handle, Qd, k, v, o, sc, keep)
+    torch.cuda.synchronize()
+    return sc.cpu().numpy(), keep.cpu().numpy()
+
+
+def decoded(X, ids, arm):
+    """The oracle's decoded low-precision rows of X[ids] (float64)."""
+    if arm == oracle.ARM_BF16:
+        return oracle.bf16_value(oracle.bf16_round(X[ids]))
+    codes, scale, _ = oracle.fp8_rows(X[ids])
+    return scale[:, None].astype(np.float64) * oracle.e4m3_value(codes)
+
+
+def check_kept(X, Q, ref, g_sc, g_keep, kp, arm, queries=None):
+    """GPU kept lists against the oracle's; returns how many queries had a
+    candidate inside the float32 band at the cut."""
+    qs = range(len(Q)) if queries is None else queries
+    banded = 0
+    for j, q in enumerate(qs):
+        ns = int(ref["s_count"][j])
+        assert g_sc[j] == ns, f"query {q}: |S| {g_sc[j]} vs {ns}"
+        m = min(ns, kp)
+        gk = g_keep[j]
+        assert np.all(gk[m:] == -1), f"query {q}: padding"
+        o_ids = ref["keep_ids"][j, :m]
+        if ns <= kp:                       # nothing ranked: the kept list is S
+            assert set(gk[:m].tolist()) == set(o_ids.tolist()), f"query {q}: S"
+            continue
+        g_ids = gk[:m]
+        assert len(set(g_ids.tolist())) == m, f"query {q}: duplicates"
+        if np.array_equal(g_ids, o_ids):
+            continue
+        # scores of every id on either list, from the oracle's quantizer
+        union = np.union1d(g_ids, o_ids)
+        xt = decoded(X, union, arm)
+        qd = Q[q].astype(np.float64)
+        sc = ((xt - qd[None, :]) ** 2).sum(1)
+        E = gamma(X.shape[1] + 4) * (np.linalg.norm(qd) + np.linalg.norm(xt, axis=1).max()) ** 2
+        score = dict(zip(union.tolist(), sc.tolist()))
+        t = ref["keep_score"][j, m - 1]
+        for x in set(g_ids.tolist()) - set(o_ids.tolist()):
+            assert score[x] <= t + 2 * E, f"query {q}: GPU kept {x} at {score[x]} beyond the cut {t} (+{2 * E})"
+        for x in set(o_ids.tolist()) - set(g_ids.tolist()):
+            assert score[x] >= t - 2 * E, f"query {q}: GPU dropped {x} at {score[x]} before the cut {t} (-{2 * E})"
+        s_g = np.array([score[x] for x in g_ids.tolist()])
+        assert np.all(np.diff(s_g) >= -2 * E), f"query {q}: kept list out of score order"
+        if set(g_ids.tolist()) != set(o_ids.tolist()):
+            banded += 1
+    return banded
+
+
+def check_answers(X, Q, ref, g_keep, gi, gd, kp, queries=None):
+    """The answers are the k nearest (float64, (distance, id)) of the kept
+    list: the oracle's wherever the GPU kept the oracle's list, else those of
+    the GPU's kept list (which check_kept has validated)."""
+    qs = range(len(Q)) if queries is None else queries
+    k = gi.shape[1]
+    for j, q in enumerate(qs):
+        m = int(min(ref["s_count"][j], kp))
+        kept = g_keep[j, :m]
+        if set(kept.tolist()) == set(ref["keep_ids"][j, :m].tolist()):
+            want = ref["idx"][j]
+        else:
+            d = dist64(X, Q[q], kept)
+            o = np.lexsort((kept, d))[:k]
+            want = np.full(k, -1, np.int32)
+            want[:len(o)] = kept[o]
+        nreal = int((want >= 0).sum())
+        assert np.all(gi[j, nreal:] == -1) and np.all(np.isinf(gd[j, nreal:])), f"query {q}: padding"
+        got = gi[j, :nreal]
+        assert set(got.tolist()) == set(want[:nreal].tolist()), f"query {q}: {got} vs {want[:nreal]}"
+        d = dist64(X, Q[q], got)
+        assert np.all(np.abs(gd[j, :nreal] - d) <= 1e-5 * d + 1e-6 * (d == 0)), f"query {q}: distances"
+        # ordered by float64 distance up to float32 near-ties (1e-6 relative)
+        assert np.all(np.diff(d) >= -1e-6 * d[1:]), f"query {q}: order"

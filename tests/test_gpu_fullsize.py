@@ -3,9 +3,12 @@ queries, T = 100, depth = 12, k = 10, v = 3) in the launch configuration the
 benchmark times: one query call over the whole batch.
 
 The oracle builds its own index from the same seed; the GPU index must equal
-it bit for bit (projection vectors, every tree), every leaf of every query
-must match, and for a sample of queries the candidate sets, vote counts and
-k nearest neighbours are recomputed by the oracle one query at a time.
+it bit for bit (projection vectors, every tree), and for all 10,000 queries
+the leaves, candidate sets, vote counts, k nearest neighbours and the
+bfloat16 arm's kept lists must equal the oracle's.  On a sample, the
+counter's candidate sets are compared at every threshold v = 1..T (which
+pins F from the counter itself) and the fp8 arm's kept lists within the
+float32 score bound.
 """
 import numpy as np
 import pytest
@@ -17,7 +20,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
 torch = pytest.importorskip("torch")
 
-from gpu_helpers import build, check_knn, dev, leaves, query, recall, votes  # noqa: E402
+from gpu_helpers import (build, check_answers, check_kept, check_knn, dev, gpu_keep, leaves, query,  # noqa: E402
+                         recall, votes)
 from paper_1509_06957_amd import mrpt  # noqa: E402
 
 SAMPLE = 300
@@ -58,33 +62,79 @@ def test_all_leaves_bit_exact(sift):
     assert np.array_equal(leaves(g, Qd), oracle.route(orc, Q))
 
 
-def test_batch_query_sampled(sift):
+def test_batch_query_full(sift):
     w, X, Q, Qd, orc, g, sample = sift
     gi, gd, sc = query(g, Qd, w.k, w.v)                 # the benchmark's call: whole batch
-    ref = oracle.query(orc, Q[sample], w.k, w.v, want_sets=True)
-    assert np.array_equal(sc[sample], ref["s_count"])
-    check_knn(X, Q, gi[sample], gd[sample], ref["idx"], ref["dist"], exact_ids=True, queries=sample,
+    ref = oracle.query(orc, Q, w.k, w.v, want_sets=True, nthreads=oracle.all_threads())
+    print("[step] oracle answered all queries", flush=True)
+    assert np.array_equal(sc, ref["s_count"])
+    check_knn(X, Q, gi, gd, ref["idx"], ref["dist"], exact_ids=True,
               S=[set(s.tolist()) for s in ref["s_ids"]])
-    # properties that hold for every query of the batch
     bound = w.T * int(np.max(np.diff(orc.off))) // w.v
     assert np.all(sc <= bound)
-    assert np.all((gi >= 0).sum(1) == np.minimum(sc, w.k))
-    fin = np.where(gi >= 0, gd, 0)
-    assert np.all(np.diff(fin, axis=1)[(gi[:, 1:] >= 0)] >= 0)
-    bi, _ = oracle.bruteforce(X, Q[sample], w.k)
+    bi, _ = oracle.bruteforce(X, Q[sample], w.k, nthreads=oracle.all_threads())
     r = recall(gi[sample], bi)
-    print(f"[recall] {w.name} fp32 recall@10 {r:.4f} |S| mean {sc.mean():.1f}", flush=True)
+    print(f"[recall] {w.name} fp32 recall@10 {r:.4f} (oracle brute force, {len(sample)} queries) "
+          f"|S| mean {sc.mean():.1f}", flush=True)
     assert r >= 0.9
 
 
-def test_sampled_votes(sift):
+def test_votes_full(sift):
     w, X, Q, Qd, orc, g, sample = sift
-    sub = sample[:64]
-    ref = oracle.query(orc, Q[sub], w.k, w.v, want_sets=True)
-    ids, cnt = votes(g, dev(Q[sub]), w.v)
+    ref = oracle.query(orc, Q, w.k, w.v, want_sets=True, nthreads=oracle.all_threads())
+    ids, cnt = votes(g, Qd, w.v)
+    for q in range(len(Q)):
+        assert np.array_equal(ids[q], ref["s_ids"][q]), f"query {q}"
+        assert np.array_equal(cnt[q], ref["s_votes"][q]), f"query {q}"
+
+
+def test_hot_counter_every_threshold_sampled(sift):
+    # S_v from the query path's counter for v = 1..T: F(x) = #{v : x in S_v}
+    w, X, Q, Qd, orc, g, sample = sift
+    sub = sample[:100]
+    Qs = Q[sub]
+    Qsd = dev(Qs)
+    ref1 = oracle.query(orc, Qs, 1, 1, want_sets=True)
+    F = [dict() for _ in range(len(sub))]
+    for v in range(1, w.T + 1):
+        ref = ref1 if v == 1 else oracle.query(orc, Qs, 1, v, want_sets=True)
+        ids, _ = votes(g, Qsd, v, with_counts=False)
+        for j in range(len(sub)):
+            assert np.array_equal(ids[j], ref["s_ids"][j]), f"v={v} query {sub[j]}"
+            for x in ids[j].tolist():
+                F[j][x] = F[j].get(x, 0) + 1
     for j in range(len(sub)):
-        assert np.array_equal(ids[j], ref["s_ids"][j])
-        assert np.array_equal(cnt[j], ref["s_votes"][j])
+        got = np.array([F[j][x] for x in ref1["s_ids"][j].tolist()], dtype=np.int32)
+        assert np.array_equal(got, ref1["s_votes"][j]), f"query {sub[j]}: F"
+
+
+def test_bf16_kept_lists_full_batch(sift):
+    # integers <= 255 are exact in bfloat16 and every score is an integer
+    # below 2^24: the kept lists equal the oracle's, order included
+    w, X, Q, Qd, orc, g, sample = sift
+    kp = 4 * w.k
+    ref = oracle.query_prefilter(orc, Q, w.k, w.v, oracle.ARM_BF16, kp, nthreads=oracle.all_threads())
+    g_sc, g_keep = gpu_keep(g, Qd, w.k, w.v, mrpt.MRPT_BF16_RERANK)
+    assert np.array_equal(g_sc, ref["s_count"])
+    ranked = ref["s_count"] > kp
+    assert ranked.mean() > 0.9
+    assert np.array_equal(g_keep[ranked], ref["keep_ids"][ranked])
+    for q in np.nonzero(~ranked)[0]:
+        assert set(g_keep[q].tolist()) == set(ref["keep_ids"][q].tolist())
+    bi, bd, _ = query(g, Qd, w.k, w.v, precision=mrpt.MRPT_BF16_RERANK)
+    assert np.array_equal(bi, ref["idx"])
+
+
+def test_fp8_kept_lists_sampled(sift):
+    w, X, Q, Qd, orc, g, sample = sift
+    kp = 4 * w.k
+    ref = oracle.query_prefilter(orc, Q[sample], w.k, w.v, oracle.ARM_FP8, kp, nthreads=oracle.all_threads())
+    g_sc, g_keep = gpu_keep(g, Qd, w.k, w.v, mrpt.MRPT_FP8_RERANK)
+    gi, gd, _ = query(g, Qd, w.k, w.v, precision=mrpt.MRPT_FP8_RERANK)
+    banded = check_kept(X, Q, ref, g_sc[sample], g_keep[sample], kp, oracle.ARM_FP8, queries=sample)
+    check_answers(X, Q, ref, g_keep[sample], gi[sample], gd[sample], kp, queries=sample)
+    print(f"[fp8] sift-like: {banded} of {len(sample)} sampled queries with a candidate in the float32 band",
+          flush=True)
 
 
 def test_bf16_arm_equals_fp32_on_8bit_data(sift):

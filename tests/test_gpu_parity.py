@@ -65,7 +65,10 @@ def test_leaves_bit_exact(case):
     assert np.array_equal(leaves(case.gpu, case.Qd), oracle.route(case.orc, case.Q))
 
 
-def test_votes_bit_exact(case):
+def test_vote_recount_bit_exact(case):
+    # s_votes come from vote_counts_kernel, a debug recount (binary search of
+    # every listed id in the query's leaves); the candidate sets come from the
+    # query path's counter.  The counter's own F is pinned by the next test.
     w = case.w
     for v in sorted({1, w.v, w.T}):
         ref = oracle.query(case.orc, case.Q, w.k, v, want_sets=True)
@@ -73,6 +76,45 @@ def test_votes_bit_exact(case):
         for q in range(len(case.Q)):
             assert np.array_equal(ids[q], ref["s_ids"][q]), f"v={v} query {q} S"
             assert np.array_equal(cnt[q], ref["s_votes"][q]), f"v={v} query {q} F"
+
+
+def _check_every_threshold(g, orc, Q, Qd, T, label):
+    """S_v from the query path's counter for every v = 1..T equals the
+    oracle's; F(x) = #{v : x in S_v} is then the counter's own vote count and
+    must equal the oracle's F (Sec. III-A)."""
+    ref1 = oracle.query(orc, Q, 1, 1, want_sets=True)
+    F = [dict() for _ in range(len(Q))]
+    for v in range(1, T + 1):
+        ref = ref1 if v == 1 else oracle.query(orc, Q, 1, v, want_sets=True)
+        ids, _ = votes(g, Qd, v, with_counts=False)
+        for q in range(len(Q)):
+            assert np.array_equal(ids[q], ref["s_ids"][q]), f"{label} v={v} query {q}"
+            for x in ids[q].tolist():
+                F[q][x] = F[q].get(x, 0) + 1
+    for q in range(len(Q)):
+        got = np.array([F[q][x] for x in ref1["s_ids"][q].tolist()], dtype=np.int32)
+        assert len(F[q]) == len(ref1["s_ids"][q])
+        assert np.array_equal(got, ref1["s_votes"][q]), f"{label} query {q}: F"
+
+
+def test_hot_counter_every_threshold(case):
+    w = case.w
+    _check_every_threshold(case.gpu, case.orc, case.Q, case.Qd, w.T, w.name)
+
+
+@pytest.mark.parametrize("kernel", ["0", "1"])
+def test_hot_counter_every_threshold_multipass(kernel, monkeypatch):
+    # the multi-pass kernels: with the leaf directory (MRPT_VOTE_KERNEL=0 at
+    # build and query time) and without it (1); n above one directory grain
+    _print_case(f"every threshold, multi-pass vote kernel {kernel}")
+    monkeypatch.setenv("MRPT_VOTE_KERNEL", kernel)
+    X, Q = _small(150000, 8, 12, 7, seed=77, nq=300)
+    orc = oracle.build_index(X, 12, 7, 0.5, 3)
+    g = build(X, 12, 7, 0.5, 3)
+    try:
+        _check_every_threshold(g, orc, Q, dev(Q), 12, f"kernel {kernel}")
+    finally:
+        g.close()
 
 
 def test_knn_fp32(case):
@@ -290,6 +332,60 @@ def test_error_paths():
     g.close()
 
 
+@pytest.mark.parametrize("precision", [mrpt.MRPT_FP32, mrpt.MRPT_BF16_RERANK])
+def test_nonfinite_query_row_unchecked(precision):
+    # with the finiteness check off (the default) a NaN or Inf row gives
+    # in-range results (ids in [-1, n), padding where no distance compares),
+    # and every other row its usual answer
+    _print_case(f"non-finite query rows, check off, precision {precision}")
+    X, Q = _small(3000, 32, 6, 5, seed=12, nq=40)
+    g = build(X, 6, 5, 0.4, 3)
+    try:
+        Qd = dev(Q)
+        ref_i, ref_d, ref_s = query(g, Qd, 10, 2, precision=precision)
+        Qn = Q.copy()
+        Qn[3, 5] = np.nan
+        Qn[17, :] = np.inf
+        Qn[29, 0] = -np.inf
+        gi, gd, sc = query(g, dev(Qn), 10, 2, precision=precision)
+        assert np.all((gi >= -1) & (gi < len(X)))
+        for r in (3, 17, 29):
+            real = gi[r] >= 0
+            assert np.all(np.isnan(gd[r][real]) | (gd[r][real] >= 0))
+            assert np.all(np.isinf(gd[r][~real]))
+        keep = np.setdiff1d(np.arange(len(Q)), [3, 17, 29])
+        assert np.array_equal(gi[keep], ref_i[keep]) and np.array_equal(gd[keep], ref_d[keep])
+        assert np.array_equal(sc[keep], ref_s[keep])
+    finally:
+        g.close()
+
+
+def test_query_pointer_checks():
+    # host memory or a wrong shape is refused before any launch
+    _print_case("query pointer checks")
+    X, Q = _small(1000, 8, 2, 3, seed=13)
+    g = build(X, 2, 3, 0.5, 1)
+    try:
+        import ctypes
+        lib = mrpt.load()
+        Qh = np.ascontiguousarray(Q)
+        idx = torch.empty((len(Q), 5), dtype=torch.int32, device="cuda")
+        dist = torch.empty((len(Q), 5), dtype=torch.float32, device="cuda")
+        st = lib.mrpt_query(g.handle, ctypes.c_void_p(Qh.ctypes.data), len(Q), 5, 1,
+                            ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(dist.data_ptr()), None)
+        assert st == mrpt.MRPT_EINVAL and "Q" in mrpt.mrpt_last_error()
+        oh = np.zeros((len(Q), 5), np.int32)
+        st = lib.mrpt_query(g.handle, ctypes.c_void_p(dev(Q).data_ptr()), len(Q), 5, 1,
+                            ctypes.c_void_p(oh.ctypes.data), ctypes.c_void_p(dist.data_ptr()), None)
+        assert st == mrpt.MRPT_EINVAL and "out_idx" in mrpt.mrpt_last_error()
+        with pytest.raises(ValueError):
+            g.query(dev(Q[:, :7]), 5, 1)
+        with pytest.raises(ValueError):
+            mrpt.mrpt_query(g.handle, dev(Q), 5, 1, idx[:, :4].contiguous(), dist)
+    finally:
+        g.close()
+
+
 def ctypes_build_host_pointer(X):
     import ctypes
     lib = mrpt.load()
@@ -353,8 +449,8 @@ def test_device_build_matches_host_and_oracle(n, d, T, depth, integer, monkeypat
 @pytest.mark.parametrize("k,precision", [(10, None), (100, None), (10, "bf16")])
 def test_gist_like_shape_full_parity(k, precision):
     # the gist-like data (d = 960, values in (0, 1)) at a size the oracle
-    # handles in seconds: 16 trees of depth 5, v = 5, k = 10 and 100; the
-    # windows exceed the single-pass vote kernel's registers (multi-pass), the
+    # handles in seconds: 16 trees of depth 5, v = 5, k = 10 and 100 (the
+    # single-pass vote kernel serves it: 15 windows of 64 ids per leaf); the
     # search runs 64 lanes x 4 float4 per row, the bf16 arm 64 lanes x 2 x 8
     w = W.GIST_LIKE.scaled(n=30000, nq=48, T=16, depth=5)
     _print_case(f"gist-like shape n={w.n} T={w.T} depth={w.depth} k={k} {precision or 'fp32'}")
