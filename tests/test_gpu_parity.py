@@ -310,9 +310,13 @@ def test_error_paths():
     g = build(X, 2, 3, 0.5, 1)
     idx = torch.empty((len(Q), 5), dtype=torch.int32, device="cuda")
     dist = torch.empty((len(Q), 5), dtype=torch.float32, device="cuda")
+    # outputs sized (nq, k) so the binding's shape check passes and the
+    # library's own argument check is what rejects k and v
     for k, v in ((0, 1), (5, 0), (5, 3), (1025, 1)):
+        ik = torch.empty((len(Q), k), dtype=torch.int32, device="cuda")
+        dk = torch.empty((len(Q), k), dtype=torch.float32, device="cuda")
         with pytest.raises(mrpt.MrptError) as e:
-            mrpt.mrpt_query(g.handle, Qd, k, v, idx, dist)
+            mrpt.mrpt_query(g.handle, Qd, k, v, ik, dk)
         assert e.value.status == mrpt.MRPT_EINVAL
     Qn = Q.copy()
     Qn[2, 1] = np.inf

@@ -98,12 +98,15 @@ def _arm_case(X, Q, T, depth, a, seed, k, v, precision, rerank_factor=4):
 @pytest.mark.parametrize("precision", [mrpt.MRPT_BF16_RERANK, mrpt.MRPT_FP8_RERANK])
 @pytest.mark.parametrize("k", [10, 100])
 def test_arm_gist_like_shape(precision, k):
-    # gist-like rows (d = 960, values in (0, 1)), |S| in the thousands: the
-    # prefilter ranks every query; bfloat16 and E4M3 are lossy here
+    # gist-like rows (d = 960, values in (0, 1)); bfloat16 and E4M3 are lossy
+    # here.  At v = 5 |S| is about 200 (above kp = 40 for k = 10); k = 100
+    # (kp = 400) takes v = 3, where |S| is about 660, so that the prefilter
+    # ranks every query at both k
     w = W.GIST_LIKE.scaled(n=30000, nq=48, T=16, depth=5)
-    _case(f"arm {precision} gist-like shape k={k}")
+    v = w.v if k == 10 else 3
+    _case(f"arm {precision} gist-like shape k={k} v={v}")
     X, Q = W.data(w), W.queries(w)
-    _arm_case(X, Q, w.T, w.depth, w.a, w.index_seed, k, w.v, precision)
+    _arm_case(X, Q, w.T, w.depth, w.a, w.index_seed, k, v, precision)
 
 
 @pytest.mark.parametrize("precision", [mrpt.MRPT_BF16_RERANK, mrpt.MRPT_FP8_RERANK])
