@@ -143,6 +143,29 @@ mrpt_status mrpt_query_ex(const mrpt_index* ix, const float* Q, int64_t nq, int3
                           int32_t* out_idx, float* out_dist, const mrpt_query_opts* opts,
                           void* stream);
 
+/* Bytes of the device array that holds mrpt_query_noalloc's temporaries (one
+ * array per GPU, held from the library's load until the process ends). */
+#define MRPT_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* mrpt_query_ex for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as mrpt_query_ex, but no call allocates
+ * (no hipMalloc, hipFree or allocating library routine): the query
+ * temporaries (per query about 4*(T + T*ceil(n/2^depth)/v + 1) bytes plus
+ * 4*T*depth for the projections) live in a fixed device array of
+ * MRPT_NOALLOC_SCRATCH_BYTES, and a batch whose temporaries do not fit runs
+ * as several sub-batches in stream order.
+ *   Errors: as mrpt_query_ex, and MRPT_EINVAL when a single query's
+ *   temporaries exceed MRPT_NOALLOC_SCRATCH_BYTES.
+ * Every call on one GPU shares that GPU's array: calls whose work overlaps on
+ * the GPU (several host threads, or several streams without an order between
+ * them) race and give undefined results; calls in one stream are ordered.
+ * The array keeps the last call's contents; nothing in it is assumed zero.
+ * opts->check_finite = 1 synchronises the stream (not capturable). */
+mrpt_status mrpt_query_noalloc(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v,
+                               int32_t* out_idx, float* out_dist, const mrpt_query_opts* opts,
+                               void* stream);
+
 /* Default options (MRPT_FP32, rerank_factor 4, recheck_rel 1e-6, no check, no
  * |S| export, no stage events). */
 void mrpt_default_opts(mrpt_query_opts* opts);

@@ -265,6 +265,22 @@ mrpt_status query_impl(const mrpt_index* cix, const float* Q, int64_t nq, int32_
     return MRPT_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free queries
+// The temporaries of mrpt_query_noalloc (leaf ids, candidate lists and
+// counts, projections, the finiteness flag) live in the file-scope array
+// `scratch` below, one copy per GPU.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in): it takes the device
+// address once per device from hipGetSymbolAddress.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+__global__ void zero_flag_kernel(int32_t* flag) {
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+mrpt_status noalloc_impl(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v, int32_t* out_idx,
+                         float* out_dist, const mrpt_query_opts* opts, void* stream);
+
 }  // namespace
 
 mrpt_status fail(mrpt_status st, const char* fmt, ...) {
@@ -279,6 +295,79 @@ mrpt_status fail(mrpt_status st, const char* fmt, ...) {
 
 void clear_error() { g_error.clear(); }
 
+}  // namespace mrpt
+
+static __device__ __align__(256) unsigned char scratch[MRPT_NOALLOC_SCRATCH_BYTES];
+
+namespace mrpt {
+namespace {
+
+// the device address of `scratch` on the current device (taken on the first
+// call per device and kept)
+mrpt_status scratch_address(int device, char** out) {
+    if (device < 0 || device >= (int)(sizeof(g_scratch_ptr) / sizeof(g_scratch_ptr[0])))
+        return fail(MRPT_EDEVICE, "device %d beyond the scratch table", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(MRPT_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *out = (char*)g_scratch_ptr[device];
+    return MRPT_OK;
+}
+
+mrpt_status noalloc_impl(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v, int32_t* out_idx,
+                         float* out_dist, const mrpt_query_opts* opts, void* stream) {
+    clear_error();
+    MRPT_TRY(check_query_args(ix, Q, nq, k, v, out_idx, out_dist));
+    mrpt_query_opts o;
+    mrpt_default_opts(&o);
+    if (opts) o = *opts;
+    MRPT_TRY(check_arm(ix, k, o));
+    if (nq == 0) return MRPT_OK;
+    if (o.s_count && pointer_device(o.s_count) != ix->device)
+        return fail(MRPT_EINVAL, "s_count must be device memory of the index's device %d", ix->device);
+    const size_t limit = MRPT_NOALLOC_SCRATCH_BYTES;
+    const int64_t cap = candidate_cap(ix, v);
+    const size_t one = workspace_layout(ix, 1, cap, nullptr, nullptr);
+    if (one > limit)
+        return fail(MRPT_EINVAL, "one query's temporaries take %zu bytes, beyond the %zu-byte scratch of "
+                    "mrpt_query_noalloc (T * ceil(n / 2^depth) / v candidates)", one, limit);
+    // the most queries whose temporaries fit the scratch
+    int64_t nb = std::min<int64_t>(nq, (int64_t)(limit / one));
+    while (nb < nq && workspace_layout(ix, nb + 1, cap, nullptr, nullptr) <= limit) ++nb;
+    while (nb > 1 && workspace_layout(ix, nb, cap, nullptr, nullptr) > limit) --nb;
+    hipStream_t s = (hipStream_t)stream;
+    MRPT_HIP_TRY(hipSetDevice(ix->device));
+    char* base = nullptr;
+    MRPT_TRY(scratch_address(ix->device, &base));
+    Workspace ws;
+    (void)workspace_layout(ix, nb, cap, base, &ws);
+    if (o.check_finite) {
+        // the flag is cleared by a kernel (no memset node where a caller captures)
+        hipLaunchKernelGGL(zero_flag_kernel, dim3(1), dim3(64), 0, s, ws.flag);
+        MRPT_HIP_TRY(hipGetLastError());
+        MRPT_HIP_TRY(launch_check_finite(Q, nq * (int64_t)ix->d, ws.flag, s));
+        int32_t h = 0;
+        MRPT_HIP_TRY(hipMemcpyAsync(&h, ws.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MRPT_HIP_TRY(hipStreamSynchronize(s));
+        if (h) return fail(MRPT_ENONFINITE, "query matrix holds NaN or Inf");
+    }
+    for (int64_t q0 = 0; q0 < nq; q0 += nb) {
+        const int64_t m = std::min(nb, nq - q0);
+        MRPT_HIP_TRY(enqueue_batch(ix, ws, Q + q0 * ix->d, m, k, v, cap, o, out_idx + q0 * k, out_dist + q0 * k, s,
+                                   q0 == 0));
+        if (o.s_count) MRPT_HIP_TRY(launch_copy_counts(ws.s_count, m, o.s_count + q0, s));
+    }
+    return MRPT_OK;
+}
+
+}  // namespace
 }  // namespace mrpt
 
 // A recorded query plan: one workspace per batch in one allocation, and the
@@ -462,6 +551,11 @@ mrpt_status mrpt_query(const mrpt_index* ix, const float* Q, int64_t nq, int32_t
 mrpt_status mrpt_query_ex(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v, int32_t* out_idx,
                           float* out_dist, const mrpt_query_opts* opts, void* stream) {
     return query_impl(ix, Q, nq, k, v, out_idx, out_dist, opts, stream);
+}
+
+mrpt_status mrpt_query_noalloc(const mrpt_index* ix, const float* Q, int64_t nq, int32_t k, int32_t v,
+                               int32_t* out_idx, float* out_dist, const mrpt_query_opts* opts, void* stream) {
+    return noalloc_impl(ix, Q, nq, k, v, out_idx, out_dist, opts, stream);
 }
 
 void mrpt_free(mrpt_index* ix) {

@@ -55,7 +55,7 @@ class mrpt_plan_opts(ctypes.Structure):
 _lib = None
 
 EXPORTED = [
-    "mrpt_build", "mrpt_build_ex", "mrpt_default_build_opts", "mrpt_query", "mrpt_query_ex", "mrpt_default_opts", "mrpt_free", "mrpt_last_error",
+    "mrpt_build", "mrpt_build_ex", "mrpt_default_build_opts", "mrpt_query", "mrpt_query_ex", "mrpt_query_noalloc", "mrpt_default_opts", "mrpt_free", "mrpt_last_error",
     "mrpt_index_info", "mrpt_export_projection", "mrpt_export_tree", "mrpt_export_leaf_offsets",
     "mrpt_debug_leaves", "mrpt_debug_votes", "mrpt_debug_prefilter", "mrpt_debug_lowp_rows", "mrpt_candidate_cap",
     "mrpt_default_plan_opts", "mrpt_plan_create", "mrpt_plan_launch", "mrpt_plan_device_bytes", "mrpt_plan_free",
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
     lib.mrpt_default_build_opts.restype = None
     lib.mrpt_query.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp]
     lib.mrpt_query_ex.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.POINTER(mrpt_query_opts), vp]
+    lib.mrpt_query_noalloc.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.POINTER(mrpt_query_opts), vp]
     lib.mrpt_default_opts.argtypes = [ctypes.POINTER(mrpt_query_opts)]
     lib.mrpt_default_opts.restype = None
     lib.mrpt_free.argtypes = [vp]
@@ -216,6 +217,17 @@ def mrpt_query_ex(ix, Q, k: int, v: int, out_idx, out_dist, opts: Optional[mrpt_
     _check(load().mrpt_query_ex(ix, _dev(Q, "float32"), nq, k, v, _dev(out_idx, "int32"),
                                 _dev(out_dist, "float32"), None if opts is None else ctypes.byref(opts),
                                 _stream(stream)))
+
+
+def mrpt_query_noalloc(ix, Q, k: int, v: int, out_idx, out_dist, opts: Optional[mrpt_query_opts] = None,
+                       stream=None, d: Optional[int] = None):
+    """mrpt_query_ex without device allocation (temporaries in the library's
+    fixed per-GPU scratch array)."""
+    check_query_tensors(mrpt_index_info(ix).d if d is None else d, Q, k, out_idx, out_dist)
+    nq = Q.shape[0]
+    _check(load().mrpt_query_noalloc(ix, _dev(Q, "float32"), nq, k, v, _dev(out_idx, "int32"),
+                                     _dev(out_dist, "float32"), None if opts is None else ctypes.byref(opts),
+                                     _stream(stream)))
 
 
 def mrpt_free(ix):
