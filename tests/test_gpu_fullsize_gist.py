@@ -87,7 +87,7 @@ def test_batch_query_matches_golden(gist, k):
     gi, gd, sc = query(g, Qd, k, w.v)                    # whole batch, one call
     assert np.array_equal(sc, knn["s_count"])
     m = len(Q) if k == 10 else knn["idx100"].shape[0]
-    check_knn(X, Q, gi[:m], gd[:m], knn[f"idx{k}"], knn[f"dist{k}"], exact_ids=False)
+    check_knn(X, Q[:m], gi[:m], gd[:m], knn[f"idx{k}"], knn[f"dist{k}"], exact_ids=False)
     if k == 10:
         bi, _ = oracle.bruteforce(X, Q[sample], k, nthreads=oracle.all_threads())
         r = recall(gi[sample], bi)
