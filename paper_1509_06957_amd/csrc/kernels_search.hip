@@ -197,12 +197,127 @@ __global__ __launch_bounds__(256) void dist_fp32_generic_kernel(const float* __r
 // ||q||^2 - 2 q.x~ + ||x~||^2 with x~ the low-precision row (bfloat16: 8
 // values per 16-byte load; fp8 e4m3: 16 values per load and a per-row scale,
 // x~ = scale * decode(code)), float32 accumulation, and keeps the best
-// kp = r*k; phase 2 recomputes those kp with float32 direct differences from
-// the float32 rows and orders them by (distance, id); phase 3 recomputes in
-// float64 every candidate whose float32 distance is within recheck_rel of the
-// k-th and orders that window by (float64 distance, id).  One workgroup (4
-// waves) per query.
+// kp = r*k under (score, id): the scores of up to kPfChunk candidates at a
+// time go to LDS, and a block-wide radix select over them and the list kept
+// so far takes the kp smallest; phase 2 recomputes those kp with float32
+// direct differences from the float32 rows and orders them by (distance,
+// id); phase 3 recomputes in float64 every candidate whose float32 distance
+// is within recheck_rel of the k-th and orders that window by (float64
+// distance, id).  One workgroup (4 waves) per query.
 // ---------------------------------------------------------------------------
+constexpr int kPfChunk = 1024;                  // candidates scored per selection round
+constexpr int kPfBuf = kPfChunk + kMaxRerank;   // one round's scores, then the list kept so far
+
+// monotone map of a float32 score to an unsigned key: -0 as +0, NaN after
+// every number (a NaN score comes from a non-finite query and ranks last)
+__device__ __forceinline__ uint32_t score_key(float s) {
+    uint32_t u = __builtin_bit_cast(uint32_t, s);
+    if ((u << 1) == 0u) u = 0u;
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0u) return 0xFFFFFFFFu;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// wave 0 of a select pass: the bucket of hist[0..255] that holds the rem-th
+// smallest of the counted pairs; sel = {bucket, rank within it, its count}
+__device__ __forceinline__ void pick_bucket(const uint32_t* hist, int rem, int* sel) {
+    const int lane = lane_id();
+    const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+    const int own = (int)(h0 + h1 + h2 + h3);
+    int incl = own;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    const int excl = incl - own;
+    if (excl < rem && rem <= incl) {
+        const uint32_t h[4] = {h0, h1, h2, h3};
+        int c = excl;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (c < rem && rem <= c + (int)h[j]) {
+                sel[0] = 4 * lane + j;
+                sel[1] = rem - c;
+                sel[2] = (int)h[j];
+            }
+            c += (int)h[j];
+        }
+    }
+}
+
+// The need smallest of the tot pairs (key[e], id[e]) under (key, id), ids
+// distinct, need < tot, written to (okey, oid)[0, need) in no particular
+// order.  A radix select over the key's bytes from the top finds the key T of
+// the need-th pair and how many pairs at T are taken; when that is not all
+// of them, a second radix select over the ids of the pairs at T finds the
+// largest id taken.  All 256 threads of the workgroup take part.
+__device__ void block_select(const uint32_t* key, const int32_t* id, int tot, int need, uint32_t* okey,
+                             int32_t* oid, uint32_t* hist, int* sel) {
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid >> 6;
+    uint32_t prefix = 0u, pmask = 0u;
+    int rem = need, eq = tot;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hist[tid] = 0u;
+        __syncthreads();
+        for (int e = tid; e < tot; e += 256) {
+            const uint32_t kk = key[e];
+            if ((kk & pmask) == prefix) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (w == 0) pick_bucket(hist, rem, sel);
+        __syncthreads();
+        prefix |= (uint32_t)sel[0] << shift;
+        pmask |= 0xFFu << shift;
+        rem = sel[1];
+        eq = sel[2];
+    }
+    const uint32_t T = prefix;
+    uint32_t idT = 0xFFFFFFFFu;                  // pairs at T with id <= idT are taken
+    if (rem < eq) {
+        uint32_t ip = 0u, im = 0u;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            hist[tid] = 0u;
+            __syncthreads();
+            for (int e = tid; e < tot; e += 256) {
+                const uint32_t ii = (uint32_t)id[e];
+                if (key[e] == T && (ii & im) == ip) atomicAdd(&hist[(ii >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (w == 0) pick_bucket(hist, rem, sel);
+            __syncthreads();
+            ip |= (uint32_t)sel[0] << shift;
+            im |= 0xFFu << shift;
+            rem = sel[1];
+        }
+        idT = ip;
+    }
+    if (tid == 0) sel[3] = 0;
+    __syncthreads();
+    for (int e0 = 0; e0 < tot; e0 += 256) {      // uniform trip count
+        const int e = e0 + tid;
+        bool take = false;
+        uint32_t kk = 0u;
+        int32_t ii = 0;
+        if (e < tot) {
+            kk = key[e];
+            ii = id[e];
+            take = kk < T || (kk == T && (uint32_t)ii <= idT);
+        }
+        const uint64_t m = __ballot(take);
+        int base = 0;
+        if (lane == 0 && m) base = atomicAdd(&sel[3], __popcll(m));
+        base = __shfl(base, 0);
+        if (take) {
+            const int p = base + __popcll(m & __lanemask_lt());
+            okey[p] = kk;
+            oid[p] = ii;
+        }
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
 
@@ -212,7 +327,7 @@ constexpr int kFmtFp8 = 1;
 // KEEP: stop after phase 1 and write the kept list (ids in prefilter rank
 // order, -1 past min(|S|, kp); S in slot order when |S| <= kp) to
 // keep_out[q * kp ...] instead of the k-NN (the parity hook of the arm)
-template <int FMT, int GB, int NVB, int RB, int G2, int NV2, bool KEEP = false>
+template <int FMT, int GB, int NVB, int G2, int NV2, bool KEEP = false>
 __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X, const uint8_t* __restrict__ Xq,
                                                     const float2* __restrict__ sn8, int32_t d,
                                                     const float* __restrict__ Q,
@@ -228,13 +343,21 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
     // phase 2 reads float32 rows as the fp32 kernel does: G2 lanes x NV2 float4
     constexpr int GPW2 = kWave / G2;
     constexpr int U2 = 8 / NV2;
-    __shared__ float md[kDistWaves][kWave * RB];
-    __shared__ int32_t mi[kDistWaves][kWave * RB];
-    __shared__ int32_t cand[kMaxRerank];      // phase-1 survivors in prefilter rank order
-    __shared__ float d32[kMaxRerank];         // their float32 squared distances
-    __shared__ double d64[kMaxRerank];        // float64 squared distances (window only)
-    __shared__ int32_t order[kMaxRerank];     // rank by (d32, id) -> candidate slot
-    __shared__ int32_t final_slot[kMaxK];
+    static_assert(kPfChunk % (kDistWaves * (kWave / GB) * (8 / NVB)) == 0, "a round covers whole steps");
+    // phase 1 (round scores and the kept list) and phases 2-3 (distances,
+    // order, final slots) use the same LDS
+    __shared__ __align__(16) unsigned char pf_smem[kPfBuf * 8];
+    uint32_t* pkey = reinterpret_cast<uint32_t*>(pf_smem);             // kPfBuf keys
+    int32_t* pid = reinterpret_cast<int32_t*>(pf_smem + kPfBuf * 4);   // kPfBuf ids
+    double* d64 = reinterpret_cast<double*>(pf_smem);                  // float64 squared distances (window only)
+    float* d32 = reinterpret_cast<float*>(pf_smem + kMaxRerank * 8);   // float32 squared distances of the kept
+    int32_t* order = reinterpret_cast<int32_t*>(pf_smem + kMaxRerank * 12);       // rank by (d32, id) -> slot
+    int32_t* final_slot = reinterpret_cast<int32_t*>(pf_smem + kMaxRerank * 16);  // k <= kp <= kMaxRerank
+    static_assert(kMaxRerank * 20 <= kPfBuf * 8, "phases 2-3 fit the phase-1 buffer");
+    __shared__ int32_t cand[kMaxRerank];      // the kept list (prefilter survivors)
+    __shared__ uint32_t ckey[kMaxRerank];     // their score keys
+    __shared__ uint32_t hist[256];
+    __shared__ int sel[4];
     __shared__ int win_lo, win_hi;
     __shared__ __align__(16) float qs[1024 + 64];   // query (float32) for phases 2-3, d <= 1024
 
@@ -264,12 +387,6 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
     const float qn = read_lane_f(group_sum<GB>(qn_part), 0);
 
     if (ns > kp) {
-        WaveTopK<RB> top;
-        top.init(kPadId + w * kWave * RB);
-        float tau_d;
-        int32_t tau_i;
-        top.get(kp - 1, tau_d, tau_i);
-
         // as in dist_fp32: the next step's candidate ids are loaded while this
         // step's rows arrive, and every load is unconditional (clamped, masked)
         constexpr int kStep = kDistWaves * GPW * U;
@@ -280,92 +397,106 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
             const int ci = slot(0, u);
             craw[u] = S[ci < ns ? ci : 0];
         }
-        for (int b0 = 0; b0 < ns; b0 += kStep) {
-            int32_t cid[U];
+        int nk = 0;                            // entries of the kept list (cand, ckey)
+        for (int c0 = 0; c0 < ns; c0 += kPfChunk) {
+            const int cend = ns - c0 < kPfChunk ? ns : c0 + kPfChunk;
+            for (int b0 = c0; b0 < cend; b0 += kStep) {
+                int32_t cid[U];
     #pragma unroll
-            for (int u = 0; u < U; ++u) cid[u] = slot(b0, u) < ns ? craw[u] : -1;
-            uint4 xv[U][NVB];
-            float xs[U], xn[U];
+                for (int u = 0; u < U; ++u) cid[u] = slot(b0, u) < cend ? craw[u] : -1;
+                uint4 xv[U][NVB];
+                float xs[U], xn[U];
     #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t row = cid[u] < 0 ? 0 : cid[u];
-                const uint4* xr = reinterpret_cast<const uint4*>(Xq + row * d * ROWB);
+                for (int u = 0; u < U; ++u) {
+                    const int64_t row = cid[u] < 0 ? 0 : cid[u];
+                    const uint4* xr = reinterpret_cast<const uint4*>(Xq + row * d * ROWB);
     #pragma unroll
-                for (int i = 0; i < NVB; ++i) {
-                    const int vi = gl + i * GB;
-                    xv[u][i] = xr[vi < nv8 ? vi : 0];
+                    for (int i = 0; i < NVB; ++i) {
+                        const int vi = gl + i * GB;
+                        xv[u][i] = xr[vi < nv8 ? vi : 0];
+                    }
+                    const float2 sn = FMT == kFmtFp8 ? sn8[row] : make_float2(1.0f, 0.0f);
+                    xs[u] = sn.x;
+                    xn[u] = sn.y;
                 }
-                const float2 sn = FMT == kFmtFp8 ? sn8[row] : make_float2(1.0f, 0.0f);
-                xs[u] = sn.x;
-                xn[u] = sn.y;
-            }
     #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int ci = slot(b0 + kStep, u);
-                craw[u] = S[ci < ns ? ci : 0];
-            }
-            // the dot product q.x~; the bfloat16 row's squared norm is accumulated
-            // beside it from the row in registers (no norm load), the fp8 row's
-            // (scale^2 * sum decode^2, stored at build) comes with the scale in
-            // one 8-byte load
-            float s[U];
+                for (int u = 0; u < U; ++u) {
+                    const int ci = slot(b0 + kStep, u);
+                    craw[u] = S[ci < ns ? ci : 0];
+                }
+                // the dot product q.x~; the bfloat16 row's squared norm is
+                // accumulated beside it from the row in registers (no norm
+                // load), the fp8 row's (scale^2 * sum decode^2, stored at
+                // build) comes with the scale in one 8-byte load
     #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                float a = 0.0f, r2 = 0.0f;
+                for (int u = 0; u < U; ++u) {
+                    float a = 0.0f, r2 = 0.0f;
     #pragma unroll
-                for (int i = 0; i < NVB; ++i) {
-                    const bool in = gl + i * GB < nv8;
-                    const uint32_t wv[4] = {in ? xv[u][i].x : 0u, in ? xv[u][i].y : 0u, in ? xv[u][i].z : 0u,
-                                            in ? xv[u][i].w : 0u};
+                    for (int i = 0; i < NVB; ++i) {
+                        const bool in = gl + i * GB < nv8;
+                        const uint32_t wv[4] = {in ? xv[u][i].x : 0u, in ? xv[u][i].y : 0u, in ? xv[u][i].z : 0u,
+                                                in ? xv[u][i].w : 0u};
     #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        if constexpr (FMT == kFmtBf16) {
-                            const float x0 = bf16_lo(wv[j]), x1 = bf16_hi(wv[j]);
-                            a = __builtin_fmaf(qf[i][2 * j], x0, a);
-                            a = __builtin_fmaf(qf[i][2 * j + 1], x1, a);
-                            r2 = __builtin_fmaf(x0, x0, r2);
-                            r2 = __builtin_fmaf(x1, x1, r2);
-                        } else {
-                            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], false);
-                            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], true);
-                            a = __builtin_fmaf(qf[i][4 * j], lo[0], a);
-                            a = __builtin_fmaf(qf[i][4 * j + 1], lo[1], a);
-                            a = __builtin_fmaf(qf[i][4 * j + 2], hi[0], a);
-                            a = __builtin_fmaf(qf[i][4 * j + 3], hi[1], a);
+                        for (int j = 0; j < 4; ++j) {
+                            if constexpr (FMT == kFmtBf16) {
+                                const float x0 = bf16_lo(wv[j]), x1 = bf16_hi(wv[j]);
+                                a = __builtin_fmaf(qf[i][2 * j], x0, a);
+                                a = __builtin_fmaf(qf[i][2 * j + 1], x1, a);
+                                r2 = __builtin_fmaf(x0, x0, r2);
+                                r2 = __builtin_fmaf(x1, x1, r2);
+                            } else {
+                                const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], false);
+                                const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)wv[j], true);
+                                a = __builtin_fmaf(qf[i][4 * j], lo[0], a);
+                                a = __builtin_fmaf(qf[i][4 * j + 1], lo[1], a);
+                                a = __builtin_fmaf(qf[i][4 * j + 2], hi[0], a);
+                                a = __builtin_fmaf(qf[i][4 * j + 3], hi[1], a);
+                            }
                         }
                     }
-                }
-                const float dot = group_sum<GB>(a);
-                if constexpr (FMT == kFmtBf16) s[u] = (qn + group_sum<GB>(r2)) - 2.0f * dot;
-                else s[u] = (qn + xn[u]) - 2.0f * (xs[u] * dot);
-            }
-    #pragma unroll
-            for (int u = 0; u < U; ++u) {
-    #pragma unroll
-                for (int gg = 0; gg < GPW; ++gg) {
-                    const int32_t ci = read_lane_i(cid[u], gg * GB);
-                    const float cd = read_lane_f(s[u], gg * GB);
-                    if (ci >= 0 && key_less(cd, ci, tau_d, tau_i)) {
-                        top.insert(cd, ci);
-                        top.get(kp - 1, tau_d, tau_i);
+                    const float dot = group_sum<GB>(a);
+                    float sc;
+                    if constexpr (FMT == kFmtBf16) sc = (qn + group_sum<GB>(r2)) - 2.0f * dot;
+                    else sc = (qn + xn[u]) - 2.0f * (xs[u] * dot);
+                    // the group's first lane files the score under the slot
+                    if (gl == 0 && cid[u] >= 0) {
+                        const int e = slot(b0, u) - c0;
+                        pkey[e] = score_key(sc);
+                        pid[e] = cid[u];
                     }
                 }
             }
+            // the round's scores, then the list kept so far; keep the best kp
+            const int m = cend - c0;
+            __syncthreads();
+            for (int j = (int)threadIdx.x; j < nk; j += (int)blockDim.x) {
+                pkey[m + j] = ckey[j];
+                pid[m + j] = cand[j];
+            }
+            __syncthreads();
+            const int tot = m + nk;
+            if (tot <= kp) {
+                for (int j = (int)threadIdx.x; j < tot; j += (int)blockDim.x) {
+                    ckey[j] = pkey[j];
+                    cand[j] = pid[j];
+                }
+                nk = tot;
+                __syncthreads();
+            } else {
+                block_select(pkey, pid, tot, kp, ckey, cand, hist, sel);
+                nk = kp;
+            }
         }
-
-        // merge the wave lists: the best kp of the prefilter, in rank order
-        top.store(md[w], mi[w], kp);
-        __syncthreads();
-        for (int e = (int)threadIdx.x; e < kDistWaves * kp; e += (int)blockDim.x) {
-            const int ww = e / kp, pos = e - ww * kp;
-            const float kd = md[ww][pos];
-            const int32_t ki = mi[ww][pos];
-            int rank = pos;
-            for (int o = 0; o < kDistWaves; ++o)
-                if (o != ww) rank += count_less(md[o], mi[o], kp, kd, ki);
-            if (rank < kp) cand[rank] = kd < INFINITY ? ki : -1;
+        if constexpr (KEEP) {
+            // the kept list in prefilter rank order, (score, id)
+            for (int c = (int)threadIdx.x; c < kp; c += (int)blockDim.x) {
+                int rank = 0;
+                for (int o = 0; o < kp; ++o)
+                    rank += (ckey[o] < ckey[c] || (ckey[o] == ckey[c] && cand[o] < cand[c])) ? 1 : 0;
+                keep_out[q * kp + rank] = cand[c];
+            }
+            return;
         }
-        __syncthreads();
     } else {
         // every candidate survives the prefilter: phase 2 takes S as it is
         // (it orders by float32 distance and id, whatever the slot order)
@@ -522,41 +653,41 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
         int32_t *__restrict__ out_idx, float *__restrict__ out_dist
 #define MRPT_PF_ARGS X, Xq, sn8, d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist
 
-template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
+template <int FMT, int GB, int NVB, int G2, int NV2>
 __global__ __launch_bounds__(256) void dist_prefilter_kernel(MRPT_PF_PARAMS) {
-    dist_prefilter_body<FMT, GB, NVB, RB, G2, NV2>(MRPT_PF_ARGS);
+    dist_prefilter_body<FMT, GB, NVB, G2, NV2>(MRPT_PF_ARGS);
 }
 
 // The same kernel held to 72 registers, for seven waves per SIMD instead of
-// six.  Used where that costs no spill: bf16 rows of d <= 128 with kp <= 64
-// (the fp8 forms and larger kp spill heavily under the cap).
-template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
+// six.  Used where that costs no spill: bf16 rows of d <= 128 (the fp8 forms
+// spill heavily under the cap).
+template <int FMT, int GB, int NVB, int G2, int NV2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void dist_prefilter_w7_kernel(
     MRPT_PF_PARAMS) {
-    dist_prefilter_body<FMT, GB, NVB, RB, G2, NV2>(MRPT_PF_ARGS);
+    dist_prefilter_body<FMT, GB, NVB, G2, NV2>(MRPT_PF_ARGS);
 }
 
 // phase 1 only: the kept list of every query (parity hook)
-template <int FMT, int GB, int NVB, int RB, int G2, int NV2>
+template <int FMT, int GB, int NVB, int G2, int NV2>
 __global__ __launch_bounds__(256) void dist_prefilter_keep_kernel(MRPT_PF_PARAMS, int32_t* __restrict__ keep_out) {
-    dist_prefilter_body<FMT, GB, NVB, RB, G2, NV2, true>(MRPT_PF_ARGS, keep_out);
+    dist_prefilter_body<FMT, GB, NVB, G2, NV2, true>(MRPT_PF_ARGS, keep_out);
 }
 
 #undef MRPT_PF_ARGS
 #undef MRPT_PF_PARAMS
 
-template <int F, int GB, int NVB, int RR, int G2, int NV2>
+template <int F, int GB, int NVB, int G2, int NV2>
 void launch_prefilter_form(dim3 grid, hipStream_t s, const float* X, const uint8_t* Xq, const float2* sn8, int32_t d,
                            const float* Q, const int32_t* s_ids, int64_t cap, const int32_t* s_count, int32_t k,
                            int32_t kp, float recheck_rel, int32_t* out_idx, float* out_dist, int32_t* keep_out) {
     if (keep_out)
-        hipLaunchKernelGGL((dist_prefilter_keep_kernel<F, GB, NVB, RR, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8,
+        hipLaunchKernelGGL((dist_prefilter_keep_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8,
                            d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist, keep_out);
-    else if constexpr (F == kFmtBf16 && GB == 16 && NVB == 1 && RR == 1)
-        hipLaunchKernelGGL((dist_prefilter_w7_kernel<F, GB, NVB, RR, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
+    else if constexpr (F == kFmtBf16 && GB == 16 && NVB == 1)
+        hipLaunchKernelGGL((dist_prefilter_w7_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
                            Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
     else
-        hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, RR, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d, Q,
+        hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d, Q,
                            s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
 }
 
@@ -613,19 +744,12 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
     if (nq == 0) return hipSuccess;
     const int d = ix->d;
     const int kp = k * rerank;
-    const int RB = kp <= 64 ? 1 : kp <= 128 ? 2 : kp <= 256 ? 4 : 8;
     dim3 grid((unsigned)nq);
     const uint8_t* Xq = fp8 ? ix->X8 : reinterpret_cast<const uint8_t*>(ix->Xb);
-#define MRPT_PF(F, GB, NVB, RR, G2, NV2)                                                                        \
-    launch_prefilter_form<F, GB, NVB, RR, G2, NV2>(grid, s, ix->X, Xq, ix->sn8, d, Q, s_ids, cap, s_count, k, kp, \
+#define MRPT_PF(F, GB, NVB, G2, NV2)                                                                            \
+    launch_prefilter_form<F, GB, NVB, G2, NV2>(grid, s, ix->X, Xq, ix->sn8, d, Q, s_ids, cap, s_count, k, kp, \
                                                    recheck_rel, out_idx, out_dist, keep_out)
-#define MRPT_PF_R(F, GB, NVB, G2, NV2)                  \
-    switch (RB) {                                       \
-        case 1: MRPT_PF(F, GB, NVB, 1, G2, NV2); break; \
-        case 2: MRPT_PF(F, GB, NVB, 2, G2, NV2); break; \
-        case 4: MRPT_PF(F, GB, NVB, 4, G2, NV2); break; \
-        default: MRPT_PF(F, GB, NVB, 8, G2, NV2); break; \
-    }
+#define MRPT_PF_R(F, GB, NVB, G2, NV2) MRPT_PF(F, GB, NVB, G2, NV2)
     if (!fp8) {
         // bf16 loads per row d/8; the float32 rerank layout follows from it
         const int nv8 = d / 8;

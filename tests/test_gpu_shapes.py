@@ -1,0 +1,83 @@
+"""Parity at the shapes of the paper's ablation columns, through the paths
+those shapes take:
+
+  * the Random set (Sec. IV-A: unit-norm Gaussian vectors in 4,096
+    dimensions), scaled to a few thousand points: projection vectors with
+    about 64 nonzeros (a = 1/64), so some hold more than 64 and the index is
+    grown on host threads and queries are routed by the fused routing kernel;
+    distances by the generic (d > 1024) distance kernel;
+  * dense random projection trees (the footnote of Sec. IV-B and the RP-tree
+    column of Table III): a = 1, every vector holds all d features (128 and
+    784), again host build and fused routing.
+
+Leaves, candidate sets with their vote counts, |S| and the k nearest are
+compared with the oracle on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_06957_amd import mrpt
+from paper_1509_06957_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_helpers import build, check_knn, dev, leaves, query, votes  # noqa: E402
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _compare(X, Q, T, depth, a, seed, k, v):
+    orc = oracle.build_index(X, T, depth, a, seed)
+    g = build(X, T, depth, a, seed)
+    try:
+        rowptr, _, _ = mrpt.mrpt_export_projection(g.handle)
+        most = int(np.diff(rowptr).max())
+        Qd = dev(Q)
+        assert np.array_equal(leaves(g, Qd), oracle.route(orc, Q))
+        ref = oracle.query(orc, Q, k, v, want_sets=True)
+        ids, cnt = votes(g, Qd, v)
+        for q in range(len(Q)):
+            assert np.array_equal(ids[q], ref["s_ids"][q]), f"query {q}: S"
+            assert np.array_equal(cnt[q], ref["s_votes"][q]), f"query {q}: votes"
+        gi, gd, sc = query(g, Qd, k, v)
+        assert np.array_equal(sc, ref["s_count"])
+        check_knn(X, Q, gi, gd, ref["idx"], ref["dist"], exact_ids=False,
+                  S=[set(s.tolist()) for s in ref["s_ids"]])
+        return most, sc
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("v", [1, 2])
+def test_random_set_shape(v):
+    w = W.RANDOM.scaled(n=6000, nq=64, T=12, depth=6)
+    _case(f"{w.name} scaled: n={w.n} d={w.d} T={w.T} depth={w.depth} v={v}")
+    X, Q = W.data(w), W.queries(w)
+    assert np.allclose(np.linalg.norm(X.astype(np.float64), axis=1), 1.0, atol=1e-6)
+    most, sc = _compare(X, Q, w.T, w.depth, w.a, w.index_seed, w.k, v)
+    # vectors with more than 64 nonzeros: the fused routing kernel and the
+    # host build serve this index
+    assert most > 64, most
+    print(f"[shape] random d=4096: largest vector {most} nonzeros, |S| mean {sc.mean():.1f}", flush=True)
+
+
+@pytest.mark.parametrize("v", [1, 3])
+def test_dense_rp_trees_d128(v):
+    w = W.MIXTURE_128.scaled(nq=80)
+    _case(f"dense RP-trees a=1 d=128 v={v}")
+    X, Q = W.data(w), W.queries(w)
+    most, sc = _compare(X, Q, w.T, w.depth, 1.0, w.index_seed, w.k, v)
+    assert most == w.d
+
+
+def test_dense_rp_trees_mnist_like():
+    w = W.MNIST_LIKE.scaled(n=6000, nq=40, T=10, depth=5)
+    _case(f"dense RP-trees a=1 {w.name} scaled n={w.n}")
+    X, Q = W.data(w), W.queries(w)
+    most, sc = _compare(X, Q, w.T, w.depth, 1.0, w.index_seed, w.k, 2)
+    assert most == w.d
