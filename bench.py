@@ -11,6 +11,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,8 +23,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "queries/sec at recall@10=0.9 (1M×128, k=10); FP32 plain vs BF16+rerank"
 CSRC = os.path.join(ROOT, "paper_1509_06957_amd", "csrc")
-KERNEL_FILE = {"project_kernel": "kernels_route.hip", "vote_map_kernel": "kernels_vote.hip",
-               "dist_fp32_kernel": "kernels_search.hip", "dist_bf16_kernel": "kernels_search.hip"}
+# source file of each kernel family (the traffic summaries record a hash of
+# it with device_common.h; a summary of older source is not used)
+KERNEL_FILE = {"project_kernel": "kernels_route.hip", "route_pq_kernel": "kernels_route.hip",
+               "vote_map_kernel": "kernels_vote.hip", "vote_dir_kernel": "kernels_vote.hip",
+               "dist_fp32_kernel": "kernels_search.hip", "dist_prefilter_kernel": "kernels_search.hip",
+               "dist_prefilter_w7_kernel": "kernels_search.hip"}
 # the kernel that dominates each stage on this workload (rocprofv3 names)
 STAGE_KERNEL = {"route": "project_kernel", "vote": "vote_map_kernel", "search": "dist_fp32_kernel"}
 COPY_BYTES = 1 << 30
@@ -68,30 +73,35 @@ def hbm_copy_gbps(torch, nbytes=COPY_BYTES, reps=5):
 
 def kernel_source_hash(kernel):
     h = hashlib.sha256()
-    for name in (KERNEL_FILE[kernel], "device_common.h"):
+    for name in (KERNEL_FILE[kernel.split("<")[0]], "device_common.h"):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def read_traffic(kernel, workload_key):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_key}_traffic.txt")
+    """Memory-side bytes per launch of `kernel` (a rocprofv3 name prefix) from
+    the committed counter summary of this workload, if it was taken on the
+    current source; else None.  Returns (read + write bytes, row of the
+    summary as a dict)."""
+    path = os.path.join(ROOT, "profiles", f"query_kernels_{workload_key}_traffic.txt")
     if not os.path.exists(path):
-        return None
-    vals = {}
+        return None, None
+    cols = None
     with open(path) as f:
         for line in f:
-            if ":" in line and not line.startswith("#"):
-                key, val = line.split(":", 1)
-                vals[key.strip()] = val.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = re.split(r"\s{2,}", line.strip())
+            if parts[0] == "kernel":
+                cols = parts
+                continue
+            if cols and parts[0].startswith(kernel) and len(parts) == len(cols):
+                row = dict(zip(cols, parts))
+                if row.get("src_sha256_16") != kernel_source_hash(kernel):
+                    return None, None
+                return (float(row["read_MB"]) + float(row["write_MB"])) * 1e6, row
+    return None, None
 
 
 def main():
@@ -210,17 +220,32 @@ def main():
     qps16, stages16, tb16 = arm_record(el16, st16, "bf16")
     qps8, stages8, tb8 = arm_record(el8, st8, "fp8")
     dom = max(STAGES, key=lambda s: stages32[s]["ms"])
-    traffic = read_traffic(STAGE_KERNEL[dom], args.workload)
     copy_gbps = hbm_copy_gbps(torch)
     log(f"plain device copy: {copy_gbps:.0f} GB/s")
-    roofline = {
-        "bound": "hbm", "kernel": STAGE_KERNEL[dom],
-        "achieved": stages32[dom]["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(stages32[dom]["GBps"] / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
-        "bytes_per_launch": stages32[dom]["bytes"], "launch_ms": stages32[dom]["ms"],
-        "copy_GBps": round(copy_gbps, 1),
-    }
+
+    def roofline_of(stage, kernel):
+        """The stage's dominant kernel against 8 TB/s: algorithmic bytes per
+        launch over the launch's duration (HIP events on the query stream);
+        traffic = memory-side bytes per launch from the committed counter
+        summary (requests leaving L2, Infinity-Cache hits included), or None
+        when that summary predates the kernel's source."""
+        traffic, row = read_traffic(kernel, args.workload)
+        return {
+            "bound": "hbm", "kernel": kernel,
+            "achieved": stage["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(stage["GBps"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "traffic_over_algorithmic": round(traffic / stage["bytes"], 4) if traffic else None,
+            "bytes_per_launch": stage["bytes"], "launch_ms": stage["ms"],
+            "profiled_launch_us": float(row["avg_us"]) if row else None,
+            "copy_GBps": round(copy_gbps, 1),
+        }
+
+    roofline = roofline_of(stages32[dom], STAGE_KERNEL[dom])
+    bf16_kernel = "dist_prefilter_w7_kernel" if w.d <= 128 else "dist_prefilter_kernel<0"
+    roofline16 = roofline_of(stages16["search"], bf16_kernel)
+    roofline8 = roofline_of(stages8["search"], "dist_prefilter_kernel<1")
+    roofline_vote = roofline_of(stages32["vote"], "vote_map_kernel" if w.d <= 128 else "vote_dir_kernel")
 
     # latency of one query call (fp32 arm, all five steps) per batch size:
     # host clock around the call and a synchronisation, inputs resident
@@ -328,17 +353,19 @@ def main():
         "s_size": {"mean": round(float(S.mean()), 1), "p50": float(np.percentile(S, 50)),
                    "p99": float(np.percentile(S, 99))},
         "stages": stages32,
+        "vote_roofline": roofline_vote,
         "path_hbm_frac": round(tb32 / (el32 / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
         "arms": {
             "fp32": {"qps": round(qps32, 1), "ms_per_step": round(el32 / args.steps * 1e3, 4),
                      "recall_at_k": round(rec32, 4), "max_rel_err_vs_fp64": err32, "stages": stages32},
             "bf16_rerank": {"qps": round(qps16, 1), "ms_per_step": round(el16 / args.steps * 1e3, 4),
                             "recall_at_k": round(rec16, 4), "max_rel_err_vs_fp64": err16,
-                            "stages": stages16,
+                            "stages": stages16, "roofline": roofline16,
                             "path_hbm_frac": round(tb16 / (el16 / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
                             "identical_to_fp32": bool(np.array_equal(gi32, gi16) and np.array_equal(gd32, gd16))},
             "fp8_rerank": {"qps": round(qps8, 1), "ms_per_step": round(el8 / args.steps * 1e3, 4),
                            "recall_at_k": round(rec8, 4), "max_rel_err_vs_fp64": err8, "stages": stages8,
+                           "roofline": roofline8,
                            "path_hbm_frac": round(tb8 / (el8 / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
                            "ids_equal_fp32_frac": round(float(np.mean(np.all(gi8 == gi32, axis=1))), 4)},
         },

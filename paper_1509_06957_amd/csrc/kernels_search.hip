@@ -27,6 +27,123 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 constexpr int kDistWaves = 4;
 
+// Selection of the best candidates of a query: up to kPfChunk candidates are
+// scored at a time into LDS, and a block-wide radix select over them and the
+// list kept so far keeps the best ones under (score, id).
+constexpr int kPfChunk = 1024;                  // candidates scored per selection round
+constexpr int kPfBuf = kPfChunk + kMaxRerank;   // prefilter: one round's scores, then the list kept so far
+
+// monotone map of a float32 score to an unsigned key: -0 as +0, NaN after
+// every number (a NaN score comes from a non-finite query and ranks last)
+__device__ __forceinline__ uint32_t score_key(float s) {
+    uint32_t u = __builtin_bit_cast(uint32_t, s);
+    if ((u << 1) == 0u) u = 0u;
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0u) return 0xFFFFFFFFu;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// wave 0 of a select pass: the bucket of hist[0..255] that holds the rem-th
+// smallest of the counted pairs; sel = {bucket, rank within it, its count}
+__device__ __forceinline__ void pick_bucket(const uint32_t* hist, int rem, int* sel) {
+    const int lane = lane_id();
+    const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+    const int own = (int)(h0 + h1 + h2 + h3);
+    int incl = own;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    const int excl = incl - own;
+    if (excl < rem && rem <= incl) {
+        const uint32_t h[4] = {h0, h1, h2, h3};
+        int c = excl;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (c < rem && rem <= c + (int)h[j]) {
+                sel[0] = 4 * lane + j;
+                sel[1] = rem - c;
+                sel[2] = (int)h[j];
+            }
+            c += (int)h[j];
+        }
+    }
+}
+
+// The need smallest of the tot pairs (key[e], id[e]) under (key, id), ids
+// distinct, need < tot, written to (okey, oid)[0, need) in no particular
+// order.  A radix select over the key's bytes from the top finds the key T of
+// the need-th pair and how many pairs at T are taken; when that is not all
+// of them, a second radix select over the ids of the pairs at T finds the
+// largest id taken.  All 256 threads of the workgroup take part.
+__device__ void block_select(const uint32_t* key, const int32_t* id, int tot, int need, uint32_t* okey,
+                             int32_t* oid, uint32_t* hist, int* sel) {
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid >> 6;
+    uint32_t prefix = 0u, pmask = 0u;
+    int rem = need, eq = tot;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hist[tid] = 0u;
+        __syncthreads();
+        for (int e = tid; e < tot; e += 256) {
+            const uint32_t kk = key[e];
+            if ((kk & pmask) == prefix) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (w == 0) pick_bucket(hist, rem, sel);
+        __syncthreads();
+        prefix |= (uint32_t)sel[0] << shift;
+        pmask |= 0xFFu << shift;
+        rem = sel[1];
+        eq = sel[2];
+    }
+    const uint32_t T = prefix;
+    uint32_t idT = 0xFFFFFFFFu;                  // pairs at T with id <= idT are taken
+    if (rem < eq) {
+        uint32_t ip = 0u, im = 0u;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            hist[tid] = 0u;
+            __syncthreads();
+            for (int e = tid; e < tot; e += 256) {
+                const uint32_t ii = (uint32_t)id[e];
+                if (key[e] == T && (ii & im) == ip) atomicAdd(&hist[(ii >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (w == 0) pick_bucket(hist, rem, sel);
+            __syncthreads();
+            ip |= (uint32_t)sel[0] << shift;
+            im |= 0xFFu << shift;
+            rem = sel[1];
+        }
+        idT = ip;
+    }
+    if (tid == 0) sel[3] = 0;
+    __syncthreads();
+    for (int e0 = 0; e0 < tot; e0 += 256) {      // uniform trip count
+        const int e = e0 + tid;
+        bool take = false;
+        uint32_t kk = 0u;
+        int32_t ii = 0;
+        if (e < tot) {
+            kk = key[e];
+            ii = id[e];
+            take = kk < T || (kk == T && (uint32_t)ii <= idT);
+        }
+        const uint64_t m = __ballot(take);
+        int base = 0;
+        if (lane == 0 && m) base = atomicAdd(&sel[3], __popcll(m));
+        base = __shfl(base, 0);
+        if (take) {
+            const int p = base + __popcll(m & __lanemask_lt());
+            okey[p] = kk;
+            oid[p] = ii;
+        }
+    }
+    __syncthreads();
+}
+
+
 template <int G, int NV, int R>
 __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict__ X, int32_t d,
                                                         const float* __restrict__ Q,
@@ -205,119 +322,6 @@ __global__ __launch_bounds__(256) void dist_fp32_generic_kernel(const float* __r
 // is within recheck_rel of the k-th and orders that window by (float64
 // distance, id).  One workgroup (4 waves) per query.
 // ---------------------------------------------------------------------------
-constexpr int kPfChunk = 1024;                  // candidates scored per selection round
-constexpr int kPfBuf = kPfChunk + kMaxRerank;   // one round's scores, then the list kept so far
-
-// monotone map of a float32 score to an unsigned key: -0 as +0, NaN after
-// every number (a NaN score comes from a non-finite query and ranks last)
-__device__ __forceinline__ uint32_t score_key(float s) {
-    uint32_t u = __builtin_bit_cast(uint32_t, s);
-    if ((u << 1) == 0u) u = 0u;
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0u) return 0xFFFFFFFFu;
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-// wave 0 of a select pass: the bucket of hist[0..255] that holds the rem-th
-// smallest of the counted pairs; sel = {bucket, rank within it, its count}
-__device__ __forceinline__ void pick_bucket(const uint32_t* hist, int rem, int* sel) {
-    const int lane = lane_id();
-    const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
-    const int own = (int)(h0 + h1 + h2 + h3);
-    int incl = own;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int t = __shfl_up(incl, o);
-        if (lane >= o) incl += t;
-    }
-    const int excl = incl - own;
-    if (excl < rem && rem <= incl) {
-        const uint32_t h[4] = {h0, h1, h2, h3};
-        int c = excl;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (c < rem && rem <= c + (int)h[j]) {
-                sel[0] = 4 * lane + j;
-                sel[1] = rem - c;
-                sel[2] = (int)h[j];
-            }
-            c += (int)h[j];
-        }
-    }
-}
-
-// The need smallest of the tot pairs (key[e], id[e]) under (key, id), ids
-// distinct, need < tot, written to (okey, oid)[0, need) in no particular
-// order.  A radix select over the key's bytes from the top finds the key T of
-// the need-th pair and how many pairs at T are taken; when that is not all
-// of them, a second radix select over the ids of the pairs at T finds the
-// largest id taken.  All 256 threads of the workgroup take part.
-__device__ void block_select(const uint32_t* key, const int32_t* id, int tot, int need, uint32_t* okey,
-                             int32_t* oid, uint32_t* hist, int* sel) {
-    const int tid = (int)threadIdx.x;
-    const int lane = lane_id();
-    const int w = tid >> 6;
-    uint32_t prefix = 0u, pmask = 0u;
-    int rem = need, eq = tot;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        hist[tid] = 0u;
-        __syncthreads();
-        for (int e = tid; e < tot; e += 256) {
-            const uint32_t kk = key[e];
-            if ((kk & pmask) == prefix) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
-        }
-        __syncthreads();
-        if (w == 0) pick_bucket(hist, rem, sel);
-        __syncthreads();
-        prefix |= (uint32_t)sel[0] << shift;
-        pmask |= 0xFFu << shift;
-        rem = sel[1];
-        eq = sel[2];
-    }
-    const uint32_t T = prefix;
-    uint32_t idT = 0xFFFFFFFFu;                  // pairs at T with id <= idT are taken
-    if (rem < eq) {
-        uint32_t ip = 0u, im = 0u;
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            hist[tid] = 0u;
-            __syncthreads();
-            for (int e = tid; e < tot; e += 256) {
-                const uint32_t ii = (uint32_t)id[e];
-                if (key[e] == T && (ii & im) == ip) atomicAdd(&hist[(ii >> shift) & 255u], 1u);
-            }
-            __syncthreads();
-            if (w == 0) pick_bucket(hist, rem, sel);
-            __syncthreads();
-            ip |= (uint32_t)sel[0] << shift;
-            im |= 0xFFu << shift;
-            rem = sel[1];
-        }
-        idT = ip;
-    }
-    if (tid == 0) sel[3] = 0;
-    __syncthreads();
-    for (int e0 = 0; e0 < tot; e0 += 256) {      // uniform trip count
-        const int e = e0 + tid;
-        bool take = false;
-        uint32_t kk = 0u;
-        int32_t ii = 0;
-        if (e < tot) {
-            kk = key[e];
-            ii = id[e];
-            take = kk < T || (kk == T && (uint32_t)ii <= idT);
-        }
-        const uint64_t m = __ballot(take);
-        int base = 0;
-        if (lane == 0 && m) base = atomicAdd(&sel[3], __popcll(m));
-        base = __shfl(base, 0);
-        if (take) {
-            const int p = base + __popcll(m & __lanemask_lt());
-            okey[p] = kk;
-            oid[p] = ii;
-        }
-    }
-    __syncthreads();
-}
-
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
 

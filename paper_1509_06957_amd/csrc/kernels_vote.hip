@@ -263,9 +263,11 @@ __global__ void vote_dir_build_kernel(const int32_t* __restrict__ perm, const in
 // round-robin over the 16 waves: slot s of wave w is window w + 16 s.  Every
 // slot issues one load per lane with no branch around it (so the compiler
 // can count the loads in flight): a lane beyond its leaf, or a slot beyond
-// the last tree, reads the padding entry n + 32 lane + s of perm row 0, which
-// holds that value; such ids are never queued or elected, and their map bits
-// lie in spare words past the ids, a different word for every lane of a slot.
+// the last tree, reads the padding entry n + lane of perm row 0, which holds
+// that value; such ids are never queued or elected, and their map bits lie
+// in spare words past the ids.  Loads address perm by a 32-bit byte offset
+// from its base.  Two queries are counted per loop turn, so the windows in
+// flight and the windows counted swap register arrays instead of moving.
 constexpr int kMapBatch = 5;         // slots whose map updates are issued together
 constexpr int kPosBufs = 3;          // leaf position buffers of the pipeline
 
@@ -343,19 +345,19 @@ __device__ __forceinline__ void slot_windows(const int2* __restrict__ tpos, int 
 }
 
 template <int S>
-__device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int32_t* __restrict__ perm, int32_t n32,
+__device__ __forceinline__ void load_windows(int32_t (&dst)[S], const int32_t* __restrict__ perm, uint32_t pad4,
                                              int first_v, int avail_v) {
     const int lane = lane_id();
+    const uint32_t lane4 = (uint32_t)lane * 4u;
+    const char* base = reinterpret_cast<const char*>(perm);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const int first = __builtin_amdgcn_readlane(first_v, s);
+        // byte offset from the start of perm (T * ld * 4 < 2^32): the slot's
+        // entry for lanes inside the window, the lane's padding entry else
+        const uint32_t first4 = (uint32_t)__builtin_amdgcn_readlane(first_v, s) * 4u;
         const int avail = __builtin_amdgcn_readlane(avail_v, s);
-        int pad = n32 + lane * 32 + s;
-        // keeps the S padding offsets separate: formed as one vector (base +
-        // 0..S-1) they are allocated as a single register tuple and spilled
-        asm volatile("" : "+v"(pad));
-        const int idx = lane < avail ? first + lane : pad;
-        dst[s] = perm[(uint32_t)idx];
+        const uint32_t at = lane < avail ? first4 + lane4 : pad4;
+        dst[s] = *reinterpret_cast<const int32_t*>(base + at);
     }
 }
 
@@ -548,14 +550,17 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     if (tid == 0) { *qfill = 0; *nsel = 0; }
     __syncthreads();
 
+    const uint32_t pad4 = (uint32_t)(n32 + lane_id()) * 4u;
     int32_t ids[S], nid[S];
     {
         int first_v, avail_v;
         slot_windows(tpos[0], slot_row, slot_tp, first_v, avail_v);
-        load_windows<S>(ids, perm, n32, first_v, avail_v);
+        load_windows<S>(ids, perm, pad4, first_v, avail_v);
     }
     int cur = 0;
-    while (true) {
+    // one query: count the windows in `win`, load the next query's into
+    // `nxt`; false after the last query of this workgroup
+    auto step = [&](int32_t (&win)[S], int32_t (&nxt)[S]) -> bool {
         const int64_t q1 = q + G, q2 = q + 2 * G, q3 = q + 3 * G;
         const int b1 = cur == kPosBufs - 1 ? 0 : cur + 1;
         const int b2 = b1 == kPosBufs - 1 ? 0 : b1 + 1;
@@ -564,11 +569,11 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         {
             int first_v, avail_v;
             slot_windows(tpos[b1], slot_row, slot_tp, first_v, avail_v);
-            load_windows<S>(nid, perm, n32, first_v, avail_v);
+            load_windows<S>(nxt, perm, pad4, first_v, avail_v);
         }
-        int ob = 0, oe = 0, Lnn = 0;
+        int pb = 0, pe = 0, Lnn = 0;
         if (tid < T) {
-            if (q2 < nq) { ob = off[Lnext]; oe = off[Lnext + 1]; }
+            if (q2 < nq) { pb = off[Lnext]; pe = off[Lnext + 1]; }
             if (q3 < nq) Lnn = leaf[q3 * T + tid];
         }
         int32_t* out = s_ids + q * cap;
@@ -586,10 +591,10 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
                 ob[g] = 0u;
                 bid[g] = n32;   // an absent slot: never real, never stored
                 if (s0 + g < S) {
-                    const uint32_t id = (uint32_t)ids[s0 + g];
-                    const uint32_t bit = 1u << (id & 31u);
+                    const int32_t id = win[s0 + g];
+                    const uint32_t bit = 1u << (id & 31);
                     ob[g] = atomicOr(&map[id >> 5], bit) & bit;
-                    bid[g] = (int32_t)id;
+                    bid[g] = id;
                 }
             }
             if constexpr (QUEUE) append_batch<true, NB>(ob, bid, n32, qfill, spare, queue, (uint32_t)qcap);
@@ -607,7 +612,7 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
             }
         }
         // buffer b2 last served the query before q, whose windows are loaded
-        if (tid < T && q2 < nq) tpos[b2][tid] = make_int2(ob, oe - ob);
+        if (tid < T && q2 < nq) tpos[b2][tid] = make_int2(pb, pe - pb);
         if (tid == 0) {
             // a queue that overflowed (more reserved than qcap) marks the query
             s_count[q] = *qfill > qcap ? -1 : (*nsel < cap ? *nsel : (int32_t)cap);
@@ -617,11 +622,13 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         for (int i = tid; i < clear_vec; i += kVoteBlock)
             reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
         lds_barrier();
-        if (q1 >= nq) break;
-        for (int s = 0; s < S; ++s) ids[s] = nid[s];
+        if (q1 >= nq) return false;
         Lnext = Lnn;
         cur = b1;
         q = q1;
+        return true;
+    };
+    while (step(ids, nid) && step(nid, ids)) {
     }
 }
 
@@ -672,7 +679,7 @@ int vote_kernel_override() {
 size_t vote_lds_limit() { return (size_t)std::min(lds_per_block_limit(), 160 * 1024); }
 
 // single-pass geometry: map words (ids 0 .. n + 2047: real ids, then the
-// empty lanes' ids n + 32 lane + s), the repeat queue in what LDS has left
+// empty lanes' ids n + lane), the repeat queue in what LDS has left
 struct SingleGeometry {
     bool ok;
     int32_t wpl;
@@ -696,7 +703,7 @@ SingleGeometry single_geometry(const mrpt_index* ix, bool queued) {
     if (queued && cap_env && *cap_env && std::atoll(cap_env) > 0)
         g.qcap = std::min<int64_t>(g.qcap, std::atoll(cap_env) / 4 * 4);
     g.ok = g.slots <= kVoteSlots && ix->n < (int64_t(1) << 24) &&
-           (int64_t)ix->T * ix->perm_ld < (int64_t(1) << 31) && room >= 0 && (!queued || g.qcap >= 1024);
+           (int64_t)ix->T * ix->perm_ld < (int64_t(1) << 30) && room >= 0 && (!queued || g.qcap >= 1024);
     g.lds = (size_t)(g.map_words + g.qcap) * 4 + kMapTail;
     return g;
 }
