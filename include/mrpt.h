@@ -189,10 +189,13 @@ mrpt_status mrpt_index_info(const mrpt_index* ix, mrpt_index_desc* out);
  * Batches with the same (index, k, v) are searched as one query call: their
  * queries are gathered into a staging array and the results scattered back
  * (every step works per query, so the results are the per-batch ones).  A
- * plan owns the workspace and staging memory of every such group, so groups
- * do not wait for each other: they are dealt over `branches` independent
- * chains of the graph (balanced by estimated work), and the GPU may run the
- * chains concurrently.  The plan keeps the pointers it was given: each launch
+ * plan owns the workspace and staging memory of every such group.  By
+ * default (fused) each stage of the search (routing, voting, exact search)
+ * is one launch per kernel form over all groups of that form, whatever
+ * their index: the kernels read each group's index arrays, queries,
+ * workspace and outputs from a device table.  Otherwise the groups are dealt
+ * over `branches` independent chains of the graph (balanced by estimated
+ * work), and the GPU may run the chains concurrently.  The plan keeps the pointers it was given: each launch
  * reads the current contents of every batch's Q and overwrites its outputs,
  * in the launch stream's order.
  * The indexes must outlive the plan.  Launches of one plan must not overlap
@@ -216,8 +219,13 @@ typedef struct mrpt_plan_opts {
     int32_t proj_rows;      /* projection vectors per wave: 0 (default) the launcher's choice
                                (4 for launches under 512 workgroups, else 16), or 4, or 16 */
     int32_t vote_kernel;    /* 0 (default) automatic; 1 the single-pass vote kernel wherever it
-                               fits; 2 the multi-pass one.  Neither knob changes a result; they
-                               are there for tuning the launches. */
+                               fits; 2 the multi-pass one. */
+    int32_t fused;          /* 1 (default): one launch per stage for all groups of a kernel form
+                               (calls of the same kernel shape, whatever their index), driven by
+                               device tables of (index arrays, query range, k, v, workspace), in
+                               one chain; 0: every group its own chain of launches, dealt over
+                               `branches`.  None of these knobs changes a result; they are there
+                               for tuning the launches. */
 } mrpt_plan_opts;
 
 typedef struct mrpt_plan mrpt_plan;

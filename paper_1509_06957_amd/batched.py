@@ -33,6 +33,7 @@ def main():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--precision", default="bf16", choices=("fp32", "bf16"))
+    p.add_argument("--fused", default="1,0", help="plan forms to try (1: per-stage launches across indexes)")
     p.add_argument("--branches", default="1,2,4,8,16")
     p.add_argument("--proj-rows", default="0,16", help="projection vectors per wave to try (0: automatic)")
     p.add_argument("--vote-kernels", default="0,2", help="vote kernels to try (0 automatic, 1 single-pass, 2 multi-pass)")
@@ -74,23 +75,29 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps * 1e3
 
-    # autotuner over the recorded graph's launch choices
+    # autotuner over the recorded graph's launch choices: per-stage launches
+    # across the indexes (fused) or per-group chains over a branch count,
+    # projection rows per wave, vote kernel
     tuning = {}
     best = None
-    for b in [int(x) for x in args.branches.split(",")]:
-        for pr in [int(x) for x in args.proj_rows.split(",")]:
-            for vk in [int(x) for x in args.vote_kernels.split(",")]:
-                plan = mrpt.Plan(batches, precision=prec, branches=b, proj_rows=pr, vote_kernel=vk)
-                ms = time_launches(plan.launch, max(2, args.steps // 2))
-                key = f"branches={b},proj_rows={pr},vote_kernel={vk}"
-                tuning[key] = round(ms, 4)
-                log(f"{key}: {ms:.3f} ms per step")
-                if best is None or ms < best[1]:
-                    if best is not None:
-                        best[2].close()
-                    best = (key, ms, plan)
-                else:
-                    plan.close()
+    cands = []
+    for f in [int(x) for x in args.fused.split(",")]:
+        for b in ([1] if f else [int(x) for x in args.branches.split(",")]):
+            for pr in [int(x) for x in args.proj_rows.split(",")]:
+                for vk in [int(x) for x in args.vote_kernels.split(",")]:
+                    cands.append((f, b, pr, vk))
+    for f, b, pr, vk in cands:
+        plan = mrpt.Plan(batches, precision=prec, branches=b, proj_rows=pr, vote_kernel=vk, fused=f)
+        ms = time_launches(plan.launch, max(2, args.steps // 2))
+        key = f"fused={f},branches={b},proj_rows={pr},vote_kernel={vk}"
+        tuning[key] = round(ms, 4)
+        log(f"{key}: {ms:.3f} ms per step")
+        if best is None or ms < best[1]:
+            if best is not None:
+                best[2].close()
+            best = (key, ms, plan)
+        else:
+            plan.close()
     b_best, _, plan = best
     plan_ms = time_launches(plan.launch, args.steps)
     out = plan.launch()

@@ -730,6 +730,7 @@ void mrpt_default_plan_opts(mrpt_plan_opts* o) {
     o->branches = 4;
     o->proj_rows = 0;
     o->vote_kernel = 0;
+    o->fused = 1;
 }
 
 mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mrpt_plan_opts* opts,
@@ -744,6 +745,7 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
     if (po.proj_rows != 0 && po.proj_rows != 4 && po.proj_rows != 16)
         return fail(MRPT_EINVAL, "proj_rows = %d is not 0, 4 or 16", po.proj_rows);
     if (po.vote_kernel < 0 || po.vote_kernel > 2) return fail(MRPT_EINVAL, "vote_kernel = %d outside [0, 2]", po.vote_kernel);
+    if (po.fused != 0 && po.fused != 1) return fail(MRPT_EINVAL, "fused = %d is not 0 or 1", po.fused);
     LaunchCfg cfg;
     cfg.proj_rows = po.proj_rows;
     cfg.vote_kernel = po.vote_kernel;
@@ -822,6 +824,83 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
         g.work = (double)g.rows * (4.0 * ids + 4.0 * g.ix->d * ids / g.v);
     }
 
+    // fused form: the groups of every stage's kernel form, and the device
+    // tables their launches read (placed after the groups' memory)
+    struct Class {
+        int64_t key = 0;
+        std::vector<int32_t> members;   // group numbers
+        size_t tab_off = 0, row_off = 0;
+        int64_t rows = 0;
+    };
+    std::vector<Class> route_cls, vote_cls, search_cls;
+    std::vector<int32_t> route_alone, vote_alone, search_alone;   // groups launched on their own
+    size_t gather_off = 0, scatter_off = 0;
+    int32_t n_gather = 0, n_scatter = 0;
+    const bool fused = po.fused != 0;
+    if (fused) {
+        auto add = [](std::vector<Class>& cls, int64_t key, int32_t g) {
+            for (Class& c : cls)
+                if (c.key == key) { c.members.push_back(g); return; }
+            Class c;
+            c.key = key;
+            c.members.push_back(g);
+            cls.push_back(c);
+        };
+        for (int32_t gi = 0; gi < (int32_t)groups.size(); ++gi) {
+            const Group& g = groups[gi];
+            const int32_t rf = route_form(g.ix);
+            if (rf >= 0) add(route_cls, rf, gi);
+            else route_alone.push_back(gi);
+            const int64_t vf = vote_form(g.ix, g.v, cfg);
+            if (vf >= 0) add(vote_cls, vf, gi);
+            else vote_alone.push_back(gi);
+            // a staged group's queries are 256-byte aligned; a lone batch's are the caller's
+            const float* qp = g.staged() ? nullptr : batches[g.members[0]].Q;
+            const int32_t sf = search_form(g.ix, o.precision, g.k, qp);
+            if (sf >= 0) add(search_cls, ((int64_t)sf << 20) | g.ix->d, gi);
+            else search_alone.push_back(gi);
+        }
+        // vote classes whose queue would not fit LDS go back to one launch per group
+        for (size_t c = 0; c < vote_cls.size();) {
+            int32_t mw = 0;
+            int64_t most = 0;
+            for (int32_t gi : vote_cls[c].members) {
+                mw = std::max(mw, vote_map_words(groups[gi].ix));
+                most = std::max<int64_t>(most, (int64_t)groups[gi].ix->T * groups[gi].ix->max_leaf);
+            }
+            if (vote_multi_qcap(mw, most) < 0) {
+                for (int32_t gi : vote_cls[c].members) vote_alone.push_back(gi);
+                vote_cls.erase(vote_cls.begin() + (long)c);
+            } else {
+                ++c;
+            }
+        }
+        for (Class& c : route_cls) {
+            c.tab_off = total;
+            total += align(c.members.size() * sizeof(RouteItem));
+        }
+        for (Class& c : vote_cls) {
+            for (int32_t gi : c.members) c.rows += groups[gi].rows;
+            c.tab_off = total;
+            total += align(c.members.size() * sizeof(VoteItem));
+            c.row_off = total;
+            total += align((size_t)c.rows * sizeof(int32_t));
+        }
+        for (Class& c : search_cls) {
+            c.tab_off = total;
+            total += align(c.members.size() * sizeof(SearchItem));
+        }
+        for (const Group& g : groups)
+            if (g.staged()) {
+                n_gather += (int32_t)g.members.size();
+                n_scatter += 2 * (int32_t)g.members.size();
+            }
+        gather_off = total;
+        total += align((size_t)n_gather * sizeof(CopyJob));
+        scatter_off = total;
+        total += align((size_t)n_scatter * sizeof(CopyJob));
+    }
+
     std::unique_ptr<mrpt_plan> plan;
     try {
         plan.reset(new mrpt_plan());
@@ -857,6 +936,233 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
                                hipMemcpyHostToDevice));
         MRPT_HIP_TRY(hipMemcpy(base + g.sj_off, scatter.data(), scatter.size() * sizeof(CopyJob),
                                hipMemcpyHostToDevice));
+    }
+
+    if (fused) {
+        // the call of group g: its queries, workspace and outputs
+        auto call_Q = [&](const Group& g) -> const float* {
+            return g.staged() ? reinterpret_cast<const float*>(base + g.q_off) : batches[g.members[0]].Q;
+        };
+        auto call_idx = [&](const Group& g) -> int32_t* {
+            return g.staged() ? reinterpret_cast<int32_t*>(base + g.oi_off) : batches[g.members[0]].out_idx;
+        };
+        auto call_dist = [&](const Group& g) -> float* {
+            return g.staged() ? reinterpret_cast<float*>(base + g.od_off) : batches[g.members[0]].out_dist;
+        };
+        auto call_ws = [&](const Group& g) -> Workspace {
+            Workspace ws;
+            (void)workspace_layout(g.ix, g.rows, g.cap, base + g.ws_off, &ws);
+            return ws;
+        };
+        // device tables
+        struct RouteLaunch { int32_t form, rpw, qpl, max_d; int64_t blocks_p, blocks_r; };
+        std::vector<RouteLaunch> rl;
+        for (const Class& c : route_cls) {
+            int64_t tiles = 0;
+            for (int32_t gi : c.members) {
+                const Group& g = groups[gi];
+                const RouteGrid r16 = route_grid(g.ix, g.rows, 16, 1);
+                tiles += r16.nbx_p * r16.nby_p;
+            }
+            RouteLaunch L{(int32_t)c.key, 0, 0, 0, 0, 0};
+            route_shape(L.form, tiles, po.proj_rows, &L.rpw, &L.qpl);
+            std::vector<RouteItem> items;
+            for (int32_t gi : c.members) {
+                const Group& g = groups[gi];
+                if (!route_form_holds(L.form, g.ix))
+                    return fail(MRPT_EINTERNAL, "routing form %d does not hold group %d", L.form, gi);
+                const Workspace ws = call_ws(g);
+                const RouteGrid rg = route_grid(g.ix, g.rows, L.rpw, L.qpl);
+                RouteItem it;
+                it.Q = call_Q(g);
+                it.rowptr = g.ix->rowptr;
+                it.col = g.ix->col;
+                it.val = g.ix->val;
+                it.splits = g.ix->splits;
+                it.Pq = ws.pq;
+                it.leaf = ws.leaf;
+                it.nq = g.rows;
+                it.blk0_p = L.blocks_p;
+                it.blk0_r = L.blocks_r;
+                it.nbx_p = rg.nbx_p;
+                it.nbx_r = rg.nbx_r;
+                it.d = g.ix->d;
+                it.nrows = g.ix->T * g.ix->depth;
+                it.T = g.ix->T;
+                it.depth = g.ix->depth;
+                items.push_back(it);
+                L.blocks_p += rg.nbx_p * rg.nby_p;
+                L.blocks_r += rg.nbx_r * rg.nby_r;
+                L.max_d = std::max(L.max_d, g.ix->d);
+            }
+            MRPT_HIP_TRY(hipMemcpy(base + c.tab_off, items.data(), items.size() * sizeof(RouteItem),
+                                   hipMemcpyHostToDevice));
+            rl.push_back(L);
+        }
+        struct VoteLaunch { int32_t map_words; int64_t qcap; };
+        std::vector<VoteLaunch> vl;
+        std::vector<std::vector<int32_t>> recount((size_t)vote_cls.size());
+        for (size_t ci = 0; ci < vote_cls.size(); ++ci) {
+            const Class& c = vote_cls[ci];
+            VoteLaunch L{0, 0};
+            int64_t most = 0;
+            for (int32_t gi : c.members) {
+                L.map_words = std::max(L.map_words, vote_map_words(groups[gi].ix));
+                most = std::max<int64_t>(most, (int64_t)groups[gi].ix->T * groups[gi].ix->max_leaf);
+            }
+            L.qcap = vote_multi_qcap(L.map_words, most);
+            std::vector<VoteItem> items;
+            std::vector<int32_t> row_item;
+            int64_t row0 = 0;
+            for (int32_t gi : c.members) {
+                const Group& g = groups[gi];
+                const Workspace ws = call_ws(g);
+                VoteItem it;
+                it.leaf = ws.leaf;
+                it.perm = g.ix->perm;
+                it.off = g.ix->off;
+                it.s_ids = ws.s_ids;
+                it.s_count = ws.s_count;
+                it.cap = g.cap;
+                it.ld = g.ix->perm_ld;
+                it.row0 = row0;
+                it.n = (int32_t)g.ix->n;
+                it.v = g.v;
+                it.map_words = vote_map_words(g.ix);
+                it.pad_ = 0;
+                row_item.insert(row_item.end(), (size_t)g.rows, (int32_t)items.size());
+                items.push_back(it);
+                row0 += g.rows;
+                // a group whose queries could overflow the queue is counted again
+                if (g.v >= 2 && L.qcap < vote_most_queued(g.ix)) recount[ci].push_back(gi);
+            }
+            MRPT_HIP_TRY(hipMemcpy(base + c.tab_off, items.data(), items.size() * sizeof(VoteItem),
+                                   hipMemcpyHostToDevice));
+            MRPT_HIP_TRY(hipMemcpy(base + c.row_off, row_item.data(), row_item.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice));
+            vl.push_back(L);
+        }
+        std::vector<int64_t> sl;   // rows per search class
+        for (const Class& c : search_cls) {
+            std::vector<SearchItem> items;
+            int64_t row0 = 0;
+            for (int32_t gi : c.members) {
+                const Group& g = groups[gi];
+                const Workspace ws = call_ws(g);
+                SearchItem it;
+                it.X = g.ix->X;
+                it.Xq = o.precision == MRPT_FP8_RERANK ? g.ix->X8 : reinterpret_cast<const uint8_t*>(g.ix->Xb);
+                it.sn8 = g.ix->sn8;
+                it.Q = call_Q(g);
+                it.s_ids = ws.s_ids;
+                it.s_count = ws.s_count;
+                it.out_idx = call_idx(g);
+                it.out_dist = call_dist(g);
+                it.cap = g.cap;
+                it.row0 = row0;
+                it.k = g.k;
+                it.kp = g.k * o.rerank_factor;
+                items.push_back(it);
+                row0 += g.rows;
+            }
+            MRPT_HIP_TRY(hipMemcpy(base + c.tab_off, items.data(), items.size() * sizeof(SearchItem),
+                                   hipMemcpyHostToDevice));
+            sl.push_back(row0);
+        }
+        // one gather and one scatter job table for all staged groups
+        std::vector<CopyJob> gather, scatter;
+        int64_t most_g = 0, most_s = 0;
+        for (const Group& g : groups) {
+            if (!g.staged()) continue;
+            int64_t row = 0;
+            const int d = g.ix->d;
+            for (int32_t i : g.members) {
+                const mrpt_batch& b = batches[i];
+                gather.push_back({reinterpret_cast<const int32_t*>(b.Q),
+                                  reinterpret_cast<int32_t*>(base + g.q_off) + row * d, b.nq * d});
+                scatter.push_back({reinterpret_cast<const int32_t*>(base + g.oi_off) + row * g.k, b.out_idx,
+                                   b.nq * g.k});
+                scatter.push_back({reinterpret_cast<const int32_t*>(base + g.od_off) + row * g.k,
+                                   reinterpret_cast<int32_t*>(b.out_dist), b.nq * g.k});
+                most_g = std::max<int64_t>(most_g, b.nq * d);
+                most_s = std::max<int64_t>(most_s, b.nq * g.k);
+                row += b.nq;
+            }
+        }
+        if (!gather.empty()) {
+            MRPT_HIP_TRY(hipMemcpy(base + gather_off, gather.data(), gather.size() * sizeof(CopyJob),
+                                   hipMemcpyHostToDevice));
+            MRPT_HIP_TRY(hipMemcpy(base + scatter_off, scatter.data(), scatter.size() * sizeof(CopyJob),
+                                   hipMemcpyHostToDevice));
+        }
+
+        // record one chain: gather, routing, voting, search, scatter
+        hipStream_t st = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        bool capturing = false;
+        if (e == hipSuccess) {
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+            capturing = e == hipSuccess;
+        }
+        if (e == hipSuccess && !gather.empty())
+            e = launch_copy_jobs(reinterpret_cast<const CopyJob*>(base + gather_off), n_gather, most_g, st);
+        for (size_t ci = 0; ci < route_cls.size() && e == hipSuccess; ++ci)
+            e = launch_route_multi(rl[ci].form, rl[ci].rpw, rl[ci].qpl, rl[ci].max_d,
+                                   reinterpret_cast<const RouteItem*>(base + route_cls[ci].tab_off),
+                                   (int32_t)route_cls[ci].members.size(), rl[ci].blocks_p, rl[ci].blocks_r, st);
+        for (int32_t gi : route_alone) {
+            if (e != hipSuccess) break;
+            const Group& g = groups[gi];
+            const Workspace ws = call_ws(g);
+            e = launch_route(g.ix, call_Q(g), g.rows, ws.leaf, ws.pq, st, cfg);
+        }
+        for (size_t ci = 0; ci < vote_cls.size() && e == hipSuccess; ++ci) {
+            e = launch_vote_multi(vote_cls[ci].key, vl[ci].map_words, vl[ci].qcap,
+                                  reinterpret_cast<const VoteItem*>(base + vote_cls[ci].tab_off),
+                                  reinterpret_cast<const int32_t*>(base + vote_cls[ci].row_off), vote_cls[ci].rows, st);
+            for (int32_t gi : recount[ci]) {
+                if (e != hipSuccess) break;
+                const Group& g = groups[gi];
+                const Workspace ws = call_ws(g);
+                e = launch_vote_recount(g.ix, ws.leaf, g.rows, g.v, ws.s_ids, g.cap, ws.s_count, st);
+            }
+        }
+        for (int32_t gi : vote_alone) {
+            if (e != hipSuccess) break;
+            const Group& g = groups[gi];
+            const Workspace ws = call_ws(g);
+            e = launch_vote(g.ix, ws.leaf, g.rows, g.v, ws.s_ids, g.cap, ws.s_count, st, cfg);
+        }
+        for (size_t ci = 0; ci < search_cls.size() && e == hipSuccess; ++ci)
+            e = launch_search_multi((int32_t)(search_cls[ci].key >> 20), (int32_t)(search_cls[ci].key & 0xFFFFF),
+                                    reinterpret_cast<const SearchItem*>(base + search_cls[ci].tab_off),
+                                    (int32_t)search_cls[ci].members.size(), sl[ci], o.recheck_rel, st);
+        for (int32_t gi : search_alone) {
+            if (e != hipSuccess) break;
+            const Group& g = groups[gi];
+            const Workspace ws = call_ws(g);
+            if (o.precision == MRPT_FP32)
+                e = launch_dist_fp32(g.ix, call_Q(g), g.rows, ws.s_ids, g.cap, ws.s_count, g.k, call_idx(g),
+                                     call_dist(g), st);
+            else
+                e = launch_dist_prefilter(g.ix, o.precision == MRPT_FP8_RERANK ? 1 : 0, call_Q(g), g.rows, ws.s_ids,
+                                          g.cap, ws.s_count, g.k, o.rerank_factor, o.recheck_rel, call_idx(g),
+                                          call_dist(g), st);
+        }
+        if (e == hipSuccess && !scatter.empty())
+            e = launch_copy_jobs(reinterpret_cast<const CopyJob*>(base + scatter_off), n_scatter, most_s, st);
+        if (capturing) {
+            const hipError_t e2 = hipStreamEndCapture(st, &plan->graph);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+        if (st) (void)hipStreamDestroy(st);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MRPT_EDEVICE, "recording the plan: %s", hipGetErrorString(e));
+        }
+        *out = plan.release();
+        return MRPT_OK;
     }
 
     // groups dealt to branches, largest first, each to the least loaded

@@ -340,17 +340,15 @@ constexpr int kProjWaves = 8;
 constexpr int kProjChunk = (64 * 1024) / (kQStride * 4);   // 252 features: 64 KB of LDS
 
 template <int RPW, bool CHUNKED, int QPL>
-__global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
-                                                                     int32_t d, const int32_t* __restrict__ rowptr,
-                                                                     const int32_t* __restrict__ col,
-                                                                     const float* __restrict__ val, int32_t nrows,
-                                                                     float* __restrict__ Pq) {
+__device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_t nq, int32_t d,
+                                             const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                             const float* __restrict__ val, int32_t nrows, float* __restrict__ Pq,
+                                             float* proj_smem, const int64_t bx, const int32_t by) {
     static_assert(QPL == 1 || !CHUNKED, "two queries per lane only with the whole tile in LDS");
-    extern __shared__ float proj_smem[];   // [min(d, kProjChunk)][QPL][65]
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
-    const int64_t q0 = (int64_t)blockIdx.x * (kWave * QPL);
-    const int r0 = uniform((int)blockIdx.y * (kProjWaves * RPW) + w * RPW);
+    const int64_t q0 = bx * (kWave * QPL);
+    const int r0 = uniform(by * (kProjWaves * RPW) + w * RPW);
     int len[RPW];
     int colr[RPW];
     float valr[RPW];
@@ -461,19 +459,29 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
     }
 }
 
+template <int RPW, bool CHUNKED, int QPL>
+__global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
+                                                                     int32_t d, const int32_t* __restrict__ rowptr,
+                                                                     const int32_t* __restrict__ col,
+                                                                     const float* __restrict__ val, int32_t nrows,
+                                                                     float* __restrict__ Pq) {
+    extern __shared__ float proj_smem[];   // [min(d, kProjChunk)][QPL][65]
+    project_body<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, nrows, Pq, proj_smem, blockIdx.x, blockIdx.y);
+}
+
 template <int MAXL, bool SPLITS_LDS>
-__global__ __launch_bounds__(256) void route_pq_kernel(const float* __restrict__ Pq, int64_t nq,
-                                                       const float* __restrict__ splits, int32_t T, int32_t depth,
-                                                       int32_t q_per_block, int32_t* __restrict__ leaf) {
-    extern __shared__ float rsp[];          // split table of this block's tree
+__device__ __forceinline__ void route_pq_body(const float* __restrict__ Pq, int64_t nq,
+                                              const float* __restrict__ splits, int32_t T, int32_t depth,
+                                              int32_t q_per_block, int32_t* __restrict__ leaf, float* rsp,
+                                              const int64_t bx, const int32_t by) {
     const int nsplit = (1 << depth) - 1;
-    const int t = (int)blockIdx.y;
+    const int t = by;
     if constexpr (SPLITS_LDS) {
         stage_splits(splits, rsp, T, t, 1, nsplit);
         __syncthreads();
     }
     const float* tsp = splits + (int64_t)t * nsplit;
-    const int64_t qb = (int64_t)blockIdx.x * q_per_block;
+    const int64_t qb = bx * q_per_block;
     const int64_t qe = qb + q_per_block < nq ? qb + q_per_block : nq;
     for (int64_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
         float p[MAXL];
@@ -492,6 +500,51 @@ __global__ __launch_bounds__(256) void route_pq_kernel(const float* __restrict__
         }
         leaf[q * T + t] = node - nsplit;
     }
+}
+
+template <int MAXL, bool SPLITS_LDS>
+__global__ __launch_bounds__(256) void route_pq_kernel(const float* __restrict__ Pq, int64_t nq,
+                                                       const float* __restrict__ splits, int32_t T, int32_t depth,
+                                                       int32_t q_per_block, int32_t* __restrict__ leaf) {
+    extern __shared__ float rsp[];          // split table of this block's tree
+    route_pq_body<MAXL, SPLITS_LDS>(Pq, nq, splits, T, depth, q_per_block, leaf, rsp, blockIdx.x, blockIdx.y);
+}
+
+// the item of a multi-index launch that holds workgroup b (items ascending
+// by their first workgroup)
+__device__ __forceinline__ int32_t find_route_item(const RouteItem* __restrict__ items, int32_t nitems, int64_t b,
+                                                   bool second) {
+    int32_t lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if ((second ? items[mid].blk0_r : items[mid].blk0_p) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// projections of several query calls (indexes of one kernel form): workgroup
+// b is tile (x, y) of its item's own grid
+template <int RPW, bool CHUNKED, int QPL>
+__global__ __launch_bounds__(kProjWaves * kWave) void project_multi_kernel(const RouteItem* __restrict__ items,
+                                                                           int32_t nitems) {
+    extern __shared__ float proj_smem[];
+    const int32_t i = find_route_item(items, nitems, blockIdx.x, false);
+    const RouteItem& it = items[i];
+    const int64_t r = (int64_t)blockIdx.x - it.blk0_p;
+    project_body<RPW, CHUNKED, QPL>(it.Q, it.nq, it.d, it.rowptr, it.col, it.val, it.nrows, it.Pq, proj_smem,
+                                    r % it.nbx_p, (int32_t)(r / it.nbx_p));
+}
+
+template <int MAXL, bool SPLITS_LDS>
+__global__ __launch_bounds__(256) void route_pq_multi_kernel(const RouteItem* __restrict__ items, int32_t nitems,
+                                                             int32_t q_per_block) {
+    extern __shared__ float rsp[];
+    const int32_t i = find_route_item(items, nitems, blockIdx.x, true);
+    const RouteItem& it = items[i];
+    const int64_t r = (int64_t)blockIdx.x - it.blk0_r;
+    route_pq_body<MAXL, SPLITS_LDS>(it.Pq, it.nq, it.splits, it.T, it.depth, q_per_block, it.leaf, rsp,
+                                    r % it.nbx_r, (int32_t)(r / it.nbx_r));
 }
 
 }  // namespace
@@ -683,6 +736,114 @@ hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_
     else MRPT_ROUTE(24);
 #undef MRPT_ROUTE
 #undef MRPT_ROUTE_K
+    return hipGetLastError();
+}
+
+// Routing forms: 100 * projection class + split-walk class.  Projection
+// class 0: d <= 128 (two queries per lane in large launches), 1: the whole
+// tile in LDS, 2: chunked tiles.  Split-walk class (< 16): 4 * depth class +
+// 2 * (split table in LDS) (depth classes up to 8, 12, 16, 24 levels).
+constexpr int32_t encode_route_form(int pc, int dc, int spl) { return 100 * pc + 4 * dc + 2 * spl; }
+constexpr bool route_forms_decode() {
+    for (int pc = 0; pc < 3; ++pc)
+        for (int dc = 0; dc < 4; ++dc)
+            for (int spl = 0; spl < 2; ++spl) {
+                const int32_t f = encode_route_form(pc, dc, spl);
+                if (f / 100 != pc || (f % 100) / 4 != dc || ((f % 100) & 2) / 2 != spl || f % 100 >= 16) return false;
+            }
+    return true;
+}
+static_assert(route_forms_decode(), "every routing form decodes to its classes");
+
+int32_t route_form(const mrpt_index* ix) {
+    if (ix->max_row_nnz > kWave) return -1;
+    const int d = ix->d, depth = ix->depth;
+    const int pc = d <= kProjPairMaxD ? 0 : d <= kProjChunk ? 1 : 2;
+    const int dc = depth <= 8 ? 0 : depth <= 12 ? 1 : depth <= 16 ? 2 : 3;
+    const size_t sp_bytes = (((size_t)1 << depth) - 1) * 4;
+    const int spl = sp_bytes <= (size_t)std::min(lds_per_block_limit(), 64 * 1024) ? 1 : 0;
+    return encode_route_form(pc, dc, spl);
+}
+
+// the most levels of a routing form's split-walk class
+static int form_max_depth(int32_t form) {
+    const int dc = (form % 100) / 4;
+    return dc == 0 ? 8 : dc == 1 ? 12 : dc == 2 ? 16 : 24;
+}
+
+void route_shape(int32_t form, int64_t total_tiles, int32_t rows_per_wave, int32_t* rpw, int32_t* qpl) {
+    const int pc = form / 100;
+    const bool small = rows_per_wave == 4 || (rows_per_wave != kProjRows && total_tiles < 512);
+    *rpw = small ? 4 : kProjRows;
+    *qpl = (!small && pc == 0) ? 2 : 1;
+}
+
+bool route_form_holds(int32_t form, const mrpt_index* ix) {
+    return route_form(ix) == form && ix->depth <= form_max_depth(form);
+}
+
+RouteGrid route_grid(const mrpt_index* ix, int64_t nq, int32_t rpw, int32_t qpl) {
+    RouteGrid g;
+    g.rpw = rpw;
+    g.qpl = qpl;
+    const int nrows = ix->T * ix->depth;
+    g.nbx_p = (nq + kWave * qpl - 1) / (kWave * qpl);
+    g.nby_p = (nrows + kProjWaves * rpw - 1) / (kProjWaves * rpw);
+    const int q_per_block = 2048;
+    g.nbx_r = (nq + q_per_block - 1) / q_per_block;
+    g.nby_r = ix->T;
+    return g;
+}
+
+hipError_t launch_route_multi(int32_t form, int32_t rpw, int32_t qpl, int32_t max_d, const RouteItem* items,
+                              int32_t nitems, int64_t blocks_p, int64_t blocks_r, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    const int pc = form / 100, rc = form % 100;
+    if (pc > 2 || rc >= 16) return hipErrorInvalidValue;
+    const bool chunked = pc == 2;
+#define MRPT_PROJM(RPW, CH, QPL)                                                                              \
+    do {                                                                                                     \
+        const size_t lds = (size_t)std::min(max_d, kProjChunk) * kQStride * 4 * (QPL);                       \
+        (void)hipFuncSetAttribute((const void*)project_multi_kernel<RPW, CH, QPL>,                           \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                     \
+        hipLaunchKernelGGL((project_multi_kernel<RPW, CH, QPL>), dim3((unsigned)blocks_p),                   \
+                           dim3(kProjWaves * kWave), lds, s, items, nitems);                                 \
+    } while (0)
+    if (rpw == 4) {
+        if (chunked) MRPT_PROJM(4, true, 1);
+        else MRPT_PROJM(4, false, 1);
+    } else {
+        if (chunked) MRPT_PROJM(kProjRows, true, 1);
+        else if (qpl == 2) MRPT_PROJM(kProjRows, false, 2);
+        else MRPT_PROJM(kProjRows, false, 1);
+    }
+#undef MRPT_PROJM
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int dc = rc / 4;
+    const bool spl = (rc & 2) != 0;
+    // the largest split table of the class (its depth class bound)
+    const int maxdepth = form_max_depth(form);
+    const size_t lds = spl ? (((size_t)1 << maxdepth) - 1) * 4 : 0;
+    const int q_per_block = 2048;
+#define MRPT_RPQM(ML)                                                                                        \
+    do {                                                                                                     \
+        if (spl) {                                                                                           \
+            const size_t l = std::min(lds, (size_t)64 * 1024);                                               \
+            (void)hipFuncSetAttribute((const void*)route_pq_multi_kernel<ML, true>,                          \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)l);                   \
+            hipLaunchKernelGGL((route_pq_multi_kernel<ML, true>), dim3((unsigned)blocks_r), dim3(256), l, s,   \
+                               items, nitems, q_per_block);                                                  \
+        } else {                                                                                             \
+            hipLaunchKernelGGL((route_pq_multi_kernel<ML, false>), dim3((unsigned)blocks_r), dim3(256), 0, s,  \
+                               items, nitems, q_per_block);                                                  \
+        }                                                                                                    \
+    } while (0)
+    if (dc == 0) MRPT_RPQM(8);
+    else if (dc == 1) MRPT_RPQM(12);
+    else if (dc == 2) MRPT_RPQM(16);
+    else MRPT_RPQM(24);
+#undef MRPT_RPQM
     return hipGetLastError();
 }
 

@@ -145,12 +145,11 @@ __device__ void block_select(const uint32_t* key, const int32_t* id, int tot, in
 
 
 template <int G, int NV, int R>
-__global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict__ X, int32_t d,
-                                                        const float* __restrict__ Q,
-                                                        const int32_t* __restrict__ s_ids, int64_t cap,
-                                                        const int32_t* __restrict__ s_count, int32_t k,
-                                                        int32_t* __restrict__ out_idx,
-                                                        float* __restrict__ out_dist) {
+__device__ __forceinline__ void dist_fp32_body(const float* __restrict__ X, int32_t d, const float* __restrict__ Q,
+                                               const int32_t* __restrict__ s_ids, int64_t cap,
+                                               const int32_t* __restrict__ s_count, int32_t k,
+                                               int32_t* __restrict__ out_idx, float* __restrict__ out_dist,
+                                               const int64_t q) {
     constexpr int GPW = kWave / G;
     constexpr int U = 8 / NV;
     __shared__ float md[kDistWaves][kWave * R];
@@ -158,7 +157,6 @@ __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict_
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
     const int g = lane / G, gl = lane - g * G;
-    const int64_t q = blockIdx.x;
     const int ns = uniform(s_count[q]);
     const int32_t* S = s_ids + q * cap;
     const int nvec = d >> 2;
@@ -256,6 +254,40 @@ __global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict_
     }
 }
 
+template <int G, int NV, int R>
+__global__ __launch_bounds__(256) void dist_fp32_kernel(const float* __restrict__ X, int32_t d,
+                                                        const float* __restrict__ Q,
+                                                        const int32_t* __restrict__ s_ids, int64_t cap,
+                                                        const int32_t* __restrict__ s_count, int32_t k,
+                                                        int32_t* __restrict__ out_idx,
+                                                        float* __restrict__ out_dist) {
+    dist_fp32_body<G, NV, R>(X, d, Q, s_ids, cap, s_count, k, out_idx, out_dist, blockIdx.x);
+}
+
+// the item of a multi-index launch that holds workgroup b: items are in
+// ascending order of their first workgroup (binary search, scalar loads)
+__device__ __forceinline__ int32_t find_item(const SearchItem* __restrict__ items, int32_t nitems, int64_t b) {
+    int32_t lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (items[mid].row0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// one launch over the queries of several query calls of the same kernel form
+// (indexes of one d, k in one register class): workgroup b serves query
+// b - row0 of the item that holds it
+template <int G, int NV, int R>
+__global__ __launch_bounds__(256) void dist_fp32_multi_kernel(const SearchItem* __restrict__ items, int32_t nitems,
+                                                              int32_t d) {
+    const int32_t i = find_item(items, nitems, blockIdx.x);
+    const SearchItem& it = items[i];
+    dist_fp32_body<G, NV, R>(it.X, d, it.Q, it.s_ids, it.cap, it.s_count, it.k, it.out_idx, it.out_dist,
+                             (int64_t)blockIdx.x - it.row0);
+}
+
 // generic fallback (any d): scalar loads, one wave per candidate row
 template <int R>
 __global__ __launch_bounds__(256) void dist_fp32_generic_kernel(const float* __restrict__ X, int32_t d,
@@ -338,7 +370,7 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
                                                     const int32_t* __restrict__ s_ids, int64_t cap,
                                                     const int32_t* __restrict__ s_count, int32_t k, int32_t kp,
                                                     float recheck_rel, int32_t* __restrict__ out_idx,
-                                                    float* __restrict__ out_dist,
+                                                    float* __restrict__ out_dist, const int64_t q,
                                                     int32_t* __restrict__ keep_out = nullptr) {
     constexpr int GPW = kWave / GB;
     constexpr int U = 8 / NVB;
@@ -368,7 +400,6 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
     const int g = lane / GB, gl = lane - g * GB;
-    const int64_t q = blockIdx.x;
     const int ns = uniform(s_count[q]);
     const int32_t* S = s_ids + q * cap;
     const int nv8 = d / EPU;                       // 16-byte loads per row
@@ -655,7 +686,7 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
         const float *__restrict__ Q, const int32_t *__restrict__ s_ids, int64_t cap,                           \
         const int32_t *__restrict__ s_count, int32_t k, int32_t kp, float recheck_rel,                         \
         int32_t *__restrict__ out_idx, float *__restrict__ out_dist
-#define MRPT_PF_ARGS X, Xq, sn8, d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist
+#define MRPT_PF_ARGS X, Xq, sn8, d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist, blockIdx.x
 
 template <int FMT, int GB, int NVB, int G2, int NV2>
 __global__ __launch_bounds__(256) void dist_prefilter_kernel(MRPT_PF_PARAMS) {
@@ -675,6 +706,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void d
 template <int FMT, int GB, int NVB, int G2, int NV2>
 __global__ __launch_bounds__(256) void dist_prefilter_keep_kernel(MRPT_PF_PARAMS, int32_t* __restrict__ keep_out) {
     dist_prefilter_body<FMT, GB, NVB, G2, NV2, true>(MRPT_PF_ARGS, keep_out);
+}
+
+// one launch over the queries of several query calls of the same kernel form
+// (indexes of one d and arm): workgroup b serves query b - row0 of its item
+template <int FMT, int GB, int NVB, int G2, int NV2>
+__global__ __launch_bounds__(256) void dist_prefilter_multi_kernel(const SearchItem* __restrict__ items,
+                                                                   int32_t nitems, int32_t d, float recheck_rel) {
+    const int32_t i = find_item(items, nitems, blockIdx.x);
+    const SearchItem& it = items[i];
+    dist_prefilter_body<FMT, GB, NVB, G2, NV2>(it.X, it.Xq, it.sn8, d, it.Q, it.s_ids, it.cap, it.s_count, it.k,
+                                               it.kp, recheck_rel, it.out_idx, it.out_dist,
+                                               (int64_t)blockIdx.x - it.row0);
+}
+
+template <int FMT, int GB, int NVB, int G2, int NV2>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void dist_prefilter_multi_w7_kernel(
+    const SearchItem* __restrict__ items, int32_t nitems, int32_t d, float recheck_rel) {
+    const int32_t i = find_item(items, nitems, blockIdx.x);
+    const SearchItem& it = items[i];
+    dist_prefilter_body<FMT, GB, NVB, G2, NV2>(it.X, it.Xq, it.sn8, d, it.Q, it.s_ids, it.cap, it.s_count, it.k,
+                                               it.kp, recheck_rel, it.out_idx, it.out_dist,
+                                               (int64_t)blockIdx.x - it.row0);
 }
 
 #undef MRPT_PF_ARGS
@@ -773,6 +826,87 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
     }
 #undef MRPT_PF_R
 #undef MRPT_PF
+    return hipGetLastError();
+}
+
+// Search forms: fp32 vector kernels 100 + 10 * layout + register class,
+// prefilter kernels 200 (bf16) / 300 (fp8) + layout; the layouts follow the
+// single-call launchers above.
+namespace {
+int32_t fp32_layout(int d) {
+    const int nvec = d / 4;
+    return nvec <= 16 ? 0 : nvec <= 32 ? 1 : nvec <= 64 ? 2 : nvec <= 128 ? 3 : 4;
+}
+int32_t r_class(int k) { return k <= 64 ? 0 : k <= 128 ? 1 : k <= 256 ? 2 : k <= 512 ? 3 : 4; }
+int32_t pf_layout(int fp8, int d) {
+    if (!fp8) {
+        const int nv8 = d / 8;
+        return nv8 <= 16 ? 0 : nv8 <= 32 ? 1 : nv8 <= 64 ? 2 : 3;
+    }
+    const int nvec = d / 4;
+    return nvec <= 16 ? 0 : nvec <= 32 ? 1 : nvec <= 64 ? 2 : nvec <= 128 ? 3 : 4;
+}
+}  // namespace
+
+int32_t search_form(const mrpt_index* ix, int32_t precision, int32_t k, const float* Q) {
+    const int d = ix->d;
+    if (precision == MRPT_FP32) {
+        const bool vec = (d % 4) == 0 && d <= 1024 && ((uintptr_t)Q % 16) == 0 && ((uintptr_t)ix->X % 16) == 0;
+        if (!vec) return -1;
+        return 100 + 10 * fp32_layout(d) + r_class(k);
+    }
+    return (precision == MRPT_FP8_RERANK ? 300 : 200) + pf_layout(precision == MRPT_FP8_RERANK, d);
+}
+
+hipError_t launch_search_multi(int32_t form, int32_t d, const SearchItem* items, int32_t nitems, int64_t rows,
+                               float recheck_rel, hipStream_t s) {
+    if (rows == 0 || nitems == 0) return hipSuccess;
+    dim3 grid((unsigned)rows), block(256);
+#define MRPT_D32(G, NV, RR) \
+    hipLaunchKernelGGL((dist_fp32_multi_kernel<G, NV, RR>), grid, block, 0, s, items, nitems, d)
+#define MRPT_D32_R(G, NV)                     \
+    switch (form % 10) {                      \
+        case 0: MRPT_D32(G, NV, 1); break;    \
+        case 1: MRPT_D32(G, NV, 2); break;    \
+        case 2: MRPT_D32(G, NV, 4); break;    \
+        case 3: MRPT_D32(G, NV, 8); break;    \
+        default: MRPT_D32(G, NV, 16); break;  \
+    }
+#define MRPT_PFM(F, GB, NVB, G2, NV2)                                                                           \
+    hipLaunchKernelGGL((dist_prefilter_multi_kernel<F, GB, NVB, G2, NV2>), grid, block, 0, s, items, nitems, d, \
+                       recheck_rel)
+    if (form >= 100 && form < 200) {
+        switch ((form - 100) / 10) {
+            case 0: MRPT_D32_R(16, 1); break;
+            case 1: MRPT_D32_R(32, 1); break;
+            case 2: MRPT_D32_R(64, 1); break;
+            case 3: MRPT_D32_R(64, 2); break;
+            default: MRPT_D32_R(64, 4); break;
+        }
+    } else if (form >= 200 && form < 300) {
+        switch (form - 200) {
+            case 0:
+                hipLaunchKernelGGL((dist_prefilter_multi_w7_kernel<kFmtBf16, 16, 1, 32, 1>), grid, block, 0, s,
+                                   items, nitems, d, recheck_rel);
+                break;
+            case 1: MRPT_PFM(kFmtBf16, 32, 1, 64, 1); break;
+            case 2: MRPT_PFM(kFmtBf16, 64, 1, 64, 2); break;
+            default: MRPT_PFM(kFmtBf16, 64, 2, 64, 4); break;
+        }
+    } else if (form >= 300 && form < 400) {
+        switch (form - 300) {
+            case 0: MRPT_PFM(kFmtFp8, 8, 1, 16, 1); break;
+            case 1: MRPT_PFM(kFmtFp8, 8, 1, 32, 1); break;
+            case 2: MRPT_PFM(kFmtFp8, 16, 1, 64, 1); break;
+            case 3: MRPT_PFM(kFmtFp8, 32, 1, 64, 2); break;
+            default: MRPT_PFM(kFmtFp8, 64, 1, 64, 4); break;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef MRPT_PFM
+#undef MRPT_D32_R
+#undef MRPT_D32
     return hipGetLastError();
 }
 

@@ -263,9 +263,9 @@ __global__ void vote_dir_build_kernel(const int32_t* __restrict__ perm, const in
 // round-robin over the 16 waves: slot s of wave w is window w + 16 s.  Every
 // slot issues one load per lane with no branch around it (so the compiler
 // can count the loads in flight): a lane beyond its leaf, or a slot beyond
-// the last tree, reads the padding entry n + lane of perm row 0, which holds
-// that value; such ids are never queued or elected, and their map bits lie
-// in spare words past the ids.  Loads address perm by a 32-bit byte offset
+// the last tree, reads the padding entry n + 32 lane of perm row 0, which
+// holds that value; such ids are never queued or elected, and their map bits
+// lie in spare words past the ids, a different word for every lane.  Loads address perm by a 32-bit byte offset
 // from its base.  Two queries are counted per loop turn, so the windows in
 // flight and the windows counted swap register arrays instead of moving.
 constexpr int kMapBatch = 5;         // slots whose map updates are issued together
@@ -325,23 +325,24 @@ __device__ __forceinline__ void append_batch(const uint32_t (&ob)[NB], const int
 }
 
 // Per-slot window descriptors of wave w, one slot per lane (lanes >= S
-// unused): row = tree * ld + 64 * part (-1 past the last tree) and
-// tp = tree | 64 * part << 8.  Computed once per kernel.
-__device__ __forceinline__ void slot_table(int w, int T, int wpl, int64_t ld, int& row, int& tp) {
+// unused): part = 64-id part of the window in its leaf (-1 past the last
+// tree) and tp = tree | 64 * part << 8.  Computed once per kernel.
+__device__ __forceinline__ void slot_table(int w, int T, int wpl, int& part64, int& tp) {
     const int u = w + kVoteWaves * lane_id();
     const int t = u / wpl, part = u - t * wpl;
-    row = t < T ? (int)((int64_t)t * ld) + part * kWave : -1;
+    part64 = t < T ? part * kWave : -1;
     tp = t < T ? (t | (part * kWave) << 8) : 0;
 }
 
 // the windows of one query, lane s holding slot s's: first = perm index of
-// its first id, avail = ids in it (0 past the last tree).  One LDS read of the
-// query's leaf positions per wave; the slots read these back with readlane.
-__device__ __forceinline__ void slot_windows(const int2* __restrict__ tpos, int slot_row, int slot_tp, int& first,
+// its first id, avail = ids in it (0 past the last tree).  The leaf positions
+// hold each tree's leaf as (perm index of its first id, length).  One LDS
+// read of them per wave; the slots read these back with readlane.
+__device__ __forceinline__ void slot_windows(const int2* __restrict__ tpos, int part64, int slot_tp, int& first,
                                              int& avail) {
     const int2 bl = tpos[slot_tp & 255];
-    first = slot_row + bl.x;
-    avail = slot_row < 0 ? 0 : bl.y - (slot_tp >> 8);
+    first = part64 + bl.x;
+    avail = part64 < 0 ? 0 : bl.y - (slot_tp >> 8);
 }
 
 template <int S>
@@ -501,14 +502,17 @@ __device__ __forceinline__ void rerun(uint32_t* map, int32_t* queue, int qn, boo
 
 // LDS: map [map_words] | queue [qcap] | leaf positions [kPosBufs][kMaxT]
 //      (int2) | qfill, nsel, 2 unused | kWave spare words
-template <int S, bool QUEUE>
-__global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __restrict__ leaf,
-                                                              const int32_t* __restrict__ perm,
-                                                              const int32_t* __restrict__ off, int64_t n,
-                                                              int64_t ld, int32_t T, int32_t wpl, int32_t v,
-                                                              int64_t nq, int32_t map_words, int32_t qcap,
-                                                              int32_t* __restrict__ s_ids, int64_t cap,
-                                                              int32_t* __restrict__ s_count) {
+//
+// The body serves one query call (MULTI false: `one` describes it, rows are
+// its queries) or several calls of one geometry (MULTI true: equal T and
+// windows per leaf; row r is query r - row0 of item row_item[r], and the map
+// and queue are laid out for the largest index).  Every row's item gives its
+// index arrays, n, v and outputs; the map is clear again after every query
+// (each query clears the words its index's ids use).
+template <int S, bool QUEUE, bool MULTI>
+__device__ __forceinline__ void vote_map_body(const VoteItem& one, const VoteItem* __restrict__ items,
+                                              const int32_t* __restrict__ row_item, int64_t nrows, int32_t T,
+                                              int32_t wpl, int32_t map_words, int32_t qcap) {
     extern __shared__ __align__(16) uint32_t map_smem[];
     uint32_t* map = map_smem;
     int32_t* queue = reinterpret_cast<int32_t*>(map_smem + map_words);
@@ -519,17 +523,31 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     int* spare = flags + 4;   // kWave words, targets of the reservations' idle lanes
     const int tid = (int)threadIdx.x;
     const int w = uniform(tid >> 6);
-    const int clear_vec = map_words >> 2;   // uint4 words of the map
-    const int32_t n32 = (int32_t)n;
-    const int32_t cap32 = (int32_t)std::min<int64_t>(cap, INT32_MAX);
     const int64_t G = gridDim.x;
     int64_t q = blockIdx.x;
-    if (q >= nq) return;
-    int slot_row, slot_tp;
-    slot_table(w, T, wpl, ld, slot_row, slot_tp);
+    if (q >= nrows) return;
+    // the call that row r belongs to (rows past the last clamp to the last
+    // row: their loads stay in range and their values are never used)
+    auto item = [&](int64_t r) -> const VoteItem& {
+        if constexpr (MULTI) return items[row_item[r < nrows ? r : nrows - 1]];
+        else return one;
+    };
+    int part64, slot_tp;
+    slot_table(w, T, wpl, part64, slot_tp);
 
-    for (int i = tid; i < clear_vec; i += kVoteBlock)
+    for (int i = tid; i < (map_words >> 2); i += kVoteBlock)
         reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
+    // leaf position of tree tid in the query of row r (tid < T): perm index
+    // of the leaf's first id, and its length
+    auto position = [&](int64_t r, int L) -> int2 {
+        const VoteItem& it = item(r);
+        const int b = it.off[L];
+        return make_int2((int)((int64_t)tid * it.ld) + b, it.off[L + 1] - b);
+    };
+    auto leaf_of = [&](int64_t r) -> int {
+        const VoteItem& it = item(r);
+        return it.leaf[(r - it.row0) * T + tid];
+    };
     int Lnext = 0;                            // leaf numbers of the query two ahead
     if (tid < T) {
         // every buffer holds in-range positions (empty ones for absent
@@ -538,24 +556,22 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         for (int k = 0; k < kPosBufs; ++k) {
             const int64_t qq = q + k * G;
             int2 p = make_int2(0, 0);
-            if (k < 2 && qq < nq) {
-                const int L = leaf[qq * T + tid];
-                const int b = off[L];
-                p = make_int2(b, off[L + 1] - b);
-            }
+            if (k < 2 && qq < nrows) p = position(qq, leaf_of(qq));
             tpos[k][tid] = p;
         }
-        if (q + 2 * G < nq) Lnext = leaf[(q + 2 * G) * T + tid];
+        if (q + 2 * G < nrows) Lnext = leaf_of(q + 2 * G);
     }
     if (tid == 0) { *qfill = 0; *nsel = 0; }
     __syncthreads();
 
-    const uint32_t pad4 = (uint32_t)(n32 + lane_id()) * 4u;
+    // each lane's padding id in a map word of its own (no bank conflicts)
+    auto pad4_of = [&](const VoteItem& it) -> uint32_t { return (uint32_t)(it.n + 32 * lane_id()) * 4u; };
     int32_t ids[S], nid[S];
     {
         int first_v, avail_v;
-        slot_windows(tpos[0], slot_row, slot_tp, first_v, avail_v);
-        load_windows<S>(ids, perm, pad4, first_v, avail_v);
+        slot_windows(tpos[0], part64, slot_tp, first_v, avail_v);
+        const VoteItem& it = item(q);
+        load_windows<S>(ids, it.perm, pad4_of(it), first_v, avail_v);
     }
     int cur = 0;
     // one query: count the windows in `win`, load the next query's into
@@ -568,15 +584,21 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         // loads stay in range and their values are never used)
         {
             int first_v, avail_v;
-            slot_windows(tpos[b1], slot_row, slot_tp, first_v, avail_v);
-            load_windows<S>(nxt, perm, pad4, first_v, avail_v);
+            slot_windows(tpos[b1], part64, slot_tp, first_v, avail_v);
+            const VoteItem& it1 = item(q1);
+            load_windows<S>(nxt, it1.perm, pad4_of(it1), first_v, avail_v);
         }
-        int pb = 0, pe = 0, Lnn = 0;
+        int2 pnext = make_int2(0, 0);
+        int Lnn = 0;
         if (tid < T) {
-            if (q2 < nq) { pb = off[Lnext]; pe = off[Lnext + 1]; }
-            if (q3 < nq) Lnn = leaf[q3 * T + tid];
+            if (q2 < nrows) pnext = position(q2, Lnext);
+            if (q3 < nrows) Lnn = leaf_of(q3);
         }
-        int32_t* out = s_ids + q * cap;
+        const VoteItem& it = item(q);
+        const int32_t n32 = it.n;
+        const int64_t lq = q - it.row0;
+        const int32_t cap32 = (int32_t)std::min<int64_t>(it.cap, INT32_MAX);
+        int32_t* out = it.s_ids + lq * it.cap;
 
         // the windows through the map: first occurrences (v = 1: S) or repeats
         // (a batch past slot S - 1 is cut short: its conditions are
@@ -603,8 +625,8 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
         lds_barrier();                        // the map pass of q is complete
         if constexpr (QUEUE) {
             const int qn = min(*qfill, qcap);
-            for (int level = 2; level <= v; ++level) {
-                const bool last = level == v;
+            for (int level = 2; level <= it.v; ++level) {
+                const bool last = level == it.v;
                 // runs 2, 4, ...: the bits of the queued ids start set
                 if ((level & 1) == 0) rerun<true>(map, queue, qn, last, w, n32, nsel, spare, out, (uint32_t)cap32);
                 else rerun<false>(map, queue, qn, last, w, n32, nsel, spare, out, (uint32_t)cap32);
@@ -612,17 +634,17 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
             }
         }
         // buffer b2 last served the query before q, whose windows are loaded
-        if (tid < T && q2 < nq) tpos[b2][tid] = make_int2(pb, pe - pb);
+        if (tid < T && q2 < nrows) tpos[b2][tid] = pnext;
         if (tid == 0) {
             // a queue that overflowed (more reserved than qcap) marks the query
-            s_count[q] = *qfill > qcap ? -1 : (*nsel < cap ? *nsel : (int32_t)cap);
+            it.s_count[lq] = *qfill > qcap ? -1 : (*nsel < it.cap ? *nsel : (int32_t)it.cap);
             *qfill = 0;
             *nsel = 0;
         }
-        for (int i = tid; i < clear_vec; i += kVoteBlock)
+        for (int i = tid; i < (it.map_words >> 2); i += kVoteBlock)
             reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
         lds_barrier();
-        if (q1 >= nq) return false;
+        if (q1 >= nrows) return false;
         Lnext = Lnn;
         cur = b1;
         q = q1;
@@ -630,6 +652,21 @@ __global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(const int32_t* __r
     };
     while (step(ids, nid) && step(nid, ids)) {
     }
+}
+
+template <int S, bool QUEUE>
+__global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(VoteItem one, int64_t nq, int32_t T, int32_t wpl,
+                                                              int32_t map_words, int32_t qcap) {
+    vote_map_body<S, QUEUE, false>(one, nullptr, nullptr, nq, T, wpl, map_words, qcap);
+}
+
+// several query calls of one geometry in one persistent launch
+template <int S, bool QUEUE>
+__global__ __launch_bounds__(kVoteBlock) void vote_map_multi_kernel(const VoteItem* __restrict__ items,
+                                                                    const int32_t* __restrict__ row_item,
+                                                                    int64_t nrows, int32_t T, int32_t wpl,
+                                                                    int32_t map_words, int32_t qcap) {
+    vote_map_body<S, QUEUE, true>(VoteItem(), items, row_item, nrows, T, wpl, map_words, qcap);
 }
 
 // debug: F(x; q) of every listed candidate, by binary search of x in each of
@@ -679,7 +716,7 @@ int vote_kernel_override() {
 size_t vote_lds_limit() { return (size_t)std::min(lds_per_block_limit(), 160 * 1024); }
 
 // single-pass geometry: map words (ids 0 .. n + 2047: real ids, then the
-// empty lanes' ids n + lane), the repeat queue in what LDS has left
+// empty lanes' ids n + 32 lane), the repeat queue in what LDS has left
 struct SingleGeometry {
     bool ok;
     int32_t wpl;
@@ -720,29 +757,42 @@ int device_cus() {
 }
 
 template <int B>
+// recount_only: no single-pass launch; the multi-pass kernel counts again
+// the queries marked as overflowed (count -1) by an earlier single-pass one
 hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
-                         int64_t cap, int32_t* s_count, hipStream_t s, const LaunchCfg& cfg) {
+                         int64_t cap, int32_t* s_count, hipStream_t s, const LaunchCfg& cfg,
+                         bool recount_only = false) {
     constexpr int per = 32 / B;
     const size_t limit = vote_lds_limit();
     // a pinned choice first (multi-pass: with the directory when there is
     // one), else the environment override, else automatic
-    const int mode = cfg.vote_kernel == 2 ? 0 : cfg.vote_kernel == 1 ? -1 : vote_kernel_override();
+    const int mode = recount_only ? -1 : cfg.vote_kernel == 2 ? 0 : cfg.vote_kernel == 1 ? -1 : vote_kernel_override();
     const bool queued = v >= 2;   // repeats are queued and rerun
     const SingleGeometry sg = single_geometry(ix, queued);
-    const bool single = mode < 0 && sg.ok;
-    if (single) {
+    const bool single = recount_only || (mode < 0 && sg.ok);
+    if (single && !recount_only) {
         const int wpl = sg.wpl;
         const int64_t slots = sg.slots, map_words = sg.map_words, qcap = sg.qcap;
         const size_t lds = sg.lds;
         const int64_t grid = std::min<int64_t>(nq, device_cus());
+        VoteItem one;
+        one.leaf = leaf;
+        one.perm = ix->perm;
+        one.off = ix->off;
+        one.s_ids = s_ids;
+        one.s_count = s_count;
+        one.cap = cap;
+        one.ld = ix->perm_ld;
+        one.row0 = 0;
+        one.n = (int32_t)ix->n;
+        one.v = v;
+        one.map_words = (int32_t)map_words;
 #define MRPT_MAP(SS, H)                                                                                          \
     do {                                                                                                         \
         (void)hipFuncSetAttribute((const void*)vote_map_kernel<SS, H>,                                           \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                         \
-        hipLaunchKernelGGL((vote_map_kernel<SS, H>), dim3((unsigned)grid), dim3(kVoteBlock), lds, s, leaf,       \
-                           ix->perm, ix->off, ix->n, ix->perm_ld, ix->T, wpl, v, nq, (int32_t)map_words,         \
-                           (int32_t)qcap,                                                                        \
-                           s_ids, cap, s_count);                                                                 \
+        hipLaunchKernelGGL((vote_map_kernel<SS, H>), dim3((unsigned)grid), dim3(kVoteBlock), lds, s, one, nq,     \
+                           ix->T, wpl, (int32_t)map_words, (int32_t)qcap);                                       \
     } while (0)
         // the smallest instantiated slot count that holds the windows: every
         // slot costs its loads and map updates even when it is empty
@@ -804,7 +854,75 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     return hipGetLastError();
 }
 
+// the slot counts the single-pass kernel is instantiated for
+constexpr int kSlotClasses[] = {4, 8, 13, 16, 20, 25, 28, kVoteSlots};
+
 }  // namespace
+
+int64_t vote_form(const mrpt_index* ix, int32_t v, const LaunchCfg& cfg) {
+    const int mode = cfg.vote_kernel == 2 ? 0 : cfg.vote_kernel == 1 ? -1 : vote_kernel_override();
+    const bool queued = v >= 2;
+    const SingleGeometry sg = single_geometry(ix, queued);
+    if (mode >= 0 || !sg.ok) return -1;
+    int c = 0;
+    while (kSlotClasses[c] < sg.slots) ++c;
+    return (((int64_t)c * 2 + (queued ? 1 : 0)) * 256 + ix->T) * 65536 + sg.wpl;
+}
+
+int32_t vote_map_words(const mrpt_index* ix) { return (int32_t)single_geometry(ix, false).map_words; }
+
+int64_t vote_most_queued(const mrpt_index* ix) {
+    return (int64_t)ix->T * ix->max_leaf - ix->n / ((int64_t)1 << ix->depth);
+}
+
+int64_t vote_multi_qcap(int32_t map_words, int64_t most_occurrences) {
+    const int64_t room = ((int64_t)vote_lds_limit() - (int64_t)kMapTail - (int64_t)map_words * 4) / 4;
+    int64_t qcap = std::min<int64_t>(room, most_occurrences) / 4 * 4;
+    const char* cap_env = std::getenv("MRPT_VOTE_QUEUE_CAP");
+    if (cap_env && *cap_env && std::atoll(cap_env) > 0) qcap = std::min<int64_t>(qcap, std::atoll(cap_env) / 4 * 4);
+    return qcap >= 1024 ? qcap : -1;
+}
+
+hipError_t launch_vote_multi(int64_t form, int32_t map_words, int64_t qcap, const VoteItem* items,
+                             const int32_t* row_item, int64_t nrows, hipStream_t s) {
+    if (nrows == 0) return hipSuccess;
+    const int32_t wpl = (int32_t)(form % 65536);
+    const int32_t T = (int32_t)((form / 65536) % 256);
+    const bool queued = ((form / 65536 / 256) & 1) != 0;
+    const int c = (int)(form / 65536 / 256 / 2);
+    const size_t lds = (size_t)(map_words + qcap) * 4 + kMapTail;
+    const int64_t grid = std::min<int64_t>(nrows, device_cus());
+#define MRPT_MAPM(SS, H)                                                                                     \
+    do {                                                                                                     \
+        (void)hipFuncSetAttribute((const void*)vote_map_multi_kernel<SS, H>,                                 \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                     \
+        hipLaunchKernelGGL((vote_map_multi_kernel<SS, H>), dim3((unsigned)grid), dim3(kVoteBlock), lds, s,     \
+                           items, row_item, nrows, T, wpl, map_words, (int32_t)qcap);                        \
+    } while (0)
+#define MRPT_MAPM_C(CI, SS)                       \
+    case CI:                                      \
+        if (queued) MRPT_MAPM(SS, true);          \
+        else MRPT_MAPM(SS, false);                \
+        break;
+    switch (c) {
+        MRPT_MAPM_C(0, 4) MRPT_MAPM_C(1, 8) MRPT_MAPM_C(2, 13) MRPT_MAPM_C(3, 16) MRPT_MAPM_C(4, 20)
+        MRPT_MAPM_C(5, 25) MRPT_MAPM_C(6, 28) default:
+            if (queued) MRPT_MAPM(kVoteSlots, true);
+            else MRPT_MAPM(kVoteSlots, false);
+    }
+#undef MRPT_MAPM_C
+#undef MRPT_MAPM
+    return hipGetLastError();
+}
+
+hipError_t launch_vote_recount(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
+                               int64_t cap, int32_t* s_count, hipStream_t s) {
+    if (nq == 0 || v == 1) return hipSuccess;
+    const LaunchCfg cfg;
+    if (v <= 3) return launch_vote_b<2>(ix, leaf, nq, v, s_ids, cap, s_count, s, cfg, true);
+    if (v <= 15) return launch_vote_b<4>(ix, leaf, nq, v, s_ids, cap, s_count, s, cfg, true);
+    return launch_vote_b<8>(ix, leaf, nq, v, s_ids, cap, s_count, s, cfg, true);
+}
 
 hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
                        int64_t cap, int32_t* s_count, hipStream_t s, const LaunchCfg& cfg) {

@@ -166,6 +166,97 @@ hipError_t launch_dist_prefilter(const mrpt_index* ix, int fp8, const float* Q, 
                                  int64_t cap, const int32_t* s_count, int32_t k, int32_t rerank, float recheck_rel,
                                  int32_t* out_idx, float* out_dist, hipStream_t s, int32_t* keep_out = nullptr);
 hipError_t launch_copy_counts(const int32_t* src, int64_t nq, int32_t* dst, hipStream_t s);
+
+// ---------------------------------------------------------------- multi-index launches
+// One launch of a stage over the queries of several query calls (a query
+// plan's groups) whose kernel form is the same: the calls are the items of a
+// device table, in ascending order of their first workgroup (row0).
+
+// exact search: one workgroup per query
+struct SearchItem {
+    const float* X;              // the index's float32 rows
+    const uint8_t* Xq;           // its bfloat16 (or fp8) rows, prefilter arms
+    const float2* sn8;           // its fp8 scales and norms, fp8 arm
+    const float* Q;              // the call's queries
+    const int32_t* s_ids;        // its candidate lists (cap per query)
+    const int32_t* s_count;      // its |S| per query
+    int32_t* out_idx;
+    float* out_dist;
+    int64_t cap;
+    int64_t row0;                // first workgroup of the call
+    int32_t k, kp;               // kp = rerank_factor * k (prefilter arms)
+};
+// voting, single-pass map kernel: one item per call (also the single-call
+// kernel's argument)
+struct VoteItem {
+    const int32_t* leaf;         // the call's leaf numbers (nq x T)
+    const int32_t* perm;         // its index's leaf lists
+    const int32_t* off;          // its leaf offsets
+    int32_t* s_ids;              // candidate lists (cap per query)
+    int32_t* s_count;            // |S| per query (-1: repeat queue overflowed)
+    int64_t cap, ld;             // candidate cap; perm row length
+    int64_t row0;                // first row of the call in a multi-index launch
+    int32_t n, v;
+    int32_t map_words;           // map words its ids use (n + 2048 padding ids)
+    int32_t pad_;
+};
+
+// the single-pass vote form of a call (equal forms share a launch: slot
+// class, queueing, T, windows per leaf), -1 when the call needs the
+// multi-pass kernel; map words of an index; the most repeats one query can
+// queue; the queue capacity of a multi-index launch whose map holds
+// map_words (-1 when too small); the launch itself (rows whose queue
+// overflows get count -1, counted again by launch_vote_recount)
+int64_t vote_form(const mrpt_index* ix, int32_t v, const LaunchCfg& cfg);
+int32_t vote_map_words(const mrpt_index* ix);
+int64_t vote_most_queued(const mrpt_index* ix);
+int64_t vote_multi_qcap(int32_t map_words, int64_t most_occurrences);
+hipError_t launch_vote_multi(int64_t form, int32_t map_words, int64_t qcap, const VoteItem* items,
+                             const int32_t* row_item, int64_t nrows, hipStream_t s);
+hipError_t launch_vote_recount(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
+                               int64_t cap, int32_t* s_count, hipStream_t s);
+
+// routing (projection kernel, then the split walk): one item per call, the
+// workgroups of its two grids flattened (x fastest)
+struct RouteItem {
+    const float* Q;              // the call's queries
+    const int32_t* rowptr;       // its index's projection vectors (CSR)
+    const int32_t* col;
+    const float* val;
+    const float* splits;         // its split tables
+    float* Pq;                   // projections workspace (nrows x nq)
+    int32_t* leaf;               // leaf numbers (nq x T)
+    int64_t nq;
+    int64_t blk0_p, blk0_r;      // first workgroup in the projection / split-walk launch
+    int64_t nbx_p, nbx_r;        // workgroups along the queries in each grid
+    int32_t d, nrows, T, depth;
+};
+// the routing form of a call's index (equal forms can share the two
+// launches), -1 without a multi-index form (vectors over 64 nonzeros)
+int32_t route_form(const mrpt_index* ix);
+// the routing kernels of `form` serve this index (its depth within the form's
+// split-walk class): checked for every item before a launch is recorded
+bool route_form_holds(int32_t form, const mrpt_index* ix);
+// grid of a call in the projection launch (rows_per_wave: 0 = by the launch's
+// total size, as launch_project decides) and in the split walk
+struct RouteGrid {
+    int32_t rpw, qpl;            // projection rows per wave, queries per lane
+    int64_t nbx_p, nby_p;        // projection grid
+    int64_t nbx_r, nby_r;        // split-walk grid
+};
+RouteGrid route_grid(const mrpt_index* ix, int64_t nq, int32_t rpw, int32_t qpl);
+// the launch-wide projection shape of a form for a set of calls: rows per
+// wave and queries per lane (total_tiles: their tiles at 16 rows per wave)
+void route_shape(int32_t form, int64_t total_tiles, int32_t rows_per_wave, int32_t* rpw, int32_t* qpl);
+hipError_t launch_route_multi(int32_t form, int32_t rpw, int32_t qpl, int32_t max_d, const RouteItem* items,
+                              int32_t nitems, int64_t blocks_p, int64_t blocks_r, hipStream_t s);
+
+// the search kernel form of a call (calls of equal form can share a launch),
+// or -1 when the call's form has no multi-index kernel (its own launch then);
+// precision as mrpt_precision
+int32_t search_form(const mrpt_index* ix, int32_t precision, int32_t k, const float* Q);
+hipError_t launch_search_multi(int32_t form, int32_t d, const SearchItem* items, int32_t nitems, int64_t rows,
+                               float recheck_rel, hipStream_t s);
 hipError_t launch_check_finite(const float* A, int64_t count, int32_t* flag, hipStream_t s);
 hipError_t launch_quantize_bf16(const float* X, int64_t n, int32_t d, uint16_t* Xb, hipStream_t s);
 // device-to-device copies of 4-byte words, one job per row of the grid

@@ -4,9 +4,11 @@ vote threshold v; Table III: the time to reach at least recall R).
 
 For every (T, depth, v) of a grid the index is built on the GPU, the whole
 query batch is timed (float32 arm, and the bfloat16 arm where the dimension
-allows it), and recall@k is measured on a sample against exact k-NN computed
-by the library's exact mode (one tree of depth 0 and v = 1, so the candidate
-set is every point).  One JSON line per configuration is printed, then a
+allows it), and recall@k is measured on a sample against exact k-NN: the
+stored float64 brute-force answers of that sample (--truth, written by
+tests/golden/make_recall_truth.py), else the library's exact mode (one tree
+of depth 0 and v = 1, so the candidate set is every point; float32
+distances), which the output then names.  One JSON line per configuration is printed, then a
 summary: for each recall target the fastest configuration reaching it, for
 MRPT (all v), MRPT with v = 1 (voting disabled, the paper's second column)
 and dense random projection trees (a = 1, v = 1, the third column; on a
@@ -35,6 +37,7 @@ def main():
     p.add_argument("--reps", type=int, default=3)
     p.add_argument("--recall-sample", type=int, default=500)
     p.add_argument("--quick", action="store_true", help="a small grid (smoke run)")
+    p.add_argument("--truth", default=None, help="npz of the sample's exact k-NN (sample, idx)")
     args = p.parse_args()
 
     import torch
@@ -46,12 +49,20 @@ def main():
     X, Q = W.data(w), W.queries(w)
     Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
     nq = len(Q)
-    rs = np.random.default_rng(0).choice(nq, size=min(args.recall_sample, nq), replace=False)
-    exact = mrpt.Index(Xd, 1, 0, 1.0, 0)
-    truth, _ = exact.query(Qd[torch.from_numpy(rs).cuda()], k, 1)
-    truth = truth.cpu().numpy()
-    exact.close()
-    log(f"{w.name}: exact k-NN of {len(rs)} sample queries ready")
+    if args.truth:
+        tf = np.load(args.truth)
+        rs, truth = tf["sample"], tf["idx"]
+        if truth.shape[1] != k:
+            raise SystemExit(f"{args.truth} holds k = {truth.shape[1]}, the sweep uses k = {k}")
+        truth_kind = "stored float64 brute force"
+    else:
+        rs = np.random.default_rng(0).choice(nq, size=min(args.recall_sample, nq), replace=False)
+        exact = mrpt.Index(Xd, 1, 0, 1.0, 0)
+        truth, _ = exact.query(Qd[torch.from_numpy(rs).cuda()], k, 1)
+        truth = truth.cpu().numpy()
+        exact.close()
+        truth_kind = "library exact mode (float32)"
+    log(f"{w.name}: exact k-NN of {len(rs)} sample queries ready ({truth_kind})")
 
     if args.quick:
         Ts, depths, vs = (10, 50), (w.depth - 1, w.depth), (1, 2, 3)
@@ -134,7 +145,7 @@ def main():
         return out
 
     summary = {
-        "workload": w.name, "k": k, "queries": nq, "recall_sample": len(rs),
+        "workload": w.name, "k": k, "queries": nq, "recall_sample": len(rs), "recall_truth": truth_kind,
         "mrpt_fp32": best(lambda x: x["a"] == "sparse", "qps_fp32"),
         "mrpt_bf16": best(lambda x: x["a"] == "sparse", "qps_bf16"),
         "mrpt_v1_fp32": best(lambda x: x["a"] == "sparse" and x["v"] == 1, "qps_fp32"),

@@ -55,14 +55,14 @@ def same(out, ref, what):
         assert np.array_equal(od.view(np.uint32), rd.view(np.uint32)), f"{what}: batch {j} distances"
 
 
-@pytest.mark.parametrize("precision", [mrpt.MRPT_FP32, mrpt.MRPT_BF16_RERANK])
-@pytest.mark.parametrize("branches", [1, 5])
-def test_plan_equals_query_calls(setup, precision, branches):
+@pytest.mark.parametrize("precision", [mrpt.MRPT_FP32, mrpt.MRPT_BF16_RERANK, mrpt.MRPT_FP8_RERANK])
+@pytest.mark.parametrize("fused,branches", [(1, 1), (0, 1), (0, 5)])
+def test_plan_equals_query_calls(setup, precision, fused, branches):
     _, _, ixs, stream, _, Qs = setup
-    print(f"[case] plan precision={precision} branches={branches} batches={len(stream)}", flush=True)
+    print(f"[case] plan precision={precision} fused={fused} branches={branches} batches={len(stream)}", flush=True)
     ref = eager(ixs, stream, Qs, precision)
     plan = mrpt.Plan([(ixs[ix], Q, k, SMALL.v) for (_, ix, _, k), Q in zip(stream, Qs)],
-                     precision=precision, branches=branches)
+                     precision=precision, branches=branches, fused=fused)
     assert plan.device_bytes() > 0
     for rep in range(3):
         out = plan.launch()
@@ -128,16 +128,68 @@ def test_plan_rejects_bad_batch(setup):
             tiny.close()
 
 
+@pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("proj_rows,vote_kernel", [(4, 0), (16, 0), (0, 1), (0, 2)])
-def test_plan_launch_choices_keep_results(setup, proj_rows, vote_kernel):
+def test_plan_launch_choices_keep_results(setup, proj_rows, vote_kernel, fused):
     # the tunable launch choices (projection vectors per wave, single- or
-    # multi-pass voting) change no result
+    # multi-pass voting, per-stage or per-group launches) change no result
     _, _, ixs, stream, _, Qs = setup
-    print(f"[case] plan proj_rows={proj_rows} vote_kernel={vote_kernel}", flush=True)
+    print(f"[case] plan proj_rows={proj_rows} vote_kernel={vote_kernel} fused={fused}", flush=True)
     ref = eager(ixs, stream, Qs, mrpt.MRPT_BF16_RERANK)
     plan = mrpt.Plan([(ixs[ix], Q, k, SMALL.v) for (_, ix, _, k), Q in zip(stream, Qs)],
-                     precision=mrpt.MRPT_BF16_RERANK, branches=3, proj_rows=proj_rows, vote_kernel=vote_kernel)
+                     precision=mrpt.MRPT_BF16_RERANK, branches=3, proj_rows=proj_rows, vote_kernel=vote_kernel,
+                     fused=fused)
     out = plan.launch()
     torch.cuda.synchronize()
-    same(out, ref, f"proj_rows={proj_rows} vote_kernel={vote_kernel}")
+    same(out, ref, f"proj_rows={proj_rows} vote_kernel={vote_kernel} fused={fused}")
     plan.close()
+
+
+@pytest.mark.parametrize("queue_cap", [None, 1024])
+def test_fused_plan_shares_launches_across_indexes(queue_cap, monkeypatch):
+    """Several indexes of one d (equal kernel forms) in one per-stage launch:
+    the items of the routing, vote and search tables come from different
+    indexes, with k = 10 and 100 and v = 2 and 3; trees of 13 and 14 levels
+    share the routing launch of the 16-level class.  With the repeat queue
+    capped at 1,024 entries (MRPT_VOTE_QUEUE_CAP, read by the plan and the
+    query calls alike) the vote launch marks overflowing queries and the
+    multi-pass kernel recounts them.  Results equal the query calls', and the
+    candidate sets equal the oracle's."""
+    if queue_cap:
+        monkeypatch.setenv("MRPT_VOTE_QUEUE_CAP", str(queue_cap))
+    print(f"[case] fused plan, shared launches, queue cap {queue_cap}", flush=True)
+    rng = np.random.default_rng(41)
+    d, T = 128, 24
+    # (n, depth): leaves of 70..156 ids, and deep trees (13 and 14 levels,
+    # leaves of 1..3 ids) whose split walk takes the 16-level kernel class
+    shapes = [(3000, 5), (4500, 5), (6000, 6), (2500, 4), (20000, 13), (33000, 14)]
+    centers = rng.normal(0, 2, (16, d)).astype(np.float32)
+    X = [(centers[rng.integers(0, 16, n)] + rng.normal(0, 1, (n, d))).astype(np.float32) for n, _ in shapes]
+    ixs = [mrpt.Index(dev(x), T, depth, 1 / np.sqrt(d), 50 + i) for i, (x, (_, depth)) in enumerate(zip(X, shapes))]
+    try:
+        jobs = []
+        for j in range(12):
+            i = j % len(ixs)
+            m = int(rng.integers(1, 90))
+            Qh = (centers[rng.integers(0, 16, m)] + rng.normal(0, 1, (m, d))).astype(np.float32)
+            jobs.append((i, Qh, dev(Qh), 10 if j % 3 else 100, 2 if j % 2 else 3))
+        for prec in (mrpt.MRPT_FP32, mrpt.MRPT_BF16_RERANK):
+            plan = mrpt.Plan([(ixs[i], Q, k, v) for i, _, Q, k, v in jobs], precision=prec, fused=1)
+            out = plan.launch()
+            torch.cuda.synchronize()
+            ref = [ixs[i].query(Q, k, v, precision=prec) for i, _, Q, k, v in jobs]
+            torch.cuda.synchronize()
+            same(out, [(a.cpu().numpy(), b.cpu().numpy()) for a, b in ref], f"precision {prec}")
+            plan.close()
+        orc = [oracle.build_index(x, T, depth, 1 / np.sqrt(d), 50 + i) for i, (x, (_, depth)) in enumerate(zip(X, shapes))]
+        plan = mrpt.Plan([(ixs[i], Q, k, v) for i, _, Q, k, v in jobs], fused=1)
+        out = plan.launch()
+        torch.cuda.synchronize()
+        for (i, Qh, _, k, v), (gi, gd) in zip(jobs, out):
+            ref = oracle.query(orc[i], Qh, k, v, want_sets=True)
+            S = [set(s.tolist()) for s in ref["s_ids"]]
+            check_knn(X[i], Qh, gi.cpu().numpy(), gd.cpu().numpy(), ref["idx"], ref["dist"], exact_ids=False, S=S)
+        plan.close()
+    finally:
+        for ix in ixs:
+            ix.close()
