@@ -215,17 +215,19 @@ typedef struct mrpt_plan_opts {
     int32_t precision;      /* mrpt_precision of every batch (default MRPT_FP32) */
     int32_t rerank_factor;  /* as in mrpt_query_opts (default 4) */
     float recheck_rel;      /* as in mrpt_query_opts (default 1e-6) */
-    int32_t branches;       /* independent chains, 1..64 (default 4) */
+    int32_t branches;       /* 1..64 (default 4): streams a stage's launches are spread over
+                               (fused), or independent chains of groups (not fused) */
     int32_t proj_rows;      /* projection vectors per wave: 0 (default) the launcher's choice
                                (4 for launches under 512 workgroups, else 16), or 4, or 16 */
     int32_t vote_kernel;    /* 0 (default) automatic; 1 the single-pass vote kernel wherever it
                                fits; 2 the multi-pass one. */
     int32_t fused;          /* 1 (default): one launch per stage for all groups of a kernel form
                                (calls of the same kernel shape, whatever their index), driven by
-                               device tables of (index arrays, query range, k, v, workspace), in
-                               one chain; 0: every group its own chain of launches, dealt over
-                               `branches`.  None of these knobs changes a result; they are there
-                               for tuning the launches. */
+                               device tables of (index arrays, query range, k, v, workspace); the
+                               launches of one stage run side by side on `branches` streams and
+                               a stage starts when the previous one has ended; 0: every group its
+                               own chain of launches, dealt over `branches`.  None of these knobs
+                               changes a result; they are there for tuning the launches. */
 } mrpt_plan_opts;
 
 typedef struct mrpt_plan mrpt_plan;

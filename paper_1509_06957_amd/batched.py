@@ -82,7 +82,7 @@ def main():
     best = None
     cands = []
     for f in [int(x) for x in args.fused.split(",")]:
-        for b in ([1] if f else [int(x) for x in args.branches.split(",")]):
+        for b in [int(x) for x in args.branches.split(",")]:
             for pr in [int(x) for x in args.proj_rows.split(",")]:
                 for vk in [int(x) for x in args.vote_kernels.split(",")]:
                     cands.append((f, b, pr, vk))

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 
@@ -1096,66 +1097,118 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
                                    hipMemcpyHostToDevice));
         }
 
-        // record one chain: gather, routing, voting, search, scatter
+        // the launches of each stage as units: classes of a stage run on up
+        // to `branches` streams side by side, and a stage starts when the one
+        // before it has ended
+        using Unit = std::function<hipError_t(hipStream_t)>;
+        std::vector<std::vector<Unit>> stages(5);
+        if (!gather.empty())
+            stages[0].push_back([&](hipStream_t x) {
+                return launch_copy_jobs(reinterpret_cast<const CopyJob*>(base + gather_off), n_gather, most_g, x);
+            });
+        for (size_t ci = 0; ci < route_cls.size(); ++ci)
+            stages[1].push_back([&, ci](hipStream_t x) {
+                return launch_route_multi(rl[ci].form, rl[ci].rpw, rl[ci].qpl, rl[ci].max_d,
+                                          reinterpret_cast<const RouteItem*>(base + route_cls[ci].tab_off),
+                                          (int32_t)route_cls[ci].members.size(), rl[ci].blocks_p, rl[ci].blocks_r, x);
+            });
+        for (int32_t gi : route_alone)
+            stages[1].push_back([&, gi](hipStream_t x) {
+                const Group& g = groups[gi];
+                const Workspace ws = call_ws(g);
+                return launch_route(g.ix, call_Q(g), g.rows, ws.leaf, ws.pq, x, cfg);
+            });
+        for (size_t ci = 0; ci < vote_cls.size(); ++ci)
+            stages[2].push_back([&, ci](hipStream_t x) {
+                hipError_t e1 = launch_vote_multi(vote_cls[ci].key, vl[ci].map_words, vl[ci].qcap,
+                                                  reinterpret_cast<const VoteItem*>(base + vote_cls[ci].tab_off),
+                                                  reinterpret_cast<const int32_t*>(base + vote_cls[ci].row_off),
+                                                  vote_cls[ci].rows, x);
+                for (int32_t gi : recount[ci]) {
+                    if (e1 != hipSuccess) break;
+                    const Group& g = groups[gi];
+                    const Workspace ws = call_ws(g);
+                    e1 = launch_vote_recount(g.ix, ws.leaf, g.rows, g.v, ws.s_ids, g.cap, ws.s_count, x);
+                }
+                return e1;
+            });
+        for (int32_t gi : vote_alone)
+            stages[2].push_back([&, gi](hipStream_t x) {
+                const Group& g = groups[gi];
+                const Workspace ws = call_ws(g);
+                return launch_vote(g.ix, ws.leaf, g.rows, g.v, ws.s_ids, g.cap, ws.s_count, x, cfg);
+            });
+        for (size_t ci = 0; ci < search_cls.size(); ++ci)
+            stages[3].push_back([&, ci](hipStream_t x) {
+                return launch_search_multi((int32_t)(search_cls[ci].key >> 20),
+                                           (int32_t)(search_cls[ci].key & 0xFFFFF),
+                                           reinterpret_cast<const SearchItem*>(base + search_cls[ci].tab_off),
+                                           (int32_t)search_cls[ci].members.size(), sl[ci], o.recheck_rel, x);
+            });
+        for (int32_t gi : search_alone)
+            stages[3].push_back([&, gi](hipStream_t x) {
+                const Group& g = groups[gi];
+                const Workspace ws = call_ws(g);
+                if (o.precision == MRPT_FP32)
+                    return launch_dist_fp32(g.ix, call_Q(g), g.rows, ws.s_ids, g.cap, ws.s_count, g.k, call_idx(g),
+                                            call_dist(g), x);
+                return launch_dist_prefilter(g.ix, o.precision == MRPT_FP8_RERANK ? 1 : 0, call_Q(g), g.rows,
+                                             ws.s_ids, g.cap, ws.s_count, g.k, o.rerank_factor, o.recheck_rel,
+                                             call_idx(g), call_dist(g), x);
+            });
+        if (!scatter.empty())
+            stages[4].push_back([&](hipStream_t x) {
+                return launch_copy_jobs(reinterpret_cast<const CopyJob*>(base + scatter_off), n_scatter, most_s, x);
+            });
+        size_t widest = 1;
+        for (const auto& u : stages) widest = std::max(widest, u.size());
+        const int nstr = (int)std::min<size_t>((size_t)po.branches, widest);
+
         hipStream_t st = nullptr;
+        std::vector<hipStream_t> side((size_t)nstr, nullptr);
+        std::vector<hipEvent_t> evs;
         hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        for (int i = 0; i < nstr && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+        auto new_event = [&](hipEvent_t* ev) {
+            hipError_t r = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+            if (r == hipSuccess) evs.push_back(*ev);
+            return r;
+        };
         bool capturing = false;
         if (e == hipSuccess) {
             e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
             capturing = e == hipSuccess;
         }
-        if (e == hipSuccess && !gather.empty())
-            e = launch_copy_jobs(reinterpret_cast<const CopyJob*>(base + gather_off), n_gather, most_g, st);
-        for (size_t ci = 0; ci < route_cls.size() && e == hipSuccess; ++ci)
-            e = launch_route_multi(rl[ci].form, rl[ci].rpw, rl[ci].qpl, rl[ci].max_d,
-                                   reinterpret_cast<const RouteItem*>(base + route_cls[ci].tab_off),
-                                   (int32_t)route_cls[ci].members.size(), rl[ci].blocks_p, rl[ci].blocks_r, st);
-        for (int32_t gi : route_alone) {
-            if (e != hipSuccess) break;
-            const Group& g = groups[gi];
-            const Workspace ws = call_ws(g);
-            e = launch_route(g.ix, call_Q(g), g.rows, ws.leaf, ws.pq, st, cfg);
-        }
-        for (size_t ci = 0; ci < vote_cls.size() && e == hipSuccess; ++ci) {
-            e = launch_vote_multi(vote_cls[ci].key, vl[ci].map_words, vl[ci].qcap,
-                                  reinterpret_cast<const VoteItem*>(base + vote_cls[ci].tab_off),
-                                  reinterpret_cast<const int32_t*>(base + vote_cls[ci].row_off), vote_cls[ci].rows, st);
-            for (int32_t gi : recount[ci]) {
-                if (e != hipSuccess) break;
-                const Group& g = groups[gi];
-                const Workspace ws = call_ws(g);
-                e = launch_vote_recount(g.ix, ws.leaf, g.rows, g.v, ws.s_ids, g.cap, ws.s_count, st);
+        for (const auto& units : stages) {
+            if (e != hipSuccess || units.empty()) continue;
+            if (units.size() == 1 || nstr == 1) {
+                for (const Unit& u : units) {
+                    if (e == hipSuccess) e = u(st);
+                }
+                continue;
+            }
+            // fork from the chain, unit j on side stream j mod nstr, join
+            hipEvent_t fork = nullptr;
+            e = new_event(&fork);
+            if (e == hipSuccess) e = hipEventRecord(fork, st);
+            const int used = (int)std::min<size_t>((size_t)nstr, units.size());
+            for (int i = 0; i < used && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[i], fork, 0);
+            for (size_t j = 0; j < units.size() && e == hipSuccess; ++j) e = units[j](side[j % (size_t)nstr]);
+            for (int i = 0; i < used && e == hipSuccess; ++i) {
+                hipEvent_t join = nullptr;
+                e = new_event(&join);
+                if (e == hipSuccess) e = hipEventRecord(join, side[i]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
             }
         }
-        for (int32_t gi : vote_alone) {
-            if (e != hipSuccess) break;
-            const Group& g = groups[gi];
-            const Workspace ws = call_ws(g);
-            e = launch_vote(g.ix, ws.leaf, g.rows, g.v, ws.s_ids, g.cap, ws.s_count, st, cfg);
-        }
-        for (size_t ci = 0; ci < search_cls.size() && e == hipSuccess; ++ci)
-            e = launch_search_multi((int32_t)(search_cls[ci].key >> 20), (int32_t)(search_cls[ci].key & 0xFFFFF),
-                                    reinterpret_cast<const SearchItem*>(base + search_cls[ci].tab_off),
-                                    (int32_t)search_cls[ci].members.size(), sl[ci], o.recheck_rel, st);
-        for (int32_t gi : search_alone) {
-            if (e != hipSuccess) break;
-            const Group& g = groups[gi];
-            const Workspace ws = call_ws(g);
-            if (o.precision == MRPT_FP32)
-                e = launch_dist_fp32(g.ix, call_Q(g), g.rows, ws.s_ids, g.cap, ws.s_count, g.k, call_idx(g),
-                                     call_dist(g), st);
-            else
-                e = launch_dist_prefilter(g.ix, o.precision == MRPT_FP8_RERANK ? 1 : 0, call_Q(g), g.rows, ws.s_ids,
-                                          g.cap, ws.s_count, g.k, o.rerank_factor, o.recheck_rel, call_idx(g),
-                                          call_dist(g), st);
-        }
-        if (e == hipSuccess && !scatter.empty())
-            e = launch_copy_jobs(reinterpret_cast<const CopyJob*>(base + scatter_off), n_scatter, most_s, st);
         if (capturing) {
             const hipError_t e2 = hipStreamEndCapture(st, &plan->graph);
             if (e == hipSuccess) e = e2;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+        for (hipEvent_t x : evs) (void)hipEventDestroy(x);
+        for (hipStream_t x : side)
+            if (x) (void)hipStreamDestroy(x);
         if (st) (void)hipStreamDestroy(st);
         if (e != hipSuccess) {
             (void)hipGetLastError();
