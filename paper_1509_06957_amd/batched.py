@@ -38,6 +38,7 @@ def main():
     p.add_argument("--proj-rows", default="0,16", help="projection vectors per wave to try (0: automatic)")
     p.add_argument("--vote-kernels", default="0,2", help="vote kernels to try (0 automatic, 1 single-pass, 2 multi-pass)")
     p.add_argument("--recall-sample", type=int, default=2000)
+    p.add_argument("--retune", action="store_true", help="time every candidate even if the cache holds a choice")
     args = p.parse_args()
 
     import torch
@@ -75,30 +76,18 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps * 1e3
 
-    # autotuner over the recorded graph's launch choices: per-stage launches
-    # across the indexes (fused) or per-group chains over a branch count,
-    # projection rows per wave, vote kernel
-    tuning = {}
-    best = None
-    cands = []
-    for f in [int(x) for x in args.fused.split(",")]:
-        for b in [int(x) for x in args.branches.split(",")]:
-            for pr in [int(x) for x in args.proj_rows.split(",")]:
-                for vk in [int(x) for x in args.vote_kernels.split(",")]:
-                    cands.append((f, b, pr, vk))
-    for f, b, pr, vk in cands:
-        plan = mrpt.Plan(batches, precision=prec, branches=b, proj_rows=pr, vote_kernel=vk, fused=f)
-        ms = time_launches(plan.launch, max(2, args.steps // 2))
-        key = f"fused={f},branches={b},proj_rows={pr},vote_kernel={vk}"
-        tuning[key] = round(ms, 4)
-        log(f"{key}: {ms:.3f} ms per step")
-        if best is None or ms < best[1]:
-            if best is not None:
-                best[2].close()
-            best = (key, ms, plan)
-        else:
-            plan.close()
-    b_best, _, plan = best
+    # autotuner over the recorded graph's launch choices (tuning.py): plan
+    # form, streams or chains, projection rows per wave, vote kernel; the
+    # choice is cached as JSON under the batches' signature
+    from paper_1509_06957_amd import tuning
+    grid = {"fused": [int(x) for x in args.fused.split(",")],
+            "branches": [int(x) for x in args.branches.split(",")],
+            "proj_rows": [int(x) for x in args.proj_rows.split(",")],
+            "vote_kernel": [int(x) for x in args.vote_kernels.split(",")]}
+    choice, tuning_ms, cached = tuning.tune(batches, prec, lambda pl: time_launches(pl.launch, max(2, args.steps // 2)),
+                                            grid=grid, retune=args.retune, log=log)
+    b_best = ",".join(f"{k}={v}" for k, v in choice.items())
+    plan = mrpt.Plan(batches, precision=prec, **choice)
     plan_ms = time_launches(plan.launch, args.steps)
     out = plan.launch()
     torch.cuda.synchronize()
@@ -136,7 +125,8 @@ def main():
         "batches": len(stream), "queries": nq, "T": bw.T, "v": bw.v,
         "precision": "bf16+rerank" if prec == mrpt.MRPT_BF16_RERANK else "fp32",
         "plan_qps": round(nq / (plan_ms / 1e3), 1), "plan_ms_per_step": round(plan_ms, 4),
-        "chosen": b_best, "tuning_ms": tuning,
+        "chosen": b_best, "tuning_ms": tuning_ms, "tuning_from_cache": cached,
+        "tuning_cache": tuning.cache_path(),
         "eager_qps": round(nq / (eager_ms / 1e3), 1), "eager_ms_per_step": round(eager_ms, 4),
         "plan_equals_eager": bool(identical),
         "recall_at_k": round(hit / max(tot, 1), 4), "recall_sample_queries": taken,

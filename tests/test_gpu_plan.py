@@ -193,3 +193,34 @@ def test_fused_plan_shares_launches_across_indexes(queue_cap, monkeypatch):
     finally:
         for ix in ixs:
             ix.close()
+
+
+def test_tuner_times_candidates_and_caches_the_choice(setup, tmp_path):
+    from paper_1509_06957_amd import tuning
+    _, _, ixs, stream, _, Qs = setup
+    print("[case] plan autotuner and its cache", flush=True)
+    batches = [(ixs[ix], Q, k, SMALL.v) for (_, ix, _, k), Q in zip(stream, Qs)]
+    path = str(tmp_path / "tuning.json")
+
+    def time_plan(plan):
+        plan.launch()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(3):
+            plan.launch()
+        ev[1].record()
+        ev[1].synchronize()
+        return ev[0].elapsed_time(ev[1]) / 3
+
+    grid = {"fused": [1, 0], "branches": [1, 3], "proj_rows": [0], "vote_kernel": [0]}
+    choice, timings, cached = tuning.tune(batches, mrpt.MRPT_FP32, time_plan, grid=grid, path=path)
+    assert not cached and len(timings) == 4 and set(choice) == {"fused", "branches", "proj_rows", "vote_kernel"}
+    again, t2, cached2 = tuning.tune(batches, mrpt.MRPT_FP32, time_plan, grid=grid, path=path)
+    assert cached2 and again == choice and t2 == {}
+    ref = eager(ixs, stream, Qs, mrpt.MRPT_FP32)
+    plan = mrpt.Plan(batches, precision=mrpt.MRPT_FP32, **choice)
+    out = plan.launch()
+    torch.cuda.synchronize()
+    same(out, ref, f"tuned plan {choice}")
+    plan.close()
