@@ -70,16 +70,16 @@ __device__ __forceinline__ void pick_bucket(const uint32_t* hist, int rem, int* 
     }
 }
 
-// The need smallest of the tot pairs (key[e], id[e]) under (key, id), ids
-// distinct, need < tot, written to (okey, oid)[0, need) in no particular
-// order.  A radix select over the key's bytes from the top finds the key T of
-// the need-th pair and how many pairs at T are taken; when that is not all
-// of them, a second radix select over the ids of the pairs at T finds the
-// largest id taken.  All 256 threads of the workgroup take part.
-__device__ void block_select(const uint32_t* key, const int32_t* id, int tot, int need, uint32_t* okey,
-                             int32_t* oid, uint32_t* hist, int* sel) {
+// The pair (T, idT) of rank need (1-based) among the tot pairs (key[e],
+// id[e]) under (key, id), ids distinct, 1 <= need <= tot: a radix select over
+// the key's bytes from the top finds T and how many pairs at T rank up to
+// need; when that is not all of them, a second radix select over the ids of
+// the pairs at T finds idT (else idT = 0xFFFFFFFF: every pair at T is within
+// the rank).  The pairs of rank <= need are those with key < T, or key == T
+// and id <= idT.  All 256 threads of the workgroup take part.
+__device__ void block_threshold(const uint32_t* key, const int32_t* id, int tot, int need, uint32_t* hist, int* sel,
+                                uint32_t& T, uint32_t& idT) {
     const int tid = (int)threadIdx.x;
-    const int lane = lane_id();
     const int w = tid >> 6;
     uint32_t prefix = 0u, pmask = 0u;
     int rem = need, eq = tot;
@@ -98,8 +98,8 @@ __device__ void block_select(const uint32_t* key, const int32_t* id, int tot, in
         rem = sel[1];
         eq = sel[2];
     }
-    const uint32_t T = prefix;
-    uint32_t idT = 0xFFFFFFFFu;                  // pairs at T with id <= idT are taken
+    T = prefix;
+    idT = 0xFFFFFFFFu;
     if (rem < eq) {
         uint32_t ip = 0u, im = 0u;
         for (int shift = 24; shift >= 0; shift -= 8) {
@@ -118,6 +118,17 @@ __device__ void block_select(const uint32_t* key, const int32_t* id, int tot, in
         }
         idT = ip;
     }
+}
+
+// The need smallest of the tot pairs (key[e], id[e]) under (key, id), ids
+// distinct, need < tot, written to (okey, oid)[0, need) in no particular
+// order (block_threshold, then one compaction).
+__device__ void block_select(const uint32_t* key, const int32_t* id, int tot, int need, uint32_t* okey,
+                             int32_t* oid, uint32_t* hist, int* sel) {
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id();
+    uint32_t T, idT;
+    block_threshold(key, id, tot, need, hist, sel, T, idT);
     if (tid == 0) sel[3] = 0;
     __syncthreads();
     for (int e0 = 0; e0 < tot; e0 += 256) {      // uniform trip count
@@ -143,6 +154,14 @@ __device__ void block_select(const uint32_t* key, const int32_t* id, int tot, in
     __syncthreads();
 }
 
+// append this thread's index e to the LDS list (out, *count) when take
+__device__ __forceinline__ void block_append(bool take, int e, int32_t* out, int* count) {
+    const uint64_t m = __ballot(take);
+    int base = 0;
+    if (lane_id() == 0 && m) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, 0);
+    if (take) out[base + __popcll(m & __lanemask_lt())] = e;
+}
 
 template <int G, int NV, int R>
 __device__ __forceinline__ void dist_fp32_body(const float* __restrict__ X, int32_t d, const float* __restrict__ Q,
@@ -546,7 +565,7 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
     // phase 2: float32 direct distances of the survivors, gathered as in
     // dist_fp32 (same lanes per row, same summation order, U2 rows per group
     // in flight).  Slots past the kq = min(|S|, kp) survivors are empty (id
-    // -1, distance +inf): they keep their slot as their rank.
+    // -1, distance +inf).
     const int kq = ns < kp ? ns : kp;
     {
         const int g2 = lane / G2, gl2 = lane - g2 * G2;
@@ -599,42 +618,60 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
         for (int c = kq + (int)threadIdx.x; c < kp; c += (int)blockDim.x) d32[c] = INFINITY;
     }
     __syncthreads();
-    // order by (d32, id); empty slots (id -1, +inf) go last in slot order
-    for (int c = (int)threadIdx.x; c < kp; c += (int)blockDim.x) {
-        if (c >= kq) {
-            order[c] = c;
-            continue;
+    // phase 3.  The kk = min(k, kp)-th kept candidate under (d32, id) (kk = k
+    // since kp >= k): when there are fewer, no recheck.  Its float32 distance
+    // dk fixes the recheck window, the candidates whose float32 distance is
+    // within recheck_rel * dk of dk (contiguous in the (d32, id) order); the
+    // candidates below it take ranks 0.. by (d32, id), the window's then
+    // follow by (d64, id) after a float64 recompute, and only ranks < k are
+    // written (so only about k candidates are ranked, not all kp).
+    const int kk = k < kp ? k : kp;
+    float dk2 = INFINITY;
+    if (kq >= kk) {
+        for (int c = (int)threadIdx.x; c < kq; c += (int)blockDim.x) ckey[c] = score_key(d32[c]);
+        __syncthreads();
+        uint32_t T, idT;
+        block_threshold(ckey, cand, kq, kk, hist, sel, T, idT);
+        dk2 = T >= 0xFF800000u ? INFINITY : __builtin_bit_cast(float, T ^ 0x80000000u);
+    }
+    int32_t* below = order;                                             // candidates below the window
+    int32_t* winl = reinterpret_cast<int32_t*>(pf_smem + kMaxRerank * 20);   // the window
+    static_assert(kMaxRerank * 24 <= kPfBuf * 8, "the window list fits the phase-1 buffer");
+    if (threadIdx.x == 0) { win_lo = 0; win_hi = 0; }
+    __syncthreads();
+    {
+        const bool finite = dk2 < INFINITY;
+        const float dk = finite ? sqrtf(dk2) : INFINITY;
+        const float tol = finite ? recheck_rel * dk : 0.0f;
+        for (int c0 = 0; c0 < kq; c0 += (int)blockDim.x) {   // uniform trip count
+            const int c = c0 + (int)threadIdx.x;
+            bool in_win = false, is_below = false;
+            if (c < kq) {
+                const float x = d32[c];
+                if (finite) {
+                    const float sx = sqrtf(x);
+                    in_win = fabsf(sx - dk) <= tol;
+                    is_below = !in_win && sx < dk;
+                } else {
+                    is_below = x < INFINITY;
+                }
+            }
+            block_append(is_below, c, below, &win_lo);
+            block_append(in_win, c, winl, &win_hi);
         }
+    }
+    __syncthreads();
+    const int nb = win_lo, nw = win_hi;
+    for (int i = (int)threadIdx.x; i < nb; i += (int)blockDim.x) {
+        const int c = below[i];
         const float kd = d32[c];
-        const int32_t ki = cand[c] < 0 ? kPadId + c : cand[c];
+        const int32_t ki = cand[c];
         int rank = 0;
-        for (int o = 0; o < kq; ++o) {
-            const int32_t oi = cand[o] < 0 ? kPadId + o : cand[o];
-            rank += key_less(d32[o], oi, kd, ki) ? 1 : 0;
-        }
-        order[rank] = c;
+        for (int j = 0; j < nb; ++j) rank += key_less(d32[below[j]], cand[below[j]], kd, ki) ? 1 : 0;
+        if (rank < k) final_slot[rank] = c;
     }
-    __syncthreads();
-    // phase 3: float64 recheck of the window around the k-th float32 distance
-    if (threadIdx.x == 0) {
-        const int kk = k < kp ? k : kp;
-        const float dk2 = d32[order[kk - 1]];
-        int lo = kk, hi = kk;
-        if (dk2 < INFINITY) {
-            const float dk = sqrtf(dk2);
-            const float tol = recheck_rel * dk;
-            lo = kk - 1;
-            while (lo > 0 && fabsf(sqrtf(d32[order[lo - 1]]) - dk) <= tol) --lo;
-            hi = kk;
-            while (hi < kp && d32[order[hi]] < INFINITY && fabsf(sqrtf(d32[order[hi]]) - dk) <= tol) ++hi;
-        }
-        win_lo = lo;
-        win_hi = hi;
-    }
-    __syncthreads();
-    const int wlo = win_lo, whi = win_hi;
-    for (int r = wlo + w; r < whi; r += kDistWaves) {
-        const int c = uniform(order[r]);
+    for (int j = w; j < nw; j += kDistWaves) {
+        const int c = uniform(winl[j]);
         const int32_t id = uniform(cand[c]);
         const float* xr = X + (int64_t)id * d;
         double a = 0.0;
@@ -647,22 +684,18 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
         if (lane == 0) d64[c] = a;
     }
     __syncthreads();
-    for (int r = (int)threadIdx.x; r < k; r += (int)blockDim.x) {
-        if (r < wlo || r >= whi) {
-            final_slot[r] = r < kp ? order[r] : -1;
-        }
-    }
-    for (int r = wlo + (int)threadIdx.x; r < whi; r += (int)blockDim.x) {
-        const int c = order[r];
+    for (int i = (int)threadIdx.x; i < nw; i += (int)blockDim.x) {
+        const int c = winl[i];
         const double kd = d64[c];
         const int32_t ki = cand[c];
-        int rank = wlo;
-        for (int o = wlo; o < whi; ++o) {
-            const int oc = order[o];
+        int rank = nb;
+        for (int j = 0; j < nw; ++j) {
+            const int oc = winl[j];
             rank += (d64[oc] < kd || (d64[oc] == kd && cand[oc] < ki)) ? 1 : 0;
         }
         if (rank < k) final_slot[rank] = -2 - c;  // marks a rechecked slot
     }
+    for (int r = nb + nw + (int)threadIdx.x; r < k; r += (int)blockDim.x) final_slot[r] = -1;
     __syncthreads();
     for (int r = (int)threadIdx.x; r < k; r += (int)blockDim.x) {
         const int fs = final_slot[r];
