@@ -3,8 +3,8 @@ experiments (Sec. IV: a grid over the number of trees T, the depth and the
 vote threshold v; Table III: the time to reach at least recall R).
 
 For every (T, depth, v) of a grid the index is built on the GPU, the whole
-query batch is timed (float32 arm, and the bfloat16 arm where the dimension
-allows it), and recall@k is measured on a sample against exact k-NN: the
+query batch is timed (float32 arm, and the bfloat16 and fp8 prefilter arms
+where the dimension allows them), and recall@k is measured on a sample against exact k-NN: the
 stored float64 brute-force answers of that sample (--truth, written by
 tests/golden/make_recall_truth.py), else the library's exact mode (one tree
 of depth 0 and v = 1, so the candidate set is every point; float32
@@ -71,6 +71,7 @@ def main():
         depths = tuple(dd for dd in range(w.depth - 3, w.depth + 2) if (1 << dd) <= w.n)
         vs = (1, 2, 3, 4, 5, 6, 8)
     bf16_ok = w.d % 8 == 0 and w.d <= 1024
+    fp8_ok = w.d % 16 == 0 and w.d <= 1024
 
     def timed(ix, v, precision):
         out = (torch.empty((nq, k), dtype=torch.int32, device="cuda"),
@@ -105,9 +106,13 @@ def main():
                     s_count = torch.zeros(nq, dtype=torch.int32, device="cuda")
                     ix.query(Qd, k, v, s_count=s_count)
                     qps32, ids = timed(ix, v, mrpt.MRPT_FP32)
-                    qps16 = timed(ix, v, mrpt.MRPT_BF16_RERANK)[0] if bf16_ok else None
+                    qps16, ids16 = timed(ix, v, mrpt.MRPT_BF16_RERANK) if bf16_ok else (None, None)
+                    qps8, ids8 = timed(ix, v, mrpt.MRPT_FP8_RERANK) if fp8_ok else (None, None)
                     row = {"a": a_mode, "T": T, "depth": depth, "v": v, "recall": round(recall_of(ids), 4),
                            "qps_fp32": round(qps32, 1), "qps_bf16": None if qps16 is None else round(qps16, 1),
+                           "qps_fp8": None if qps8 is None else round(qps8, 1),
+                           "recall_bf16": None if ids16 is None else round(recall_of(ids16), 4),
+                           "recall_fp8": None if ids8 is None else round(recall_of(ids8), 4),
                            "s_mean": round(float(s_count.float().mean()), 1), "build_s": round(build_s, 3)}
                     rows.append(row)
                     print(json.dumps(row), flush=True)
@@ -133,13 +138,13 @@ def main():
 
     targets = (0.8, 0.9, 0.95, 0.99)
 
-    def best(sel, key):
+    def best(sel, key, rkey="recall"):
         out = {}
         for r in targets:
-            ok = [x for x in rows if sel(x) and x["recall"] >= r and x[key] is not None]
+            ok = [x for x in rows if sel(x) and x[key] is not None and x[rkey] >= r]
             if ok:
                 b = max(ok, key=lambda x: x[key])
-                out[str(r)] = {"qps": b[key], "T": b["T"], "depth": b["depth"], "v": b["v"], "recall": b["recall"]}
+                out[str(r)] = {"qps": b[key], "T": b["T"], "depth": b["depth"], "v": b["v"], "recall": b[rkey]}
             else:
                 out[str(r)] = None
         return out
@@ -147,7 +152,8 @@ def main():
     summary = {
         "workload": w.name, "k": k, "queries": nq, "recall_sample": len(rs), "recall_truth": truth_kind,
         "mrpt_fp32": best(lambda x: x["a"] == "sparse", "qps_fp32"),
-        "mrpt_bf16": best(lambda x: x["a"] == "sparse", "qps_bf16"),
+        "mrpt_bf16": best(lambda x: x["a"] == "sparse", "qps_bf16", "recall_bf16"),
+        "mrpt_fp8": best(lambda x: x["a"] == "sparse", "qps_fp8", "recall_fp8"),
         "mrpt_v1_fp32": best(lambda x: x["a"] == "sparse" and x["v"] == 1, "qps_fp32"),
         "rp_trees_dense_fp32": best(lambda x: x["a"] == "dense", "qps_fp32"),
         "exact_nnz_ablation": [{"v": b["v"], "recall": b["recall"], "recall_exact": e["recall"],
