@@ -339,6 +339,45 @@ constexpr int kProjWaves = 8;
 // chain still runs over the features in ascending order, chunk after chunk.
 constexpr int kProjChunk = (64 * 1024) / (kQStride * 4);   // 252 features: 64 KB of LDS
 
+// The tile of 64 * QPL queries from q0 (d features, d % 4 == 0, rows 16-byte
+// aligned) into LDS as qt[f * QPL * 65 + (r / 64) * 65 + r % 64] for tile
+// row r; rows past nq read as zero.  Each thread issues all its 16-byte
+// loads before it stores any: one memory round trip for the tile when it
+// holds at most kStageUnroll loads per thread (d = 128, two 64-query halves).
+template <int QPL>
+__device__ __forceinline__ void stage_tile_v4(const float* __restrict__ Q, int64_t q0, int64_t nq, int d,
+                                              float* qt) {
+    constexpr int FS = QPL * kQStride;
+    const int tid = (int)threadIdx.x, nthreads = (int)blockDim.x;
+    const int d4 = d >> 2;
+    const int total = kWave * QPL * d4;
+    const int64_t rows_left = nq - q0;
+    for (int e0 = tid; e0 < total; e0 += kStageUnroll * nthreads) {
+        float4 r[kStageUnroll];
+        int rq[kStageUnroll], rf[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int e = e0 + u * nthreads;
+            const int qq = e / d4;
+            rq[u] = qq;
+            rf[u] = e - qq * d4;
+            r[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (e < total && qq < rows_left)
+                r[u] = reinterpret_cast<const float4*>(Q + (q0 + qq) * d)[rf[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            if (e0 + u * nthreads < total) {
+                float* dst = qt + 4 * rf[u] * FS + (rq[u] >> 6) * kQStride + (rq[u] & (kWave - 1));
+                dst[0] = r[u].x;
+                dst[FS] = r[u].y;
+                dst[2 * FS] = r[u].z;
+                dst[3 * FS] = r[u].w;
+            }
+        }
+    }
+}
+
 template <int RPW, bool CHUNKED, int QPL>
 __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_t nq, int32_t d,
                                              const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -381,13 +420,20 @@ __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_
         // queries q0 + l and q0 + 64 + l (QPL = 2), which share every
         // nonzero taken from the row registers
         constexpr int FS = QPL * kQStride;
+        if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0) {
+            stage_tile_v4<QPL>(Q, q0, nq, d, proj_smem);
+        } else {
 #pragma unroll
-        for (int h = 0; h < QPL; ++h)
-            stage_query_chunk(Q, q0 + h * kWave, nq, d, 0, d, proj_smem + h * kQStride, FS);
+            for (int h = 0; h < QPL; ++h)
+                stage_query_chunk(Q, q0 + h * kWave, nq, d, 0, d, proj_smem + h * kQStride, FS);
+        }
         __syncthreads();
         // entries every row has: no branch, so the LDS reads of all rows
         // issue together; then the rows' remaining entries
         int k = 0;
+        // two steps per turn: the LDS reads of the next step issue before
+        // this step's multiply-adds wait on theirs
+#pragma unroll 2
         for (; k < minlen; ++k) {
 #pragma unroll
             for (int i = 0; i < RPW; ++i) {
