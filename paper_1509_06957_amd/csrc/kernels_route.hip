@@ -378,16 +378,19 @@ __device__ __forceinline__ void stage_tile_v4(const float* __restrict__ Q, int64
     }
 }
 
+// acc[h][i] = projection of query q0 + 64 h + lane on row r0 + i (rows at
+// or past rend give 0) for this wave's RPW rows; the workgroup stages the
+// query tile in proj_smem (every wave calls this; it ends with the tile
+// still being read, so a caller that reuses proj_smem waits first)
 template <int RPW, bool CHUNKED, int QPL>
-__device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_t nq, int32_t d,
-                                             const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                             const float* __restrict__ val, int32_t nrows, float* __restrict__ Pq,
-                                             float* proj_smem, const int64_t bx, const int32_t by) {
+__device__ __forceinline__ void project_accumulate(const float* __restrict__ Q, int64_t nq, int32_t d,
+                                                   const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col, const float* __restrict__ val,
+                                                   int32_t r0, int32_t rend, int64_t q0, float* proj_smem,
+                                                   float (&acc)[QPL][RPW]) {
     static_assert(QPL == 1 || !CHUNKED, "two queries per lane only with the whole tile in LDS");
     const int lane = lane_id();
-    const int w = uniform((int)(threadIdx.x >> 6));
-    const int64_t q0 = bx * (kWave * QPL);
-    const int r0 = uniform(by * (kProjWaves * RPW) + w * RPW);
+    const int nrows = rend;
     int len[RPW];
     int colr[RPW];
     float valr[RPW];
@@ -410,7 +413,6 @@ __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_
         }
         minlen = len[i] < minlen ? len[i] : minlen;
     }
-    float acc[QPL][RPW];
 #pragma unroll
     for (int h = 0; h < QPL; ++h)
 #pragma unroll
@@ -431,9 +433,6 @@ __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_
         // entries every row has: no branch, so the LDS reads of all rows
         // issue together; then the rows' remaining entries
         int k = 0;
-        // two steps per turn: the LDS reads of the next step issue before
-        // this step's multiply-adds wait on theirs
-#pragma unroll 2
         for (; k < minlen; ++k) {
 #pragma unroll
             for (int i = 0; i < RPW; ++i) {
@@ -494,6 +493,19 @@ __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_
 #pragma unroll
         for (int i = 0; i < RPW; ++i) kb[i] = ke[i];
     }
+}
+
+template <int RPW, bool CHUNKED, int QPL>
+__device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_t nq, int32_t d,
+                                             const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                             const float* __restrict__ val, int32_t nrows, float* __restrict__ Pq,
+                                             float* proj_smem, const int64_t bx, const int32_t by) {
+    const int lane = lane_id();
+    const int w = uniform((int)(threadIdx.x >> 6));
+    const int64_t q0 = bx * (kWave * QPL);
+    const int r0 = uniform(by * (kProjWaves * RPW) + w * RPW);
+    float acc[QPL][RPW];
+    project_accumulate<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, r0, nrows, q0, proj_smem, acc);
 #pragma unroll
     for (int h = 0; h < QPL; ++h) {
         const int64_t q = q0 + h * kWave + lane;
@@ -501,6 +513,70 @@ __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_
 #pragma unroll
             for (int i = 0; i < RPW; ++i)
                 if (r0 + i < nrows) Pq[(int64_t)(r0 + i) * nq + q] = acc[h][i];
+        }
+    }
+}
+
+// Projection and descent in one kernel (Sec. II-C, Alg. 3): workgroup
+// (x, y) takes the query tile x (64 * QPL queries) and the trees
+// y * G .. y * G + G - 1, G = floor(8 * RPW / depth), i.e. their G * depth
+// projection rows, one RPW-row group per wave.  The projections go to LDS
+// (over the query tile, once every wave is done with it) instead of to
+// memory, and each thread then walks (tree, query) pairs of the group, three
+// descents interleaved, reading the split tables from memory.  Same
+// arithmetic as the two-kernel form: every projection is the same chain in
+// ascending feature order and the walk the same comparisons.
+template <int RPW, bool CHUNKED, int QPL, int MAXL>
+__global__ __launch_bounds__(kProjWaves * kWave) void project_route_kernel(
+    const float* __restrict__ Q, int64_t nq, int32_t d, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ col, const float* __restrict__ val, const float* __restrict__ splits, int32_t T,
+    int32_t depth, int32_t G, int32_t* __restrict__ leaf) {
+    extern __shared__ float proj_smem[];   // query tile, then [G * depth][64 * QPL] projections
+    constexpr int TQ = kWave * QPL;
+    const int lane = lane_id();
+    const int w = uniform((int)(threadIdx.x >> 6));
+    const int64_t q0 = (int64_t)blockIdx.x * TQ;
+    const int t0 = (int)blockIdx.y * G;
+    const int ng = T - t0 < G ? T - t0 : G;
+    const int row_begin = t0 * depth, row_end = (t0 + ng) * depth;
+    const int r0 = uniform(row_begin + w * RPW);
+    float acc[QPL][RPW];
+    project_accumulate<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, r0, row_end, q0, proj_smem, acc);
+    __syncthreads();                          // every wave is done with the query tile
+#pragma unroll
+    for (int h = 0; h < QPL; ++h)
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+            if (r0 + i < row_end) proj_smem[(r0 + i - row_begin) * TQ + h * kWave + lane] = acc[h][i];
+    __syncthreads();
+    const int nsplit = (1 << depth) - 1;
+    const int pairs = ng * TQ;
+    constexpr int kChains = 3;
+    for (int base = (int)threadIdx.x; base < pairs; base += kChains * kProjWaves * kWave) {
+        int node[kChains], g[kChains], qi[kChains];
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            const int i = base + c * kProjWaves * kWave;
+            g[c] = i < pairs ? i / TQ : 0;
+            qi[c] = i < pairs ? i - g[c] * TQ : 0;
+            node[c] = 0;
+        }
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) {
+            if (j < depth) {
+#pragma unroll
+                for (int c = 0; c < kChains; ++c) {
+                    const float sp = splits[(int64_t)(t0 + g[c]) * nsplit + node[c]];
+                    const float p = proj_smem[(g[c] * depth + j) * TQ + qi[c]];
+                    node[c] = (p <= sp) ? 2 * node[c] + 1 : 2 * node[c] + 2;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            const int i = base + c * kProjWaves * kWave;
+            const int64_t q = q0 + qi[c];
+            if (i < pairs && q < nq) leaf[q * T + t0 + g[c]] = node[c] - nsplit;
         }
     }
 }
@@ -697,6 +773,47 @@ namespace {
 hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
                             hipStream_t s, const LaunchCfg& cfg) {
     const int depth = ix->depth;
+    static_assert(kMaxDepth <= kProjWaves * 4, "a workgroup of 4-row waves holds one tree's rows");
+    if (depth >= 1) {
+        // the fused form: small batches take 4 rows per wave (more, shorter
+        // workgroups), large ones 16, with two queries per lane when d <= 128
+        const int d = ix->d;
+        const int64_t tiles64 = (nq + kWave - 1) / kWave;
+        const int g16 = std::max(1, kProjWaves * kProjRows / depth);
+        const bool small = cfg.proj_rows == 4 ||
+                           (cfg.proj_rows != kProjRows && tiles64 * ((ix->T + g16 - 1) / g16) < 512);
+        const bool chunked = d > kProjChunk;
+#define MRPT_PR_K(RPW, CH, QPL, ML)                                                                              \
+    do {                                                                                                        \
+        const int G = kProjWaves * (RPW) / depth;                                                               \
+        const size_t tile_b = (size_t)std::min(d, kProjChunk) * kQStride * 4 * (QPL);                           \
+        const size_t proj_b = (size_t)G * depth * kWave * (QPL) * 4;                                            \
+        const size_t lds = std::max(tile_b, proj_b);                                                            \
+        dim3 grid((unsigned)((nq + kWave * (QPL) - 1) / (kWave * (QPL))), (unsigned)((ix->T + G - 1) / G));   \
+        (void)hipFuncSetAttribute((const void*)project_route_kernel<RPW, CH, QPL, ML>,                          \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                        \
+        hipLaunchKernelGGL((project_route_kernel<RPW, CH, QPL, ML>), grid, dim3(kProjWaves * kWave), lds, s, Q,  \
+                           nq, d, ix->rowptr, ix->col, ix->val, ix->splits, ix->T, depth, G, leaf);             \
+    } while (0)
+#define MRPT_PR(RPW, CH, QPL)                         \
+    do {                                              \
+        if (depth <= 8) MRPT_PR_K(RPW, CH, QPL, 8);   \
+        else if (depth <= 12) MRPT_PR_K(RPW, CH, QPL, 12); \
+        else if (depth <= 16) MRPT_PR_K(RPW, CH, QPL, 16); \
+        else MRPT_PR_K(RPW, CH, QPL, 24);             \
+    } while (0)
+        if (small) {
+            if (chunked) MRPT_PR(4, true, 1);
+            else MRPT_PR(4, false, 1);
+        } else {
+            if (chunked) MRPT_PR(kProjRows, true, 1);
+            else if (d <= kProjPairMaxD) MRPT_PR(kProjRows, false, 2);
+            else MRPT_PR(kProjRows, false, 1);
+        }
+#undef MRPT_PR
+#undef MRPT_PR_K
+        return hipGetLastError();
+    }
     {
         hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s, cfg.proj_rows);
         if (e != hipSuccess) return e;
