@@ -87,21 +87,19 @@ mrpt_status check_query_args(const mrpt_index* ix, const float* Q, int64_t nq, i
 
 // bytes of a query workspace for nb queries at candidate cap `cap`; with
 // base given, also lays the workspace out there (leaf | s_ids | s_count |
-// flag | pq, each 256-byte aligned)
+// flag, each 256-byte aligned)
 size_t workspace_layout(const mrpt_index* ix, int64_t nb, int64_t cap, void* base, Workspace* ws) {
     const size_t leaf_b = ((size_t)nb * ix->T * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t ids_b = ((size_t)nb * (size_t)cap * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t cnt_b = ((size_t)nb * sizeof(int32_t) + 255) & ~size_t(255);
-    const size_t pq_b = (route_workspace_floats(ix, nb) * sizeof(float) + 255) & ~size_t(255);
     if (base && ws) {
         char* b = (char*)base;
         ws->leaf = (int32_t*)b;
         ws->s_ids = (int32_t*)(b + leaf_b);
         ws->s_count = (int32_t*)(b + leaf_b + ids_b);
         ws->flag = (int32_t*)(b + leaf_b + ids_b + cnt_b);
-        ws->pq = pq_b ? (float*)(b + leaf_b + ids_b + cnt_b + 256) : nullptr;
     }
-    return leaf_b + ids_b + cnt_b + 256 + pq_b;
+    return leaf_b + ids_b + cnt_b + 256;
 }
 
 // workspace for nb queries at candidate cap `cap` (caller holds ix->mu)
@@ -179,8 +177,7 @@ int64_t candidate_cap(const mrpt_index* ix, int32_t v) {
 }
 
 int64_t batch_size(const mrpt_index* ix, int64_t nq, int64_t cap) {
-    const int64_t per_q = (int64_t)(ix->T + cap + 1) * (int64_t)sizeof(int32_t) +
-                          (int64_t)route_workspace_floats(ix, 1) * (int64_t)sizeof(float);
+    const int64_t per_q = (int64_t)(ix->T + cap + 1) * (int64_t)sizeof(int32_t);
     const int64_t nb = std::max<int64_t>(1, (int64_t)workspace_limit() / per_q);
     return std::min(nq, nb);
 }
@@ -216,7 +213,7 @@ hipError_t enqueue_batch(const mrpt_index* ix, const Workspace& ws, const float*
     };
     hipError_t e;
     if ((e = mark(0)) != hipSuccess) return e;
-    if ((e = launch_route(ix, Qb, m, ws.leaf, ws.pq, s, cfg)) != hipSuccess) return e;
+    if ((e = launch_route(ix, Qb, m, ws.leaf, s, cfg)) != hipSuccess) return e;
     if ((e = mark(1)) != hipSuccess) return e;
     if ((e = launch_vote(ix, ws.leaf, m, v, ws.s_ids, cap, ws.s_count, s, cfg)) != hipSuccess) return e;
     if ((e = mark(2)) != hipSuccess) return e;
@@ -627,7 +624,7 @@ mrpt_status mrpt_debug_leaves(const mrpt_index* ix, const float* Q, int64_t nq, 
     MRPT_HIP_TRY(hipSetDevice(ix->device));
     MRPT_TRY(ensure_workspace(mix, nq, 1));
     MRPT_HIP_TRY(hipStreamWaitEvent(s, mix->ws.done, 0));
-    MRPT_HIP_TRY(launch_route(ix, Q, nq, leaf, mix->ws.pq, s));
+    MRPT_HIP_TRY(launch_route(ix, Q, nq, leaf, s));
     MRPT_HIP_TRY(hipEventRecord(mix->ws.done, s));
     return MRPT_OK;
 }
@@ -649,7 +646,7 @@ mrpt_status mrpt_debug_votes(const mrpt_index* cix, const float* Q, int64_t nq, 
     MRPT_HIP_TRY(hipSetDevice(ix->device));
     MRPT_TRY(ensure_workspace(ix, nq, 1));
     MRPT_HIP_TRY(hipStreamWaitEvent(s, ix->ws.done, 0));
-    MRPT_HIP_TRY(launch_route(ix, Q, nq, ix->ws.leaf, ix->ws.pq, s));
+    MRPT_HIP_TRY(launch_route(ix, Q, nq, ix->ws.leaf, s));
     MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, nq, v, s_ids, cap, s_count, s));
     if (s_votes) MRPT_HIP_TRY(launch_vote_counts(ix, ix->ws.leaf, nq, s_ids, cap, s_count, s_votes, s));
     MRPT_HIP_TRY(hipEventRecord(ix->ws.done, s));
@@ -679,7 +676,7 @@ mrpt_status mrpt_debug_prefilter(const mrpt_index* cix, const float* Q, int64_t 
     for (int64_t q0 = 0; q0 < nq; q0 += nb) {
         const int64_t m = std::min(nb, nq - q0);
         const float* Qb = Q + q0 * ix->d;
-        MRPT_HIP_TRY(launch_route(ix, Qb, m, ix->ws.leaf, ix->ws.pq, s));
+        MRPT_HIP_TRY(launch_route(ix, Qb, m, ix->ws.leaf, s));
         MRPT_HIP_TRY(launch_vote(ix, ix->ws.leaf, m, v, ix->ws.s_ids, cap, ix->ws.s_count, s));
         MRPT_HIP_TRY(launch_dist_prefilter(ix, o.precision == MRPT_FP8_RERANK ? 1 : 0, Qb, m, ix->ws.s_ids, cap,
                                            ix->ws.s_count, k, o.rerank_factor, o.recheck_rel, nullptr, nullptr, s,
@@ -956,16 +953,16 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
             return ws;
         };
         // device tables
-        struct RouteLaunch { int32_t form, rpw, qpl, max_d; int64_t blocks_p, blocks_r; };
+        struct RouteLaunch { int32_t form, rpw, qpl, max_d; int64_t blocks; };
         std::vector<RouteLaunch> rl;
         for (const Class& c : route_cls) {
             int64_t tiles = 0;
             for (int32_t gi : c.members) {
                 const Group& g = groups[gi];
                 const RouteGrid r16 = route_grid(g.ix, g.rows, 16, 1);
-                tiles += r16.nbx_p * r16.nby_p;
+                tiles += r16.nbx * r16.nby;
             }
-            RouteLaunch L{(int32_t)c.key, 0, 0, 0, 0, 0};
+            RouteLaunch L{(int32_t)c.key, 0, 0, 0, 0};
             route_shape(L.form, tiles, po.proj_rows, &L.rpw, &L.qpl);
             std::vector<RouteItem> items;
             for (int32_t gi : c.members) {
@@ -980,20 +977,16 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
                 it.col = g.ix->col;
                 it.val = g.ix->val;
                 it.splits = g.ix->splits;
-                it.Pq = ws.pq;
                 it.leaf = ws.leaf;
                 it.nq = g.rows;
-                it.blk0_p = L.blocks_p;
-                it.blk0_r = L.blocks_r;
-                it.nbx_p = rg.nbx_p;
-                it.nbx_r = rg.nbx_r;
+                it.blk0 = L.blocks;
+                it.nbx = rg.nbx;
                 it.d = g.ix->d;
-                it.nrows = g.ix->T * g.ix->depth;
                 it.T = g.ix->T;
                 it.depth = g.ix->depth;
+                it.pad_ = 0;
                 items.push_back(it);
-                L.blocks_p += rg.nbx_p * rg.nby_p;
-                L.blocks_r += rg.nbx_r * rg.nby_r;
+                L.blocks += rg.nbx * rg.nby;
                 L.max_d = std::max(L.max_d, g.ix->d);
             }
             MRPT_HIP_TRY(hipMemcpy(base + c.tab_off, items.data(), items.size() * sizeof(RouteItem),
@@ -1110,13 +1103,13 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
             stages[1].push_back([&, ci](hipStream_t x) {
                 return launch_route_multi(rl[ci].form, rl[ci].rpw, rl[ci].qpl, rl[ci].max_d,
                                           reinterpret_cast<const RouteItem*>(base + route_cls[ci].tab_off),
-                                          (int32_t)route_cls[ci].members.size(), rl[ci].blocks_p, rl[ci].blocks_r, x);
+                                          (int32_t)route_cls[ci].members.size(), rl[ci].blocks, x);
             });
         for (int32_t gi : route_alone)
             stages[1].push_back([&, gi](hipStream_t x) {
                 const Group& g = groups[gi];
                 const Workspace ws = call_ws(g);
-                return launch_route(g.ix, call_Q(g), g.rows, ws.leaf, ws.pq, x, cfg);
+                return launch_route(g.ix, call_Q(g), g.rows, ws.leaf, x, cfg);
             });
         for (size_t ci = 0; ci < vote_cls.size(); ++ci)
             stages[2].push_back([&, ci](hipStream_t x) {

@@ -1,15 +1,18 @@
-// Routing kernel: the sparse projection of a query tile onto the depth
-// vectors of a tree (Sec. II-C: one vector per tree level, so a query's
+// Routing kernels: the sparse projection of a query tile onto the depth
+// vectors of each tree (Sec. II-C: one vector per tree level, so a query's
 // T*depth projections form one sparse product) fused with the descent of
 // Alg. 3: at level j the query goes left when its projection is <= the node's
-// split (Sec. III), right otherwise.
+// split (Sec. III), right otherwise.  Every projection is a float32 fused
+// multiply-add chain in ascending feature order from +0.
 //
-// Layout of one workgroup: one wave per tree (trees_per_block trees), lanes =
-// 64 queries of a tile; the workgroup walks `tiles` consecutive query tiles so
-// the staged tables are reused.  LDS holds the split tables of its trees
-// (heap order), their CSR rows, and the current query tile transposed
-// ([feature][query], row stride 65 to spread the banks).  Every projection is
-// a float32 fused multiply-add chain in ascending feature order from +0.
+//  * project_route_kernel (every vector has at most 64 nonzeros, the usual
+//    case): a workgroup projects a 64- or 128-query tile on the rows of a
+//    group of trees, keeps the projections in LDS and walks those trees.
+//  * route_kernel (any vector length): one wave per tree (trees_per_block
+//    trees), lanes = 64 queries of a tile, `tiles` consecutive query tiles per
+//    workgroup so the staged tables are reused; LDS holds the split tables of
+//    its trees (heap order), their CSR rows, and the current query tile
+//    transposed ([feature][query], row stride 65 to spread the banks).
 #include "device_common.h"
 #include "mrpt_internal.h"
 
@@ -20,60 +23,6 @@ using namespace dev;
 
 constexpr int kQStride = 65;
 constexpr int kStageUnroll = 8;     // global loads in flight per thread while staging
-
-// split tables of trees t_first .. t_first+count-1 into LDS (heap order)
-__device__ __forceinline__ void stage_splits(const float* __restrict__ splits, float* sp, int T, int t_first,
-                                             int count, int nsplit) {
-    const int tid = (int)threadIdx.x, nthreads = (int)blockDim.x;
-    for (int tw = 0; tw < count; ++tw) {
-        const int tt = t_first + tw;
-        if (tt >= T) break;
-        const float* src = splits + (int64_t)tt * nsplit;
-        float* dst = sp + tw * nsplit;
-        for (int e0 = tid; e0 < nsplit; e0 += kStageUnroll * nthreads) {
-            float r[kStageUnroll];
-#pragma unroll
-            for (int u = 0; u < kStageUnroll; ++u) {
-                const int e = e0 + u * nthreads;
-                r[u] = e < nsplit ? src[e] : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < kStageUnroll; ++u) {
-                const int e = e0 + u * nthreads;
-                if (e < nsplit) dst[e] = r[u];
-            }
-        }
-    }
-}
-
-// the 64-query tile starting at q0 (contiguous rows of Q) into LDS as
-// qt[feature * 65 + query]; rows past nq read as zero
-__device__ __forceinline__ void stage_query_tile(const float* __restrict__ Q, int64_t q0, int64_t nq, int d,
-                                                 float* qt) {
-    const int tid = (int)threadIdx.x, nthreads = (int)blockDim.x;
-    const int total = kWave * d;
-    const int step_q = nthreads / d, step_f = nthreads - step_q * d;
-    int qq = tid / d, f = tid - qq * d;
-    const float* src = Q + q0 * d;
-    const int64_t rows_left = nq - q0;
-    for (int e0 = tid; e0 < total; e0 += kStageUnroll * nthreads) {
-        float r[kStageUnroll];
-        int rq[kStageUnroll], rf[kStageUnroll];
-#pragma unroll
-        for (int u = 0; u < kStageUnroll; ++u) {
-            const int e = e0 + u * nthreads;
-            rq[u] = qq;
-            rf[u] = f;
-            r[u] = (e < total && qq < rows_left) ? src[e] : 0.0f;
-            qq += step_q;
-            f += step_f;
-            if (f >= d) { f -= d; ++qq; }
-        }
-#pragma unroll
-        for (int u = 0; u < kStageUnroll; ++u)
-            if (e0 + u * nthreads < total) qt[rf[u] * kQStride + rq[u]] = r[u];
-    }
-}
 
 // features [c0, c0 + cw) of the 64-query tile starting at q0 into LDS as
 // qt[(feature - c0) * 65 + query]; rows past nq read as zero
@@ -225,110 +174,18 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q,
     }
 }
 
-// Fast form, used when every projection vector has at most 64 nonzeros: the
-// wave's tree keeps row j of its CSR in registers (lane e holds entry e of
-// the row) and all depth levels advance together, step k adding the k-th
-// nonzero of every row, so the depth fused multiply-add chains overlap; each
-// chain still runs in ascending feature order.  The query tile sits in LDS
-// whole ([feature][query]) when it fits (QLDS), else each lane reads its own
-// query row from memory.
-template <int MAXL, bool QLDS, bool SPLITS_LDS>
-__global__ __launch_bounds__(256) void route_fast_kernel(const float* __restrict__ Q, int64_t nq, int32_t d,
-                                                         const int32_t* __restrict__ rowptr,
-                                                         const int32_t* __restrict__ col,
-                                                         const float* __restrict__ val,
-                                                         const float* __restrict__ splits, int32_t T,
-                                                         int32_t depth, int32_t trees_per_block, int32_t tiles,
-                                                         int32_t* __restrict__ leaf) {
-    extern __shared__ float route_smem[];
-    const int nsplit = (1 << depth) - 1;
-    float* qt = route_smem;                                   // [d][65] when QLDS
-    float* sp = qt + (QLDS ? d * kQStride : 0);               // [trees_per_block][nsplit]
-    const int lane = lane_id();
-    const int w = uniform((int)(threadIdx.x >> 6));
-    const int t = uniform((int)blockIdx.y * trees_per_block + w);
-    const bool tree_ok = t < T;
-    const int t_first = (int)blockIdx.y * trees_per_block;
-
-    if constexpr (SPLITS_LDS) stage_splits(splits, sp, T, t_first, trees_per_block, nsplit);
-    int len[MAXL];
-    int colr[MAXL];
-    float valr[MAXL];
-    int maxlen = 0;
-#pragma unroll
-    for (int j = 0; j < MAXL; ++j) {
-        len[j] = 0;
-        colr[j] = 0;
-        valr[j] = 0.0f;
-        if (j < depth && tree_ok) {
-            const int b = uniform(rowptr[(int64_t)t * depth + j]);
-            len[j] = uniform(rowptr[(int64_t)t * depth + j + 1]) - b;
-            if (lane < len[j]) {
-                colr[j] = col[b + lane];
-                valr[j] = val[b + lane];
-            }
-            maxlen = len[j] > maxlen ? len[j] : maxlen;
-        }
-    }
-
-    for (int tile = 0; tile < tiles; ++tile) {
-        const int64_t q0 = ((int64_t)blockIdx.x * tiles + tile) * kWave;
-        if (q0 >= nq) break;
-        const int64_t q = q0 + lane;
-        if constexpr (QLDS) {
-            __syncthreads();
-            stage_query_tile(Q, q0, nq, d, qt);
-        }
-        __syncthreads();
-        const float* qrow = Q + (q < nq ? q : nq - 1) * d;
-        float acc[MAXL];
-#pragma unroll
-        for (int j = 0; j < MAXL; ++j) acc[j] = 0.0f;
-        for (int k = 0; k < maxlen; ++k) {
-#pragma unroll
-            for (int j = 0; j < MAXL; ++j) {
-                if (j < depth && k < len[j]) {
-                    const int c = read_lane_i(colr[j], k);
-                    const float v = read_lane_f(valr[j], k);
-                    float x;
-                    if constexpr (QLDS) x = qt[c * kQStride + lane];
-                    else x = qrow[c];
-                    acc[j] = __builtin_fmaf(x, v, acc[j]);
-                }
-            }
-        }
-        if (tree_ok && q < nq) {
-            int node = 0;
-#pragma unroll
-            for (int j = 0; j < MAXL; ++j) {
-                if (j < depth) {
-                    float s;
-                    if constexpr (SPLITS_LDS) s = sp[w * nsplit + node];
-                    else s = splits[(int64_t)t * nsplit + node];
-                    node = (acc[j] <= s) ? 2 * node + 1 : 2 * node + 2;
-                }
-            }
-            leaf[q * T + t] = node - nsplit;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Two-kernel form (every projection vector has at most 64 nonzeros).
+// Form for projection vectors of at most 64 nonzeros.
 //
-// project_kernel: Pq[r][q] = q . R_r for all T*depth rows r, i.e. the sparse
-// product of Sec. II-C for a batch of queries.  A workgroup takes a tile of
-// 64 * QPL queries (staged in LDS as [feature][query] when it fits) and
-// 8 waves x RPW rows; a wave keeps its RPW rows in registers (lane e holds
-// entry e) and advances them together, one nonzero per row per step, so
-// RPW * QPL fused multiply-add chains overlap while each runs in ascending
-// feature order.  The steps that every row has run without a branch.
-// Writes are coalesced along queries.
-//
-// route_pq_kernel: Alg. 3's descent for one tree and a range of queries, the
-// tree's split table staged in LDS once per workgroup; each thread first
-// loads the depth projections of its query (independent loads) and then
-// walks the table.
+// The projection Pq[r][q] = q . R_r (the sparse product of Sec. II-C): a
+// workgroup takes a tile of 64 * QPL queries (staged in LDS as
+// [feature][query]) and 8 waves x RPW rows; a wave keeps its RPW rows in
+// registers (lane e holds entry e) and advances them together, one nonzero
+// per row per step, so RPW * QPL fused multiply-add chains overlap while
+// each runs in ascending feature order.  The steps that every row has run
+// without a branch.  project_kernel writes the rows to memory (index build);
+// project_route_kernel keeps them in LDS and walks the trees (Alg. 3's
+// descent) in the same workgroup.
 // ---------------------------------------------------------------------------
 constexpr int kProjWaves = 8;
 
@@ -526,17 +383,25 @@ __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_
 // descents interleaved, reading the split tables from memory.  Same
 // arithmetic as the two-kernel form: every projection is the same chain in
 // ascending feature order and the walk the same comparisons.
+// trees per workgroup of the fused form: as many whole trees as the eight
+// waves' RPW-row groups hold (all trees when there is no level)
+__host__ __device__ constexpr int route_group_trees(int rpw, int depth, int T) {
+    return depth > 0 ? kProjWaves * rpw / depth : T;
+}
+
 template <int RPW, bool CHUNKED, int QPL, int MAXL>
-__global__ __launch_bounds__(kProjWaves * kWave) void project_route_kernel(
-    const float* __restrict__ Q, int64_t nq, int32_t d, const int32_t* __restrict__ rowptr,
-    const int32_t* __restrict__ col, const float* __restrict__ val, const float* __restrict__ splits, int32_t T,
-    int32_t depth, int32_t G, int32_t* __restrict__ leaf) {
-    extern __shared__ float proj_smem[];   // query tile, then [G * depth][64 * QPL] projections
+__device__ __forceinline__ void project_route_body(const float* __restrict__ Q, int64_t nq, int32_t d,
+                                                   const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col, const float* __restrict__ val,
+                                                   const float* __restrict__ splits, int32_t T, int32_t depth,
+                                                   int32_t* __restrict__ leaf, float* proj_smem, int64_t bx,
+                                                   int32_t by) {
     constexpr int TQ = kWave * QPL;
+    const int G = route_group_trees(RPW, depth, T);
     const int lane = lane_id();
     const int w = uniform((int)(threadIdx.x >> 6));
-    const int64_t q0 = (int64_t)blockIdx.x * TQ;
-    const int t0 = (int)blockIdx.y * G;
+    const int64_t q0 = bx * TQ;
+    const int t0 = by * G;
     const int ng = T - t0 < G ? T - t0 : G;
     const int row_begin = t0 * depth, row_end = (t0 + ng) * depth;
     const int r0 = uniform(row_begin + w * RPW);
@@ -581,6 +446,16 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_route_kernel(
     }
 }
 
+template <int RPW, bool CHUNKED, int QPL, int MAXL>
+__global__ __launch_bounds__(kProjWaves * kWave) void project_route_kernel(
+    const float* __restrict__ Q, int64_t nq, int32_t d, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ col, const float* __restrict__ val, const float* __restrict__ splits, int32_t T,
+    int32_t depth, int32_t* __restrict__ leaf) {
+    extern __shared__ float proj_smem[];   // query tile, then [G * depth][64 * QPL] projections
+    project_route_body<RPW, CHUNKED, QPL, MAXL>(Q, nq, d, rowptr, col, val, splits, T, depth, leaf, proj_smem,
+                                                blockIdx.x, (int32_t)blockIdx.y);
+}
+
 template <int RPW, bool CHUNKED, int QPL>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
                                                                      int32_t d, const int32_t* __restrict__ rowptr,
@@ -591,82 +466,29 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
     project_body<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, nrows, Pq, proj_smem, blockIdx.x, blockIdx.y);
 }
 
-template <int MAXL, bool SPLITS_LDS>
-__device__ __forceinline__ void route_pq_body(const float* __restrict__ Pq, int64_t nq,
-                                              const float* __restrict__ splits, int32_t T, int32_t depth,
-                                              int32_t q_per_block, int32_t* __restrict__ leaf, float* rsp,
-                                              const int64_t bx, const int32_t by) {
-    const int nsplit = (1 << depth) - 1;
-    const int t = by;
-    if constexpr (SPLITS_LDS) {
-        stage_splits(splits, rsp, T, t, 1, nsplit);
-        __syncthreads();
-    }
-    const float* tsp = splits + (int64_t)t * nsplit;
-    const int64_t qb = bx * q_per_block;
-    const int64_t qe = qb + q_per_block < nq ? qb + q_per_block : nq;
-    for (int64_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
-        float p[MAXL];
-#pragma unroll
-        for (int j = 0; j < MAXL; ++j)
-            p[j] = j < depth ? Pq[((int64_t)t * depth + j) * nq + q] : 0.0f;
-        int node = 0;
-#pragma unroll
-        for (int j = 0; j < MAXL; ++j) {
-            if (j < depth) {
-                float s;
-                if constexpr (SPLITS_LDS) s = rsp[node];
-                else s = tsp[node];
-                node = (p[j] <= s) ? 2 * node + 1 : 2 * node + 2;
-            }
-        }
-        leaf[q * T + t] = node - nsplit;
-    }
-}
-
-template <int MAXL, bool SPLITS_LDS>
-__global__ __launch_bounds__(256) void route_pq_kernel(const float* __restrict__ Pq, int64_t nq,
-                                                       const float* __restrict__ splits, int32_t T, int32_t depth,
-                                                       int32_t q_per_block, int32_t* __restrict__ leaf) {
-    extern __shared__ float rsp[];          // split table of this block's tree
-    route_pq_body<MAXL, SPLITS_LDS>(Pq, nq, splits, T, depth, q_per_block, leaf, rsp, blockIdx.x, blockIdx.y);
-}
-
 // the item of a multi-index launch that holds workgroup b (items ascending
 // by their first workgroup)
-__device__ __forceinline__ int32_t find_route_item(const RouteItem* __restrict__ items, int32_t nitems, int64_t b,
-                                                   bool second) {
+__device__ __forceinline__ int32_t find_route_item(const RouteItem* __restrict__ items, int32_t nitems, int64_t b) {
     int32_t lo = 0, hi = nitems - 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
-        if ((second ? items[mid].blk0_r : items[mid].blk0_p) <= b) lo = mid;
+        if (items[mid].blk0 <= b) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
 
-// projections of several query calls (indexes of one kernel form): workgroup
-// b is tile (x, y) of its item's own grid
-template <int RPW, bool CHUNKED, int QPL>
-__global__ __launch_bounds__(kProjWaves * kWave) void project_multi_kernel(const RouteItem* __restrict__ items,
-                                                                           int32_t nitems) {
+// projection and descent of several query calls in one launch: workgroup b
+// is (query tile, tree group) (x, y) of its item's own grid
+template <int RPW, bool CHUNKED, int QPL, int MAXL>
+__global__ __launch_bounds__(kProjWaves * kWave) void project_route_multi_kernel(const RouteItem* __restrict__ items,
+                                                                                 int32_t nitems) {
     extern __shared__ float proj_smem[];
-    const int32_t i = find_route_item(items, nitems, blockIdx.x, false);
+    const int32_t i = find_route_item(items, nitems, blockIdx.x);
     const RouteItem& it = items[i];
-    const int64_t r = (int64_t)blockIdx.x - it.blk0_p;
-    project_body<RPW, CHUNKED, QPL>(it.Q, it.nq, it.d, it.rowptr, it.col, it.val, it.nrows, it.Pq, proj_smem,
-                                    r % it.nbx_p, (int32_t)(r / it.nbx_p));
-}
-
-template <int MAXL, bool SPLITS_LDS>
-__global__ __launch_bounds__(256) void route_pq_multi_kernel(const RouteItem* __restrict__ items, int32_t nitems,
-                                                             int32_t q_per_block) {
-    extern __shared__ float rsp[];
-    const int32_t i = find_route_item(items, nitems, blockIdx.x, true);
-    const RouteItem& it = items[i];
-    const int64_t r = (int64_t)blockIdx.x - it.blk0_r;
-    route_pq_body<MAXL, SPLITS_LDS>(it.Pq, it.nq, it.splits, it.T, it.depth, q_per_block, it.leaf, rsp,
-                                    r % it.nbx_r, (int32_t)(r / it.nbx_r));
+    const int64_t r = (int64_t)blockIdx.x - it.blk0;
+    project_route_body<RPW, CHUNKED, QPL, MAXL>(it.Q, it.nq, it.d, it.rowptr, it.col, it.val, it.splits, it.T,
+                                                it.depth, it.leaf, proj_smem, r % it.nbx, (int32_t)(r / it.nbx));
 }
 
 }  // namespace
@@ -684,48 +506,6 @@ int lds_per_block_limit() {
 }
 
 namespace {
-
-hipError_t launch_route_fast(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s) {
-    const int depth = ix->depth;
-    const int nsplit = (1 << depth) - 1;
-    const int d = ix->d;
-    const size_t limit = (size_t)std::min(lds_per_block_limit(), 160 * 1024);
-    const size_t q_bytes = (size_t)d * kQStride * 4;
-    const bool qlds = q_bytes <= 96 * 1024;
-    int tpb = std::min(4, ix->T);
-    const size_t base = qlds ? q_bytes : 0;
-    while (tpb > 1 && base + (size_t)tpb * nsplit * 4 > limit) --tpb;
-    const bool spl = base + (size_t)tpb * nsplit * 4 <= limit;
-    const size_t lds = base + (spl ? (size_t)tpb * nsplit * 4 : 0);
-    const int64_t ntiles = (nq + kWave - 1) / kWave;
-    const int64_t tree_groups = (ix->T + tpb - 1) / tpb;
-    // several query tiles per workgroup (so each staged split table serves more
-    // queries) while keeping about 4 workgroups per CU
-    const int tiles = (int)std::max<int64_t>(1, std::min<int64_t>(8, ntiles * tree_groups / 1024));
-    dim3 grid((unsigned)((ntiles + tiles - 1) / tiles), (unsigned)tree_groups);
-    dim3 block(kWave * tpb);
-#define MRPT_ROUTE_F(ML, QL, SL)                                                                             \
-    do {                                                                                                     \
-        (void)hipFuncSetAttribute((const void*)route_fast_kernel<ML, QL, SL>,                                \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                     \
-        hipLaunchKernelGGL((route_fast_kernel<ML, QL, SL>), grid, block, lds, s, Q, nq, d, ix->rowptr, ix->col, \
-                           ix->val, ix->splits, ix->T, depth, tpb, tiles, leaf);                             \
-    } while (0)
-#define MRPT_ROUTE_FQ(ML)                                      \
-    do {                                                       \
-        if (qlds && spl) MRPT_ROUTE_F(ML, true, true);         \
-        else if (qlds) MRPT_ROUTE_F(ML, true, false);          \
-        else if (spl) MRPT_ROUTE_F(ML, false, true);           \
-        else MRPT_ROUTE_F(ML, false, false);                   \
-    } while (0)
-    if (depth <= 8) MRPT_ROUTE_FQ(8);
-    else if (depth <= 12) MRPT_ROUTE_FQ(12);
-    else if (depth <= 16) MRPT_ROUTE_FQ(16);
-    else MRPT_ROUTE_FQ(24);
-#undef MRPT_ROUTE_FQ
-#undef MRPT_ROUTE_F
-    return hipGetLastError();
-}
 
 constexpr int kProjRows = 16;     // rows per wave in project_kernel
 // at most this d, a lane of a large batch takes two queries: the tile
@@ -770,22 +550,23 @@ hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32
 
 namespace {
 
-hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
-                            hipStream_t s, const LaunchCfg& cfg) {
+// every projection vector with at most 64 nonzeros: projection and descent
+// in one launch of project_route_kernel
+hipError_t launch_route_fused(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s,
+                              const LaunchCfg& cfg) {
     const int depth = ix->depth;
     static_assert(kMaxDepth <= kProjWaves * 4, "a workgroup of 4-row waves holds one tree's rows");
-    if (depth >= 1) {
-        // the fused form: small batches take 4 rows per wave (more, shorter
-        // workgroups), large ones 16, with two queries per lane when d <= 128
-        const int d = ix->d;
-        const int64_t tiles64 = (nq + kWave - 1) / kWave;
-        const int g16 = std::max(1, kProjWaves * kProjRows / depth);
-        const bool small = cfg.proj_rows == 4 ||
-                           (cfg.proj_rows != kProjRows && tiles64 * ((ix->T + g16 - 1) / g16) < 512);
-        const bool chunked = d > kProjChunk;
+    // small batches take 4 rows per wave (more, shorter workgroups), large
+    // ones 16, with two queries per lane when d <= 128
+    const int d = ix->d;
+    const int64_t tiles64 = (nq + kWave - 1) / kWave;
+    const int g16 = route_group_trees(kProjRows, depth, ix->T);
+    const bool small = cfg.proj_rows == 4 ||
+                       (cfg.proj_rows != kProjRows && tiles64 * ((ix->T + g16 - 1) / g16) < 512);
+    const bool chunked = d > kProjChunk;
 #define MRPT_PR_K(RPW, CH, QPL, ML)                                                                              \
     do {                                                                                                        \
-        const int G = kProjWaves * (RPW) / depth;                                                               \
+        const int G = route_group_trees(RPW, depth, ix->T);                                                     \
         const size_t tile_b = (size_t)std::min(d, kProjChunk) * kQStride * 4 * (QPL);                           \
         const size_t proj_b = (size_t)G * depth * kWave * (QPL) * 4;                                            \
         const size_t lds = std::max(tile_b, proj_b);                                                            \
@@ -793,7 +574,7 @@ hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, in
         (void)hipFuncSetAttribute((const void*)project_route_kernel<RPW, CH, QPL, ML>,                          \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                        \
         hipLaunchKernelGGL((project_route_kernel<RPW, CH, QPL, ML>), grid, dim3(kProjWaves * kWave), lds, s, Q,  \
-                           nq, d, ix->rowptr, ix->col, ix->val, ix->splits, ix->T, depth, G, leaf);             \
+                           nq, d, ix->rowptr, ix->col, ix->val, ix->splits, ix->T, depth, leaf);                \
     } while (0)
 #define MRPT_PR(RPW, CH, QPL)                         \
     do {                                              \
@@ -802,62 +583,25 @@ hipError_t launch_route_two(const mrpt_index* ix, const float* Q, int64_t nq, in
         else if (depth <= 16) MRPT_PR_K(RPW, CH, QPL, 16); \
         else MRPT_PR_K(RPW, CH, QPL, 24);             \
     } while (0)
-        if (small) {
-            if (chunked) MRPT_PR(4, true, 1);
-            else MRPT_PR(4, false, 1);
-        } else {
-            if (chunked) MRPT_PR(kProjRows, true, 1);
-            else if (d <= kProjPairMaxD) MRPT_PR(kProjRows, false, 2);
-            else MRPT_PR(kProjRows, false, 1);
-        }
+    if (small) {
+        if (chunked) MRPT_PR(4, true, 1);
+        else MRPT_PR(4, false, 1);
+    } else {
+        if (chunked) MRPT_PR(kProjRows, true, 1);
+        else if (d <= kProjPairMaxD) MRPT_PR(kProjRows, false, 2);
+        else MRPT_PR(kProjRows, false, 1);
+    }
 #undef MRPT_PR
 #undef MRPT_PR_K
-        return hipGetLastError();
-    }
-    {
-        hipError_t e = launch_project(ix, Q, nq, 0, ix->T * depth, pq, s, cfg.proj_rows);
-        if (e != hipSuccess) return e;
-    }
-    const int nsplit = (1 << depth) - 1;
-    const size_t sp_bytes = (size_t)nsplit * 4;
-    const bool spl = sp_bytes <= (size_t)std::min(lds_per_block_limit(), 64 * 1024);
-    const int q_per_block = 2048;
-    dim3 grid((unsigned)((nq + q_per_block - 1) / q_per_block), (unsigned)ix->T);
-    const size_t lds = spl ? sp_bytes : 0;
-#define MRPT_RPQ(ML)                                                                                            \
-    do {                                                                                                        \
-        if (spl) {                                                                                              \
-            (void)hipFuncSetAttribute((const void*)route_pq_kernel<ML, true>,                                   \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
-            hipLaunchKernelGGL((route_pq_kernel<ML, true>), grid, dim3(256), lds, s, pq, nq, ix->splits, ix->T, \
-                               depth, q_per_block, leaf);                                                       \
-        } else {                                                                                                \
-            hipLaunchKernelGGL((route_pq_kernel<ML, false>), grid, dim3(256), 0, s, pq, nq, ix->splits, ix->T,  \
-                               depth, q_per_block, leaf);                                                       \
-        }                                                                                                       \
-    } while (0)
-    if (depth <= 8) MRPT_RPQ(8);
-    else if (depth <= 12) MRPT_RPQ(12);
-    else if (depth <= 16) MRPT_RPQ(16);
-    else MRPT_RPQ(24);
-#undef MRPT_RPQ
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t route_workspace_floats(const mrpt_index* ix, int64_t nq) {
-    if (ix->max_row_nnz > kWave) return 0;
-    return (size_t)nq * ix->T * ix->depth;   // the projections
-}
-
-hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
-                        hipStream_t s, const LaunchCfg& cfg) {
+hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s,
+                        const LaunchCfg& cfg) {
     if (nq == 0) return hipSuccess;
-    if (ix->max_row_nnz <= kWave) {
-        if (pq) return launch_route_two(ix, Q, nq, leaf, pq, s, cfg);
-        return launch_route_fast(ix, Q, nq, leaf, s);
-    }
+    if (ix->max_row_nnz <= kWave) return launch_route_fused(ix, Q, nq, leaf, s, cfg);
     const int depth = ix->depth;
     const int nsplit = (1 << depth) - 1;
     const int limit = std::min(lds_per_block_limit(), 80 * 1024);   // two workgroups per CU
@@ -902,18 +646,17 @@ hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_
     return hipGetLastError();
 }
 
-// Routing forms: 100 * projection class + split-walk class.  Projection
-// class 0: d <= 128 (two queries per lane in large launches), 1: the whole
-// tile in LDS, 2: chunked tiles.  Split-walk class (< 16): 4 * depth class +
-// 2 * (split table in LDS) (depth classes up to 8, 12, 16, 24 levels).
-constexpr int32_t encode_route_form(int pc, int dc, int spl) { return 100 * pc + 4 * dc + 2 * spl; }
+// Routing forms: 100 * projection class + depth class.  Projection class
+// 0: d <= 128 (two queries per lane in large launches), 1: the whole tile in
+// LDS, 2: chunked tiles.  Depth class 0..3: walks of up to 8, 12, 16, 24
+// levels.
+constexpr int32_t encode_route_form(int pc, int dc) { return 100 * pc + dc; }
 constexpr bool route_forms_decode() {
     for (int pc = 0; pc < 3; ++pc)
-        for (int dc = 0; dc < 4; ++dc)
-            for (int spl = 0; spl < 2; ++spl) {
-                const int32_t f = encode_route_form(pc, dc, spl);
-                if (f / 100 != pc || (f % 100) / 4 != dc || ((f % 100) & 2) / 2 != spl || f % 100 >= 16) return false;
-            }
+        for (int dc = 0; dc < 4; ++dc) {
+            const int32_t f = encode_route_form(pc, dc);
+            if (f / 100 != pc || f % 100 != dc) return false;
+        }
     return true;
 }
 static_assert(route_forms_decode(), "every routing form decodes to its classes");
@@ -923,14 +666,12 @@ int32_t route_form(const mrpt_index* ix) {
     const int d = ix->d, depth = ix->depth;
     const int pc = d <= kProjPairMaxD ? 0 : d <= kProjChunk ? 1 : 2;
     const int dc = depth <= 8 ? 0 : depth <= 12 ? 1 : depth <= 16 ? 2 : 3;
-    const size_t sp_bytes = (((size_t)1 << depth) - 1) * 4;
-    const int spl = sp_bytes <= (size_t)std::min(lds_per_block_limit(), 64 * 1024) ? 1 : 0;
-    return encode_route_form(pc, dc, spl);
+    return encode_route_form(pc, dc);
 }
 
-// the most levels of a routing form's split-walk class
+// the most levels of a routing form's depth class
 static int form_max_depth(int32_t form) {
-    const int dc = (form % 100) / 4;
+    const int dc = form % 100;
     return dc == 0 ? 8 : dc == 1 ? 12 : dc == 2 ? 16 : 24;
 }
 
@@ -949,64 +690,46 @@ RouteGrid route_grid(const mrpt_index* ix, int64_t nq, int32_t rpw, int32_t qpl)
     RouteGrid g;
     g.rpw = rpw;
     g.qpl = qpl;
-    const int nrows = ix->T * ix->depth;
-    g.nbx_p = (nq + kWave * qpl - 1) / (kWave * qpl);
-    g.nby_p = (nrows + kProjWaves * rpw - 1) / (kProjWaves * rpw);
-    const int q_per_block = 2048;
-    g.nbx_r = (nq + q_per_block - 1) / q_per_block;
-    g.nby_r = ix->T;
+    const int G = route_group_trees(rpw, ix->depth, ix->T);
+    g.nbx = (nq + kWave * qpl - 1) / (kWave * qpl);
+    g.nby = (ix->T + G - 1) / G;
     return g;
 }
 
 hipError_t launch_route_multi(int32_t form, int32_t rpw, int32_t qpl, int32_t max_d, const RouteItem* items,
-                              int32_t nitems, int64_t blocks_p, int64_t blocks_r, hipStream_t s) {
+                              int32_t nitems, int64_t blocks, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    const int pc = form / 100, rc = form % 100;
-    if (pc > 2 || rc >= 16) return hipErrorInvalidValue;
+    const int pc = form / 100, dc = form % 100;
+    if (pc > 2 || dc > 3) return hipErrorInvalidValue;
     const bool chunked = pc == 2;
-#define MRPT_PROJM(RPW, CH, QPL)                                                                              \
-    do {                                                                                                     \
-        const size_t lds = (size_t)std::min(max_d, kProjChunk) * kQStride * 4 * (QPL);                       \
-        (void)hipFuncSetAttribute((const void*)project_multi_kernel<RPW, CH, QPL>,                           \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                     \
-        hipLaunchKernelGGL((project_multi_kernel<RPW, CH, QPL>), dim3((unsigned)blocks_p),                   \
-                           dim3(kProjWaves * kWave), lds, s, items, nitems);                                 \
+    // LDS: the largest query tile of the class, or the most projections a
+    // workgroup keeps (8 * RPW rows of 64 * QPL queries)
+#define MRPT_PRM_K(RPW, CH, QPL, ML)                                                                            \
+    do {                                                                                                       \
+        const size_t lds = std::max((size_t)std::min(max_d, kProjChunk) * kQStride * 4 * (QPL),                \
+                                    (size_t)kProjWaves * (RPW) * kWave * (QPL) * 4);                           \
+        (void)hipFuncSetAttribute((const void*)project_route_multi_kernel<RPW, CH, QPL, ML>,                   \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                       \
+        hipLaunchKernelGGL((project_route_multi_kernel<RPW, CH, QPL, ML>), dim3((unsigned)blocks),             \
+                           dim3(kProjWaves * kWave), lds, s, items, nitems);                                   \
+    } while (0)
+#define MRPT_PRM(RPW, CH, QPL)                             \
+    do {                                                   \
+        if (dc == 0) MRPT_PRM_K(RPW, CH, QPL, 8);          \
+        else if (dc == 1) MRPT_PRM_K(RPW, CH, QPL, 12);    \
+        else if (dc == 2) MRPT_PRM_K(RPW, CH, QPL, 16);    \
+        else MRPT_PRM_K(RPW, CH, QPL, 24);                 \
     } while (0)
     if (rpw == 4) {
-        if (chunked) MRPT_PROJM(4, true, 1);
-        else MRPT_PROJM(4, false, 1);
+        if (chunked) MRPT_PRM(4, true, 1);
+        else MRPT_PRM(4, false, 1);
     } else {
-        if (chunked) MRPT_PROJM(kProjRows, true, 1);
-        else if (qpl == 2) MRPT_PROJM(kProjRows, false, 2);
-        else MRPT_PROJM(kProjRows, false, 1);
+        if (chunked) MRPT_PRM(kProjRows, true, 1);
+        else if (qpl == 2) MRPT_PRM(kProjRows, false, 2);
+        else MRPT_PRM(kProjRows, false, 1);
     }
-#undef MRPT_PROJM
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int dc = rc / 4;
-    const bool spl = (rc & 2) != 0;
-    // the largest split table of the class (its depth class bound)
-    const int maxdepth = form_max_depth(form);
-    const size_t lds = spl ? (((size_t)1 << maxdepth) - 1) * 4 : 0;
-    const int q_per_block = 2048;
-#define MRPT_RPQM(ML)                                                                                        \
-    do {                                                                                                     \
-        if (spl) {                                                                                           \
-            const size_t l = std::min(lds, (size_t)64 * 1024);                                               \
-            (void)hipFuncSetAttribute((const void*)route_pq_multi_kernel<ML, true>,                          \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)l);                   \
-            hipLaunchKernelGGL((route_pq_multi_kernel<ML, true>), dim3((unsigned)blocks_r), dim3(256), l, s,   \
-                               items, nitems, q_per_block);                                                  \
-        } else {                                                                                             \
-            hipLaunchKernelGGL((route_pq_multi_kernel<ML, false>), dim3((unsigned)blocks_r), dim3(256), 0, s,  \
-                               items, nitems, q_per_block);                                                  \
-        }                                                                                                    \
-    } while (0)
-    if (dc == 0) MRPT_RPQM(8);
-    else if (dc == 1) MRPT_RPQM(12);
-    else if (dc == 2) MRPT_RPQM(16);
-    else MRPT_RPQM(24);
-#undef MRPT_RPQM
+#undef MRPT_PRM
+#undef MRPT_PRM_K
     return hipGetLastError();
 }
 

@@ -54,7 +54,6 @@ struct Workspace {
     int32_t* s_ids = nullptr;    // nb x cap
     int32_t* s_count = nullptr;  // nb
     int32_t* flag = nullptr;     // 1 int
-    float* pq = nullptr;         // nb x T*depth projections (two-kernel routing)
     void* base = nullptr;
     size_t bytes = 0;
     hipEvent_t done = nullptr;   // recorded after the last kernel that used it
@@ -142,11 +141,9 @@ struct LaunchCfg {
 // P[r * m + i] (the float32 fused multiply-add chain of Sec. II-C)
 hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32_t row0, int32_t nrows, float* P,
                           hipStream_t s, int32_t rows_per_wave = 0);
-// pq: scratch of route_workspace_floats(ix, nq) floats for the projections
-// (nullptr selects the fused single-kernel form)
-size_t route_workspace_floats(const mrpt_index* ix, int64_t nq);
-hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, float* pq,
-                        hipStream_t s, const LaunchCfg& cfg = LaunchCfg());
+// leaf numbers leaf[q * T + t] of the nq queries of Q (Alg. 3)
+hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s,
+                        const LaunchCfg& cfg = LaunchCfg());
 hipError_t launch_vote(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v,
                        int32_t* s_ids, int64_t cap, int32_t* s_count, hipStream_t s,
                        const LaunchCfg& cfg = LaunchCfg());
@@ -216,40 +213,37 @@ hipError_t launch_vote_multi(int64_t form, int32_t map_words, int64_t qcap, cons
 hipError_t launch_vote_recount(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
                                int64_t cap, int32_t* s_count, hipStream_t s);
 
-// routing (projection kernel, then the split walk): one item per call, the
-// workgroups of its two grids flattened (x fastest)
+// routing (projection and split walk in one kernel): one item per call, the
+// workgroups of its grid (query tiles x tree groups) flattened (x fastest)
 struct RouteItem {
     const float* Q;              // the call's queries
     const int32_t* rowptr;       // its index's projection vectors (CSR)
     const int32_t* col;
     const float* val;
     const float* splits;         // its split tables
-    float* Pq;                   // projections workspace (nrows x nq)
     int32_t* leaf;               // leaf numbers (nq x T)
     int64_t nq;
-    int64_t blk0_p, blk0_r;      // first workgroup in the projection / split-walk launch
-    int64_t nbx_p, nbx_r;        // workgroups along the queries in each grid
-    int32_t d, nrows, T, depth;
+    int64_t blk0;                // first workgroup of the call in the launch
+    int64_t nbx;                 // workgroups along the queries
+    int32_t d, T, depth, pad_;
 };
-// the routing form of a call's index (equal forms can share the two
-// launches), -1 without a multi-index form (vectors over 64 nonzeros)
+// the routing form of a call's index (equal forms can share the launch),
+// -1 without a multi-index form (vectors over 64 nonzeros)
 int32_t route_form(const mrpt_index* ix);
-// the routing kernels of `form` serve this index (its depth within the form's
-// split-walk class): checked for every item before a launch is recorded
+// the routing kernel of `form` serves this index (its depth within the
+// form's depth class): checked for every item before a launch is recorded
 bool route_form_holds(int32_t form, const mrpt_index* ix);
-// grid of a call in the projection launch (rows_per_wave: 0 = by the launch's
-// total size, as launch_project decides) and in the split walk
+// grid of a call in the routing launch: query tiles x tree groups
 struct RouteGrid {
     int32_t rpw, qpl;            // projection rows per wave, queries per lane
-    int64_t nbx_p, nby_p;        // projection grid
-    int64_t nbx_r, nby_r;        // split-walk grid
+    int64_t nbx, nby;
 };
 RouteGrid route_grid(const mrpt_index* ix, int64_t nq, int32_t rpw, int32_t qpl);
 // the launch-wide projection shape of a form for a set of calls: rows per
-// wave and queries per lane (total_tiles: their tiles at 16 rows per wave)
+// wave and queries per lane (total_tiles: their workgroups at 16 rows per wave)
 void route_shape(int32_t form, int64_t total_tiles, int32_t rows_per_wave, int32_t* rpw, int32_t* qpl);
 hipError_t launch_route_multi(int32_t form, int32_t rpw, int32_t qpl, int32_t max_d, const RouteItem* items,
-                              int32_t nitems, int64_t blocks_p, int64_t blocks_r, hipStream_t s);
+                              int32_t nitems, int64_t blocks, hipStream_t s);
 
 // the search kernel form of a call (calls of equal form can share a launch),
 // or -1 when the call's form has no multi-index kernel (its own launch then);
