@@ -425,33 +425,79 @@ __global__ __launch_bounds__(kVoteBlock) void vote_dir_kernel(
                 }
             }
             __syncthreads();
-            for (int j2 = w, u2 = 0; j2 < T;) {   // wave-uniform: every lane takes part
-                int32_t sid[kDirWindows];
+            // this wave's slices (trees w, w + 16, ...; at most 16): lane j
+            // holds slice j's start and length and, after an inclusive scan,
+            // the end of its windows in the wave's window sequence
+            const int ntw = T > w ? (T - w + kVoteWaves - 1) / kVoteWaves : 0;
+            int64_t sbase = 0;
+            int slen = 0, nwin = 0;
+            if (lane < ntw) {
+                const int t = w + kVoteWaves * lane;
+                sbase = tslice[t];
+                slen = tlen[t];
+                nwin = (slen + kWave - 1) / kWave;
+            }
+            int wend = nwin;
 #pragma unroll
-                for (int b = 0; b < kDirWindows; ++b) {
-                    sid[b] = -1;
-                    if (j2 < T) {
-                        const int len = uniform(tlen[j2]);
-                        const int e = u2 * kWave + lane;
-                        const int32_t x = perm[tslice[j2] + e];
-                        if (e < len) sid[b] = x;
-                        ++u2;
-                        if (u2 * kWave >= len) { u2 = 0; j2 += kVoteWaves; }
-                    }
-                }
-                uint32_t ob[kDirWindows];    // nonzero: this occurrence is the v-th
+            for (int o = 1; o < kVoteWaves; o <<= 1) {
+                const int y = __shfl_up(wend, o);
+                if (lane >= o) wend += y;
+            }
+            const int nwin_all = __builtin_amdgcn_readlane(wend, kVoteWaves - 1);
+            for (int r0 = 0; r0 < nwin_all; r0 += kWave) {   // wave-uniform
+                // lane s describes window r0 + s: its slice j (the number of
+                // slices that end at or before it) and its place in the slice
+                const int wi = r0 + lane;
+                int j = 0;
 #pragma unroll
-                for (int b = 0; b < kDirWindows; ++b) {
-                    // (every id of a slice lies in [lo, hi); the bound keeps the
-                    // counter index inside the array regardless)
-                    const uint32_t rel = (uint32_t)(sid[b] - lo);
-                    ob[b] = 0u;
-                    if (sid[b] >= 0 && rel < (uint32_t)chunk) {
-                        const uint32_t sh = (rel & 3u) * 8u;
-                        ob[b] = ((atomicAdd(&vote_cnt[rel >> 2], 1u << sh) >> sh) & 0xffu) == hit ? 1u : 0u;
+                for (int jj = 0; jj < kVoteWaves; ++jj) j += __builtin_amdgcn_readlane(wend, jj) <= wi ? 1 : 0;
+                const int jc = j < kVoteWaves ? j : kVoteWaves - 1;
+                const int64_t b0 = __shfl(sbase, jc);
+                const int l0 = __shfl(slen, jc);
+                const int k0 = wi - (__shfl(wend, jc) - __shfl(nwin, jc));
+                const int64_t first = b0 + (int64_t)k0 * kWave;
+                const int first_lo = (int)(uint32_t)first, first_hi = (int)(first >> 32);
+                const int avail_v = wi < nwin_all ? min(kWave, l0 - k0 * kWave) : 0;
+                const int nw = nwin_all - r0 < kWave ? nwin_all - r0 : kWave;
+                // windows g0 .. g0 + 15 of this round into dst: their ids, or
+                // -1; a window reads at most 63 entries past its slice, which
+                // stay inside the tree's perm row
+                auto load = [&](int32_t (&dst)[kDirWindows], int g0) {
+#pragma unroll
+                    for (int b = 0; b < kDirWindows; ++b) {
+                        dst[b] = -1;
+                        if (g0 + b < nw) {   // wave-uniform
+                            const int64_t f = ((int64_t)__builtin_amdgcn_readlane(first_hi, g0 + b) << 32) |
+                                              (uint32_t)__builtin_amdgcn_readlane(first_lo, g0 + b);
+                            const int avail = __builtin_amdgcn_readlane(avail_v, g0 + b);
+                            const int32_t x = perm[f + lane];
+                            if (lane < avail) dst[b] = x;
+                        }
                     }
+                };
+                // count the windows in `cur` while the next 16 load into `nxt`
+                auto count = [&](int32_t (&cur)[kDirWindows], int32_t (&nxt)[kDirWindows], int g0) -> bool {
+                    const bool more = g0 + kDirWindows < nw;
+                    if (more) load(nxt, g0 + kDirWindows);
+                    uint32_t ob[kDirWindows];    // nonzero: this occurrence is the v-th
+#pragma unroll
+                    for (int b = 0; b < kDirWindows; ++b) {
+                        // (every id of a slice lies in [lo, hi); the bound keeps
+                        // the counter index inside the array regardless)
+                        const uint32_t rel = (uint32_t)(cur[b] - lo);
+                        ob[b] = 0u;
+                        if (cur[b] >= 0 && rel < (uint32_t)chunk) {
+                            const uint32_t sh = (rel & 3u) * 8u;
+                            ob[b] = ((atomicAdd(&vote_cnt[rel >> 2], 1u << sh) >> sh) & 0xffu) == hit ? 1u : 0u;
+                        }
+                    }
+                    append_batch<true, kDirWindows>(ob, cur, INT32_MAX, &nsel, spare, out, cap32);
+                    return more;
+                };
+                int32_t sa[kDirWindows], sb[kDirWindows];
+                load(sa, 0);
+                for (int g0 = 0; count(sa, sb, g0) && count(sb, sa, g0 + kDirWindows); g0 += 2 * kDirWindows) {
                 }
-                append_batch<true, kDirWindows>(ob, sid, INT32_MAX, &nsel, spare, out, cap32);
             }
         }
         __syncthreads();
