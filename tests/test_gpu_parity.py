@@ -211,6 +211,32 @@ def test_large_batch_projection_tiles(nq, d):
     g.close()
 
 
+@pytest.mark.parametrize("nq", [5, 700])
+def test_query_rows_not_16_byte_aligned(nq):
+    """Q starting 4 bytes past a 16-byte boundary (d = 128, a multiple of 4):
+    the projection stages the tile with 4-byte loads instead of 16-byte ones,
+    and the leaves still equal the oracle's."""
+    _print_case(f"misaligned Q nq={nq}")
+    d = 128
+    rng = np.random.default_rng(nq)
+    X = rng.standard_normal((6000, d)).astype(np.float32)
+    Q = rng.standard_normal((nq, d)).astype(np.float32)
+    T, depth, a, seed = 12, 7, 1 / np.sqrt(d), 19
+    orc = oracle.build_index(X, T, depth, a, seed)
+    g = build(X, T, depth, a, seed)
+    try:
+        flat = torch.empty(nq * d + 4, dtype=torch.float32, device="cuda")
+        Qm = flat[1:1 + nq * d].view(nq, d)
+        Qm.copy_(dev(Q))
+        assert Qm.data_ptr() % 16 == 4
+        assert np.array_equal(leaves(g, Qm), oracle.route(orc, Q))
+        gi, gd, sc = query(g, Qm, 10, 2)
+        ref = oracle.query(orc, Q, 10, 2)
+        assert np.array_equal(sc, ref["s_count"])
+    finally:
+        g.close()
+
+
 @pytest.mark.parametrize("d", [1, 3, 4, 13, 36, 64, 200, 520])
 def test_dimensions_generic_and_vector_kernels(d):
     _print_case(f"dim d={d}")
