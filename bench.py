@@ -381,6 +381,7 @@ def main():
         "build_s": round(build_s, 3),
         "build": {"device_s": round(build["device"], 3),
                   "host_s": round(build["host"], 2) if "host" in build else None,
+                  "built_on_device": bool(ix.info.built_on_device), "max_row_nnz": int(ix.info.max_row_nnz),
                   # projection work of the build: n * (nonzeros of all T*depth vectors) multiply-adds
                   "projection_fma": int(w.n) * nnz,
                   "note": "device: projection kernel + per-level segmented sort; host: threads over trees"},

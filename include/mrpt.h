@@ -89,6 +89,10 @@ typedef struct {
     int32_t max_leaf;      /* ceil(n / 2^depth) */
     int32_t id_chunk;      /* ids per vote-counting pass of the query kernels */
     int64_t device_bytes;  /* device memory held by the index (without workspace) */
+    int32_t built_on_device; /* 1: the trees were grown on the GPU; 0: on host threads
+                              (asked for, or a projection vector has more than 64
+                              nonzeros, which the GPU build does not take) */
+    int32_t max_row_nnz;   /* nonzeros of the longest projection vector */
 } mrpt_index_desc;
 
 /* Build the index (paper Alg. 1 grow_trees, Alg. 2 grow_tree; Sec. II-B sparse

@@ -574,6 +574,8 @@ mrpt_status mrpt_index_info(const mrpt_index* ix, mrpt_index_desc* out) {
     out->max_leaf = ix->max_leaf;
     out->id_chunk = ix->id_chunk;
     out->device_bytes = ix->device_bytes;
+    out->built_on_device = ix->built_on_device;
+    out->max_row_nnz = ix->max_row_nnz;
     return MRPT_OK;
 }
 

@@ -39,7 +39,8 @@ class mrpt_build_opts(ctypes.Structure):
 class mrpt_index_desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("T", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("a", ctypes.c_float), ("seed", ctypes.c_uint64), ("nnz", ctypes.c_int64),
-                ("max_leaf", ctypes.c_int32), ("id_chunk", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("max_leaf", ctypes.c_int32), ("id_chunk", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("built_on_device", ctypes.c_int32), ("max_row_nnz", ctypes.c_int32)]
 
 
 class mrpt_batch(ctypes.Structure):

@@ -34,6 +34,10 @@ def test_binding_structs_match_header_layout():
     # int32 precision, int32 rerank_factor, float recheck_rel, int32 check_finite,
     # then two pointers (8-byte aligned)
     assert ctypes.sizeof(mrpt.mrpt_query_opts) == 16 + 8 + 8
+    # n; d, T, depth; a; seed; nnz; max_leaf, id_chunk; device_bytes;
+    # built_on_device, max_row_nnz
+    assert ctypes.sizeof(mrpt.mrpt_index_desc) == 8 + 12 + 4 + 8 + 8 + 8 + 8 + 8
+    assert mrpt.mrpt_index_desc.built_on_device.offset == 56
     assert mrpt.mrpt_query_opts.s_count.offset == 16
     assert mrpt.mrpt_query_opts.stage_events.offset == 24
 

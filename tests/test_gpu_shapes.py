@@ -37,6 +37,10 @@ def _compare(X, Q, T, depth, a, seed, k, v):
     try:
         rowptr, _, _ = mrpt.mrpt_export_projection(g.handle)
         most = int(np.diff(rowptr).max())
+        # the index reports its longest vector and where its trees were grown
+        # (the GPU build takes vectors of at most 64 nonzeros)
+        assert g.info.max_row_nnz == most
+        assert g.info.built_on_device == (1 if most <= 64 else 0)
         Qd = dev(Q)
         assert np.array_equal(leaves(g, Qd), oracle.route(orc, Q))
         ref = oracle.query(orc, Q, k, v, want_sets=True)
