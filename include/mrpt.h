@@ -90,8 +90,7 @@ typedef struct {
     int32_t id_chunk;      /* ids per vote-counting pass of the query kernels */
     int64_t device_bytes;  /* device memory held by the index (without workspace) */
     int32_t built_on_device; /* 1: the trees were grown on the GPU; 0: on host threads
-                              (asked for, or a projection vector has more than 64
-                              nonzeros, which the GPU build does not take) */
+                              (mrpt_build_opts.on_device = 0) */
     int32_t max_row_nnz;   /* nonzeros of the longest projection vector */
 } mrpt_index_desc;
 
@@ -111,11 +110,9 @@ typedef struct {
     int32_t on_device;     /* 1 (default): grow the trees on the GPU (data projected by the
                               query path's projection kernel, every level cut by a segmented
                               sort of (projection, id) keys); 0: on host threads.  Both give
-                              bit-identical trees.  The GPU build needs every projection
-                              vector to have at most 64 nonzeros (else the host build runs)
-                              and takes scratch device memory of about n*(4*depth + 16) bytes
-                              per tree of a group (groups sized to MRPT_BUILD_LIMIT bytes,
-                              default 8 GiB). */
+                              bit-identical trees.  The GPU build takes scratch device memory
+                              of about n*(4*depth + 16) bytes per tree of a group (groups
+                              sized to MRPT_BUILD_LIMIT bytes, default 8 GiB). */
     int32_t exact_nnz;     /* 0 (default): each entry of a projection vector is nonzero with
                               probability a (Sec. II-B).  1: every vector has exactly
                               m = ceil(a*d) nonzeros (the variant of the Sec. II-D footnote):

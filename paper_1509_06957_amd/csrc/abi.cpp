@@ -466,13 +466,10 @@ mrpt_status mrpt_build_ex(const float* data, int64_t n, int32_t d, int32_t T, in
     }
 
     generate_projection(d, T, depth, a, seed, bo.exact_nnz != 0, ix->h_rowptr, ix->h_col, ix->h_val);
-    for (int32_t t = 0; t < T; ++t)
-        ix->max_tree_nnz = std::max(ix->max_tree_nnz, ix->h_rowptr[(size_t)(t + 1) * depth] -
-                                                        ix->h_rowptr[(size_t)t * depth]);
     for (size_t r = 0; r + 1 < ix->h_rowptr.size(); ++r)
         ix->max_row_nnz = std::max(ix->max_row_nnz, ix->h_rowptr[r + 1] - ix->h_rowptr[r]);
-    // the GPU build projects with the query path's kernel (<= 64 nonzeros per vector)
-    const bool on_device = bo.on_device != 0 && ix->max_row_nnz <= 64;
+    // the GPU build projects the data with the query path's projection kernel
+    const bool on_device = bo.on_device != 0;
     ix->built_on_device = on_device ? 1 : 0;
     HostTrees trees;
     if (on_device) {

@@ -1,18 +1,14 @@
-// Routing kernels: the sparse projection of a query tile onto the depth
+// Routing kernel: the sparse projection of a query tile onto the depth
 // vectors of each tree (Sec. II-C: one vector per tree level, so a query's
 // T*depth projections form one sparse product) fused with the descent of
 // Alg. 3: at level j the query goes left when its projection is <= the node's
 // split (Sec. III), right otherwise.  Every projection is a float32 fused
 // multiply-add chain in ascending feature order from +0.
 //
-//  * project_route_kernel (every vector has at most 64 nonzeros, the usual
-//    case): a workgroup projects a 64- or 128-query tile on the rows of a
-//    group of trees, keeps the projections in LDS and walks those trees.
-//  * route_kernel (any vector length): one wave per tree (trees_per_block
-//    trees), lanes = 64 queries of a tile, `tiles` consecutive query tiles per
-//    workgroup so the staged tables are reused; LDS holds the split tables of
-//    its trees (heap order), their CSR rows, and the current query tile
-//    transposed ([feature][query], row stride 65 to spread the banks).
+// project_route_kernel: a workgroup projects a 64- or 128-query tile on the
+// rows of a group of trees, keeps the projections in LDS and walks those
+// trees.  project_kernel is its projection half alone, writing the rows to
+// memory (the index build projects the data with it).
 #include "device_common.h"
 #include "mrpt_internal.h"
 
@@ -53,136 +49,14 @@ __device__ __forceinline__ void stage_query_chunk(const float* __restrict__ Q, i
     }
 }
 
-template <int MAXL, bool CSR_LDS, bool SPLITS_LDS>
-__global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Q, int64_t nq, int32_t d,
-                                                    const int32_t* __restrict__ rowptr,
-                                                    const int32_t* __restrict__ col,
-                                                    const float* __restrict__ val,
-                                                    const float* __restrict__ splits, int32_t T,
-                                                    int32_t depth, int32_t trees_per_block, int32_t tiles,
-                                                    int32_t fb_size, int32_t splits_in_lds, int32_t csr_cap,
-                                                    int32_t* __restrict__ leaf) {
-    extern __shared__ float route_smem[];
-    const int nsplit = (1 << depth) - 1;
-    float* qt = route_smem;                                   // [fb_size][65]
-    float* sp = qt + fb_size * kQStride;                      // [trees_per_block][nsplit] (if staged)
-    float* cv = sp + (splits_in_lds ? trees_per_block * nsplit : 0);  // [trees_per_block][csr_cap]
-    int32_t* cc = reinterpret_cast<int32_t*>(cv + trees_per_block * csr_cap);
-    const int lane = lane_id();
-    const int w = uniform((int)(threadIdx.x >> 6));
-    const int t = uniform((int)blockIdx.y * trees_per_block + w);
-    const bool tree_ok = t < T;
-    const int nthreads = (int)blockDim.x;
-    const int t_first = (int)blockIdx.y * trees_per_block;
-
-    // stage split tables and CSR rows of this block's trees
-    if constexpr (SPLITS_LDS) {
-        for (int i = (int)threadIdx.x; i < trees_per_block * nsplit; i += nthreads) {
-            const int tw = i / nsplit;
-            const int tt = t_first + tw;
-            sp[i] = tt < T ? splits[(int64_t)tt * nsplit + (i - tw * nsplit)] : 0.0f;
-        }
-    }
-    const int row0 = tree_ok ? uniform(rowptr[(int64_t)t * depth]) : 0;
-    const int row_end = tree_ok ? uniform(rowptr[(int64_t)(t + 1) * depth]) : 0;
-    if constexpr (CSR_LDS) {
-        for (int i = (int)threadIdx.x; i < trees_per_block * csr_cap; i += nthreads) {
-            const int tw = i / csr_cap, e = i - tw * csr_cap;
-            const int tt = t_first + tw;
-            float vv = 0.0f;
-            int32_t c = 0;
-            if (tt < T) {
-                const int b = rowptr[(int64_t)tt * depth];
-                if (b + e < rowptr[(int64_t)(tt + 1) * depth]) {
-                    vv = val[b + e];
-                    c = col[b + e];
-                }
-            }
-            cv[i] = vv;
-            cc[i] = c;
-        }
-    }
-    // entry p of this tree (row0 <= p < row_end) sits at LDS index p - row0 + w*csr_cap;
-    // the index is formed in integers so the LDS address never leaves the array
-    const int lds_shift = w * csr_cap - row0;
-
-    int rp[MAXL + 1];
-#pragma unroll
-    for (int j = 0; j <= MAXL; ++j) rp[j] = (j <= depth && tree_ok) ? uniform(rowptr[(int64_t)t * depth + j]) : 0;
-    (void)row_end;
-
-    for (int tile = 0; tile < tiles; ++tile) {
-        const int64_t q0 = ((int64_t)blockIdx.x * tiles + tile) * kWave;
-        if (q0 >= nq) break;
-        float acc[MAXL];
-        int ptr[MAXL];
-#pragma unroll
-        for (int j = 0; j < MAXL; ++j) {
-            acc[j] = 0.0f;
-            ptr[j] = rp[j];
-        }
-        for (int fb = 0; fb < d; fb += fb_size) {
-            __syncthreads();
-            const int fcount = d - fb < fb_size ? d - fb : fb_size;
-            for (int i = (int)threadIdx.x; i < kWave * fcount; i += nthreads) {
-                const int qq = i / fcount, f = i - qq * fcount;
-                const int64_t gq = q0 + qq;
-                qt[f * kQStride + qq] = gq < nq ? Q[gq * d + fb + f] : 0.0f;
-            }
-            __syncthreads();
-            const int fe = fb + fcount;
-#pragma unroll
-            for (int j = 0; j < MAXL; ++j) {
-                if (j < depth) {
-                    int p = ptr[j];
-                    const int e = rp[j + 1];
-                    float a = acc[j];
-                    if constexpr (CSR_LDS) {
-                        while (p < e) {
-                            const int c = cc[p + lds_shift];
-                            if (c >= fe) break;
-                            a = __builtin_fmaf(qt[(c - fb) * kQStride + lane], cv[p + lds_shift], a);
-                            ++p;
-                        }
-                    } else {
-                        while (p < e) {
-                            const int c = col[p];
-                            if (c >= fe) break;
-                            a = __builtin_fmaf(qt[(c - fb) * kQStride + lane], val[p], a);
-                            ++p;
-                        }
-                    }
-                    acc[j] = a;
-                    ptr[j] = p;
-                }
-            }
-        }
-        const int64_t q = q0 + lane;
-        if (tree_ok && q < nq) {
-            int node = 0;
-#pragma unroll
-            for (int j = 0; j < MAXL; ++j) {
-                if (j < depth) {
-                    float s;
-                    if constexpr (SPLITS_LDS) s = sp[w * nsplit + node];
-                    else s = splits[(int64_t)t * nsplit + node];
-                    node = (acc[j] <= s) ? 2 * node + 1 : 2 * node + 2;
-                }
-            }
-            leaf[q * T + t] = node - nsplit;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Form for projection vectors of at most 64 nonzeros.
-//
 // The projection Pq[r][q] = q . R_r (the sparse product of Sec. II-C): a
 // workgroup takes a tile of 64 * QPL queries (staged in LDS as
 // [feature][query]) and 8 waves x RPW rows; a wave keeps its RPW rows in
-// registers (lane e holds entry e) and advances them together, one nonzero
-// per row per step, so RPW * QPL fused multiply-add chains overlap while
-// each runs in ascending feature order.  The steps that every row has run
+// registers (lane e holds entry e; vectors of more than 64 nonzeros are
+// taken 64 entries at a time) and advances them together, one nonzero per
+// row per step, so RPW * QPL fused multiply-add chains overlap while each
+// runs in ascending feature order.  The steps that every row has run
 // without a branch.  project_kernel writes the rows to memory (index build);
 // project_route_kernel keeps them in LDS and walks the trees (Alg. 3's
 // descent) in the same workgroup.
@@ -352,7 +226,96 @@ __device__ __forceinline__ void project_accumulate(const float* __restrict__ Q, 
     }
 }
 
+// As project_accumulate for vectors of any length: a row's entries are
+// taken 64 at a time into the registers (lane e holds entry kb + e), in
+// ascending feature order, so every chain is the same as with the whole row
+// in registers.  A window of a feature chunk holds the row's next entries
+// below the chunk's end (a ballot counts them); a row with 64 such entries
+// may have more, so the windows of a chunk repeat until no row fills one.
 template <int RPW, bool CHUNKED, int QPL>
+__device__ __forceinline__ void project_accumulate_long(const float* __restrict__ Q, int64_t nq, int32_t d,
+                                                        const int32_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const float* __restrict__ val, int32_t r0, int32_t rend,
+                                                        int64_t q0, float* proj_smem, float (&acc)[QPL][RPW]) {
+    static_assert(QPL == 1 || !CHUNKED, "two queries per lane only with the whole tile in LDS");
+    constexpr int FS = CHUNKED ? kQStride : QPL * kQStride;
+    const int lane = lane_id();
+    int rb[RPW], rlen[RPW], kb[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        rb[i] = 0;
+        rlen[i] = 0;
+        kb[i] = 0;
+        if (r0 + i < rend) {
+            rb[i] = uniform(rowptr[r0 + i]);
+            rlen[i] = uniform(rowptr[r0 + i + 1]) - rb[i];
+        }
+#pragma unroll
+        for (int h = 0; h < QPL; ++h) acc[h][i] = 0.0f;
+    }
+    const int cstep = CHUNKED ? kProjChunk : d;
+    for (int c0 = 0; c0 < d; c0 += cstep) {
+        const int cw = d - c0 < cstep ? d - c0 : cstep;
+        if (c0 > 0) __syncthreads();     // every wave is done with the previous chunk
+        if constexpr (CHUNKED) {
+            stage_query_chunk(Q, q0, nq, d, c0, cw, proj_smem);
+        } else if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0) {
+            stage_tile_v4<QPL>(Q, q0, nq, d, proj_smem);
+        } else {
+#pragma unroll
+            for (int h = 0; h < QPL; ++h)
+                stage_query_chunk(Q, q0 + h * kWave, nq, d, 0, d, proj_smem + h * kQStride, FS);
+        }
+        __syncthreads();
+        for (;;) {
+            int colr[RPW], cnt[RPW];
+            float valr[RPW];
+            int span = 0, common = kWave;
+            bool full = false;
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                const int e = kb[i] + lane;
+                const bool in = e < rlen[i];
+                colr[i] = in ? col[rb[i] + e] : 0;
+                valr[i] = in ? val[rb[i] + e] : 0.0f;
+                cnt[i] = (int)__popcll(__builtin_amdgcn_ballot_w64(in && colr[i] < c0 + cw));
+                span = cnt[i] > span ? cnt[i] : span;
+                common = cnt[i] < common ? cnt[i] : common;
+                full = full || cnt[i] == kWave;
+            }
+            int k = 0;
+            for (; k < common; ++k) {
+#pragma unroll
+                for (int i = 0; i < RPW; ++i) {
+                    const int c = read_lane_i(colr[i], k);
+                    const float v = read_lane_f(valr[i], k);
+#pragma unroll
+                    for (int h = 0; h < QPL; ++h)
+                        acc[h][i] = __builtin_fmaf(proj_smem[(c - c0) * FS + h * kQStride + lane], v, acc[h][i]);
+                }
+            }
+            for (; k < span; ++k) {
+#pragma unroll
+                for (int i = 0; i < RPW; ++i) {
+                    if (k < cnt[i]) {
+                        const int c = read_lane_i(colr[i], k);
+                        const float v = read_lane_f(valr[i], k);
+#pragma unroll
+                        for (int h = 0; h < QPL; ++h)
+                            acc[h][i] = __builtin_fmaf(proj_smem[(c - c0) * FS + h * kQStride + lane], v,
+                                                       acc[h][i]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) kb[i] += cnt[i];
+            if (!full) break;
+        }
+    }
+}
+
+template <int RPW, bool CHUNKED, int QPL, bool LONG>
 __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_t nq, int32_t d,
                                              const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                              const float* __restrict__ val, int32_t nrows, float* __restrict__ Pq,
@@ -362,7 +325,8 @@ __device__ __forceinline__ void project_body(const float* __restrict__ Q, int64_
     const int64_t q0 = bx * (kWave * QPL);
     const int r0 = uniform(by * (kProjWaves * RPW) + w * RPW);
     float acc[QPL][RPW];
-    project_accumulate<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, r0, nrows, q0, proj_smem, acc);
+    if constexpr (LONG) project_accumulate_long<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, r0, nrows, q0, proj_smem, acc);
+    else project_accumulate<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, r0, nrows, q0, proj_smem, acc);
 #pragma unroll
     for (int h = 0; h < QPL; ++h) {
         const int64_t q = q0 + h * kWave + lane;
@@ -389,7 +353,7 @@ __host__ __device__ constexpr int route_group_trees(int rpw, int depth, int T) {
     return depth > 0 ? kProjWaves * rpw / depth : T;
 }
 
-template <int RPW, bool CHUNKED, int QPL, int MAXL>
+template <int RPW, bool CHUNKED, int QPL, int MAXL, bool LONG>
 __device__ __forceinline__ void project_route_body(const float* __restrict__ Q, int64_t nq, int32_t d,
                                                    const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col, const float* __restrict__ val,
@@ -406,7 +370,8 @@ __device__ __forceinline__ void project_route_body(const float* __restrict__ Q, 
     const int row_begin = t0 * depth, row_end = (t0 + ng) * depth;
     const int r0 = uniform(row_begin + w * RPW);
     float acc[QPL][RPW];
-    project_accumulate<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, r0, row_end, q0, proj_smem, acc);
+    if constexpr (LONG) project_accumulate_long<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, r0, row_end, q0, proj_smem, acc);
+    else project_accumulate<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, r0, row_end, q0, proj_smem, acc);
     __syncthreads();                          // every wave is done with the query tile
 #pragma unroll
     for (int h = 0; h < QPL; ++h)
@@ -446,24 +411,24 @@ __device__ __forceinline__ void project_route_body(const float* __restrict__ Q, 
     }
 }
 
-template <int RPW, bool CHUNKED, int QPL, int MAXL>
+template <int RPW, bool CHUNKED, int QPL, int MAXL, bool LONG>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_route_kernel(
     const float* __restrict__ Q, int64_t nq, int32_t d, const int32_t* __restrict__ rowptr,
     const int32_t* __restrict__ col, const float* __restrict__ val, const float* __restrict__ splits, int32_t T,
     int32_t depth, int32_t* __restrict__ leaf) {
     extern __shared__ float proj_smem[];   // query tile, then [G * depth][64 * QPL] projections
-    project_route_body<RPW, CHUNKED, QPL, MAXL>(Q, nq, d, rowptr, col, val, splits, T, depth, leaf, proj_smem,
-                                                blockIdx.x, (int32_t)blockIdx.y);
+    project_route_body<RPW, CHUNKED, QPL, MAXL, LONG>(Q, nq, d, rowptr, col, val, splits, T, depth, leaf, proj_smem,
+                                                      blockIdx.x, (int32_t)blockIdx.y);
 }
 
-template <int RPW, bool CHUNKED, int QPL>
+template <int RPW, bool CHUNKED, int QPL, bool LONG>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float* __restrict__ Q, int64_t nq,
                                                                      int32_t d, const int32_t* __restrict__ rowptr,
                                                                      const int32_t* __restrict__ col,
                                                                      const float* __restrict__ val, int32_t nrows,
                                                                      float* __restrict__ Pq) {
     extern __shared__ float proj_smem[];   // [min(d, kProjChunk)][QPL][65]
-    project_body<RPW, CHUNKED, QPL>(Q, nq, d, rowptr, col, val, nrows, Pq, proj_smem, blockIdx.x, blockIdx.y);
+    project_body<RPW, CHUNKED, QPL, LONG>(Q, nq, d, rowptr, col, val, nrows, Pq, proj_smem, blockIdx.x, blockIdx.y);
 }
 
 // the item of a multi-index launch that holds workgroup b (items ascending
@@ -487,7 +452,7 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_route_multi_kernel
     const int32_t i = find_route_item(items, nitems, blockIdx.x);
     const RouteItem& it = items[i];
     const int64_t r = (int64_t)blockIdx.x - it.blk0;
-    project_route_body<RPW, CHUNKED, QPL, MAXL>(it.Q, it.nq, it.d, it.rowptr, it.col, it.val, it.splits, it.T,
+    project_route_body<RPW, CHUNKED, QPL, MAXL, false>(it.Q, it.nq, it.d, it.rowptr, it.col, it.val, it.splits, it.T,
                                                 it.depth, it.leaf, proj_smem, r % it.nbx, (int32_t)(r / it.nbx));
 }
 
@@ -525,17 +490,23 @@ hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32
     const bool small = rows_per_wave == 4 ||
                        (rows_per_wave != kProjRows &&
                         tiles * ((nrows + kProjWaves * kProjRows - 1) / (kProjWaves * kProjRows)) < 512);
-#define MRPT_PROJ(RPW, CH, QPL)                                                                                \
+#define MRPT_PROJ_K(RPW, CH, QPL, LG)                                                                          \
     do {                                                                                                      \
         const size_t lds = (size_t)std::min(d, kProjChunk) * kQStride * 4 * (QPL);                           \
         dim3 grid((unsigned)((m + kWave * (QPL) - 1) / (kWave * (QPL))),                                      \
                   (unsigned)((nrows + kProjWaves * (RPW) - 1) / (kProjWaves * (RPW))));                       \
-        (void)hipFuncSetAttribute((const void*)project_kernel<RPW, CH, QPL>,                                  \
+        (void)hipFuncSetAttribute((const void*)project_kernel<RPW, CH, QPL, LG>,                              \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                      \
-        hipLaunchKernelGGL((project_kernel<RPW, CH, QPL>), grid, dim3(kProjWaves * kWave), lds, s, A, m, d,    \
-                           ix->rowptr + row0, ix->col, ix->val, nrows, P);                                    \
+        hipLaunchKernelGGL((project_kernel<RPW, CH, QPL, LG>), grid, dim3(kProjWaves * kWave), lds, s, A, m,   \
+                           d, ix->rowptr + row0, ix->col, ix->val, nrows, P);                                 \
+    } while (0)
+#define MRPT_PROJ(RPW, CH, QPL)                     \
+    do {                                            \
+        if (long_rows) MRPT_PROJ_K(RPW, CH, 1, true); \
+        else MRPT_PROJ_K(RPW, CH, QPL, false);      \
     } while (0)
     const bool chunked = d > kProjChunk;
+    const bool long_rows = ix->max_row_nnz > kWave;
     if (small) {
         if (chunked) MRPT_PROJ(4, true, 1);
         else MRPT_PROJ(4, false, 1);
@@ -545,13 +516,14 @@ hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32
         else MRPT_PROJ(kProjRows, false, 1);
     }
 #undef MRPT_PROJ
+#undef MRPT_PROJ_K
     return hipGetLastError();
 }
 
 namespace {
 
-// every projection vector with at most 64 nonzeros: projection and descent
-// in one launch of project_route_kernel
+// projection and descent in one launch of project_route_kernel (vectors of
+// more than 64 nonzeros: the windowed form, one query per lane)
 hipError_t launch_route_fused(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s,
                               const LaunchCfg& cfg) {
     const int depth = ix->depth;
@@ -564,24 +536,30 @@ hipError_t launch_route_fused(const mrpt_index* ix, const float* Q, int64_t nq, 
     const bool small = cfg.proj_rows == 4 ||
                        (cfg.proj_rows != kProjRows && tiles64 * ((ix->T + g16 - 1) / g16) < 512);
     const bool chunked = d > kProjChunk;
-#define MRPT_PR_K(RPW, CH, QPL, ML)                                                                              \
+    const bool long_rows = ix->max_row_nnz > kWave;
+#define MRPT_PR_K(RPW, CH, QPL, ML, LG)                                                                          \
     do {                                                                                                        \
         const int G = route_group_trees(RPW, depth, ix->T);                                                     \
         const size_t tile_b = (size_t)std::min(d, kProjChunk) * kQStride * 4 * (QPL);                           \
         const size_t proj_b = (size_t)G * depth * kWave * (QPL) * 4;                                            \
         const size_t lds = std::max(tile_b, proj_b);                                                            \
         dim3 grid((unsigned)((nq + kWave * (QPL) - 1) / (kWave * (QPL))), (unsigned)((ix->T + G - 1) / G));   \
-        (void)hipFuncSetAttribute((const void*)project_route_kernel<RPW, CH, QPL, ML>,                          \
+        (void)hipFuncSetAttribute((const void*)project_route_kernel<RPW, CH, QPL, ML, LG>,                      \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                        \
-        hipLaunchKernelGGL((project_route_kernel<RPW, CH, QPL, ML>), grid, dim3(kProjWaves * kWave), lds, s, Q,  \
+        hipLaunchKernelGGL((project_route_kernel<RPW, CH, QPL, ML, LG>), grid, dim3(kProjWaves * kWave), lds, s, Q, \
                            nq, d, ix->rowptr, ix->col, ix->val, ix->splits, ix->T, depth, leaf);                \
     } while (0)
-#define MRPT_PR(RPW, CH, QPL)                         \
-    do {                                              \
-        if (depth <= 8) MRPT_PR_K(RPW, CH, QPL, 8);   \
-        else if (depth <= 12) MRPT_PR_K(RPW, CH, QPL, 12); \
-        else if (depth <= 16) MRPT_PR_K(RPW, CH, QPL, 16); \
-        else MRPT_PR_K(RPW, CH, QPL, 24);             \
+#define MRPT_PR_D(RPW, CH, QPL, LG)                         \
+    do {                                                    \
+        if (depth <= 8) MRPT_PR_K(RPW, CH, QPL, 8, LG);     \
+        else if (depth <= 12) MRPT_PR_K(RPW, CH, QPL, 12, LG); \
+        else if (depth <= 16) MRPT_PR_K(RPW, CH, QPL, 16, LG); \
+        else MRPT_PR_K(RPW, CH, QPL, 24, LG);               \
+    } while (0)
+#define MRPT_PR(RPW, CH, QPL)                           \
+    do {                                                \
+        if (long_rows) MRPT_PR_D(RPW, CH, 1, true);     \
+        else MRPT_PR_D(RPW, CH, QPL, false);            \
     } while (0)
     if (small) {
         if (chunked) MRPT_PR(4, true, 1);
@@ -592,6 +570,7 @@ hipError_t launch_route_fused(const mrpt_index* ix, const float* Q, int64_t nq, 
         else MRPT_PR(kProjRows, false, 1);
     }
 #undef MRPT_PR
+#undef MRPT_PR_D
 #undef MRPT_PR_K
     return hipGetLastError();
 }
@@ -601,49 +580,7 @@ hipError_t launch_route_fused(const mrpt_index* ix, const float* Q, int64_t nq, 
 hipError_t launch_route(const mrpt_index* ix, const float* Q, int64_t nq, int32_t* leaf, hipStream_t s,
                         const LaunchCfg& cfg) {
     if (nq == 0) return hipSuccess;
-    if (ix->max_row_nnz <= kWave) return launch_route_fused(ix, Q, nq, leaf, s, cfg);
-    const int depth = ix->depth;
-    const int nsplit = (1 << depth) - 1;
-    const int limit = std::min(lds_per_block_limit(), 80 * 1024);   // two workgroups per CU
-    const int d = ix->d;
-    int tpb = std::min(4, ix->T);
-    int fb = std::min(d, 128);
-    int csr_cap = ix->max_tree_nnz;
-    int splits_in_lds = 1;
-    auto bytes = [&](int tp, int f, int sl, int cc) {
-        return (size_t)f * kQStride * 4 + (sl ? (size_t)tp * nsplit * 4 : 0) + (size_t)tp * cc * 8;
-    };
-    while (tpb > 1 && bytes(tpb, fb, 1, csr_cap) > (size_t)limit) --tpb;
-    if (bytes(tpb, fb, 1, csr_cap) > (size_t)limit) splits_in_lds = 0;
-    if (bytes(tpb, fb, splits_in_lds, csr_cap) > (size_t)limit) csr_cap = 0;
-    while (fb > 8 && bytes(tpb, fb, splits_in_lds, csr_cap) > (size_t)limit) fb /= 2;
-    const size_t lds = bytes(tpb, fb, splits_in_lds, csr_cap);
-    const int64_t ntiles = (nq + kWave - 1) / kWave;
-    const int tiles = ntiles >= 4 * 256 ? 4 : (ntiles >= 2 * 256 ? 2 : 1);
-    dim3 grid((unsigned)((ntiles + tiles - 1) / tiles), (unsigned)((ix->T + tpb - 1) / tpb));
-    dim3 block(kWave * tpb);
-#define MRPT_ROUTE_K(ML, CL, SL)                                                                        \
-    do {                                                                                                \
-        (void)hipFuncSetAttribute((const void*)route_kernel<ML, CL, SL>,                                \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-        hipLaunchKernelGGL((route_kernel<ML, CL, SL>), grid, block, lds, s, Q, nq, d, ix->rowptr, ix->col, \
-                           ix->val, ix->splits, ix->T, depth, tpb, tiles, fb, splits_in_lds, csr_cap,    \
-                           leaf);                                                                       \
-    } while (0)
-#define MRPT_ROUTE(ML)                                          \
-    do {                                                        \
-        if (csr_cap > 0 && splits_in_lds) MRPT_ROUTE_K(ML, true, true); \
-        else if (csr_cap > 0) MRPT_ROUTE_K(ML, true, false);    \
-        else if (splits_in_lds) MRPT_ROUTE_K(ML, false, true);  \
-        else MRPT_ROUTE_K(ML, false, false);                    \
-    } while (0)
-    if (depth <= 8) MRPT_ROUTE(8);
-    else if (depth <= 12) MRPT_ROUTE(12);
-    else if (depth <= 16) MRPT_ROUTE(16);
-    else MRPT_ROUTE(24);
-#undef MRPT_ROUTE
-#undef MRPT_ROUTE_K
-    return hipGetLastError();
+    return launch_route_fused(ix, Q, nq, leaf, s, cfg);
 }
 
 // Routing forms: 100 * projection class + depth class.  Projection class

@@ -69,7 +69,6 @@ struct mrpt_index {
     int32_t nleaf = 1;           // 2^depth
     int32_t max_leaf = 0;        // ceil(n / 2^depth)
     int32_t id_chunk = 0;        // ids per vote pass at v = 1 (reported by mrpt_index_info)
-    int32_t max_tree_nnz = 0;    // largest number of projection nonzeros of one tree
     int32_t max_row_nnz = 0;     // largest number of nonzeros of one projection vector
     int32_t built_on_device = 0; // trees grown by the GPU build
     int device = 0;

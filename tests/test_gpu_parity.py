@@ -476,6 +476,31 @@ def test_device_build_matches_host_and_oracle(n, d, T, depth, integer, monkeypat
         g.close()
 
 
+@pytest.mark.parametrize("n,d,a", [(3000, 100, 1.0), (2500, 300, 1.0), (2000, 600, 0.3)])
+def test_device_build_long_vectors(n, d, a):
+    """Projection vectors of more than 64 nonzeros (dense RP trees, a = 1;
+    a = 0.3 at d = 600): the GPU build's projection and the routing take a
+    vector 64 entries at a time, within one feature chunk (d = 100) or over
+    chunks of 252 features with several windows per chunk (d = 300, 600).
+    Trees and leaves equal the oracle's bit for bit."""
+    _print_case(f"device build, long vectors n={n} d={d} a={a}")
+    T, depth = 4, 6
+    X, Q = _small(n, d, T, depth, seed=n + d, nq=130)
+    orc = oracle.build_index(X, T, depth, a, 17)
+    g = mrpt.Index(dev(X), T, depth, a, 17)
+    try:
+        assert g.info.built_on_device == 1 and g.info.max_row_nnz > 64
+        assert np.array_equal(mrpt.mrpt_export_leaf_offsets(g.handle), orc.off)
+        for t in range(T):
+            splits, perm = mrpt.mrpt_export_tree(g.handle, t)
+            assert np.array_equal(splits.view(np.uint32), orc.splits[t].view(np.uint32)), f"tree {t} splits"
+            assert np.array_equal(perm, orc.perm[t]), f"tree {t} perm"
+        for nq in (1, 130):
+            assert np.array_equal(leaves(g, dev(Q[:nq])), oracle.route(orc, Q[:nq])), f"nq={nq}"
+    finally:
+        g.close()
+
+
 @pytest.mark.parametrize("k,precision", [(10, None), (100, None), (10, "bf16")])
 def test_gist_like_shape_full_parity(k, precision):
     # the gist-like data (d = 960, values in (0, 1)) at a size the oracle

@@ -3,12 +3,12 @@ those shapes take:
 
   * the Random set (Sec. IV-A: unit-norm Gaussian vectors in 4,096
     dimensions), scaled to a few thousand points: projection vectors with
-    about 64 nonzeros (a = 1/64), so some hold more than 64 and the index is
-    grown on host threads and queries are routed by the fused routing kernel;
-    distances by the generic (d > 1024) distance kernel;
+    about 64 nonzeros (a = 1/64), so some hold more than 64 and both the GPU
+    build's projection and the routing take them 64 entries at a time, over
+    feature chunks; distances by the generic (d > 1024) distance kernel;
   * dense random projection trees (the footnote of Sec. IV-B and the RP-tree
-    column of Table III): a = 1, every vector holds all d features (128 and
-    784), again host build and fused routing.
+    column of Table III): a = 1, every vector holds all d features (128: one
+    feature chunk, several windows; 784: several chunks).
 
 Leaves, candidate sets with their vote counts, |S| and the k nearest are
 compared with the oracle on the same seeded inputs.
@@ -37,10 +37,14 @@ def _compare(X, Q, T, depth, a, seed, k, v):
     try:
         rowptr, _, _ = mrpt.mrpt_export_projection(g.handle)
         most = int(np.diff(rowptr).max())
-        # the index reports its longest vector and where its trees were grown
-        # (the GPU build takes vectors of at most 64 nonzeros)
+        # the index reports its longest vector; its trees were grown on the GPU
+        # (vectors of more than 64 nonzeros taken 64 entries at a time)
         assert g.info.max_row_nnz == most
-        assert g.info.built_on_device == (1 if most <= 64 else 0)
+        assert g.info.built_on_device == 1
+        for t in range(T):
+            splits, perm = mrpt.mrpt_export_tree(g.handle, t)
+            assert np.array_equal(splits.view(np.uint32), orc.splits[t].view(np.uint32)), f"tree {t} splits"
+            assert np.array_equal(perm, orc.perm[t]), f"tree {t} perm"
         Qd = dev(Q)
         assert np.array_equal(leaves(g, Qd), oracle.route(orc, Q))
         ref = oracle.query(orc, Q, k, v, want_sets=True)
