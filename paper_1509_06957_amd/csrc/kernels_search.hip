@@ -735,6 +735,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void d
     dist_prefilter_body<FMT, GB, NVB, G2, NV2>(MRPT_PF_ARGS);
 }
 
+// The fp8 forms of d <= 128 held to 96 registers, five waves per SIMD
+// instead of four (two registers spill; seven waves would spill 37).
+template <int FMT, int GB, int NVB, int G2, int NV2>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void dist_prefilter_w5_kernel(
+    MRPT_PF_PARAMS) {
+    dist_prefilter_body<FMT, GB, NVB, G2, NV2>(MRPT_PF_ARGS);
+}
+
 // phase 1 only: the kept list of every query (parity hook)
 template <int FMT, int GB, int NVB, int G2, int NV2>
 __global__ __launch_bounds__(256) void dist_prefilter_keep_kernel(MRPT_PF_PARAMS, int32_t* __restrict__ keep_out) {
@@ -763,6 +771,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void d
                                                (int64_t)blockIdx.x - it.row0);
 }
 
+template <int FMT, int GB, int NVB, int G2, int NV2>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void dist_prefilter_multi_w5_kernel(
+    const SearchItem* __restrict__ items, int32_t nitems, int32_t d, float recheck_rel) {
+    const int32_t i = find_item(items, nitems, blockIdx.x);
+    const SearchItem& it = items[i];
+    dist_prefilter_body<FMT, GB, NVB, G2, NV2>(it.X, it.Xq, it.sn8, d, it.Q, it.s_ids, it.cap, it.s_count, it.k,
+                                               it.kp, recheck_rel, it.out_idx, it.out_dist,
+                                               (int64_t)blockIdx.x - it.row0);
+}
+
 #undef MRPT_PF_ARGS
 #undef MRPT_PF_PARAMS
 
@@ -775,6 +793,9 @@ void launch_prefilter_form(dim3 grid, hipStream_t s, const float* X, const uint8
                            d, Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist, keep_out);
     else if constexpr (F == kFmtBf16 && GB == 16 && NVB == 1)
         hipLaunchKernelGGL((dist_prefilter_w7_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
+                           Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
+    else if constexpr (F == kFmtFp8 && GB == 8 && NVB == 1)
+        hipLaunchKernelGGL((dist_prefilter_w5_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
                            Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
     else
         hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d, Q,
@@ -928,8 +949,14 @@ hipError_t launch_search_multi(int32_t form, int32_t d, const SearchItem* items,
         }
     } else if (form >= 300 && form < 400) {
         switch (form - 300) {
-            case 0: MRPT_PFM(kFmtFp8, 8, 1, 16, 1); break;
-            case 1: MRPT_PFM(kFmtFp8, 8, 1, 32, 1); break;
+            case 0:
+                hipLaunchKernelGGL((dist_prefilter_multi_w5_kernel<kFmtFp8, 8, 1, 16, 1>), grid, block, 0, s,
+                                   items, nitems, d, recheck_rel);
+                break;
+            case 1:
+                hipLaunchKernelGGL((dist_prefilter_multi_w5_kernel<kFmtFp8, 8, 1, 32, 1>), grid, block, 0, s,
+                                   items, nitems, d, recheck_rel);
+                break;
             case 2: MRPT_PFM(kFmtFp8, 16, 1, 64, 1); break;
             case 3: MRPT_PFM(kFmtFp8, 32, 1, 64, 2); break;
             default: MRPT_PFM(kFmtFp8, 64, 1, 64, 4); break;
