@@ -865,7 +865,7 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
                 mw = std::max(mw, vote_map_words(groups[gi].ix));
                 most = std::max<int64_t>(most, (int64_t)groups[gi].ix->T * groups[gi].ix->max_leaf);
             }
-            if (vote_multi_qcap(mw, most) < 0) {
+            if (vote_multi_qcap(vote_cls[c].key, mw, most) < 0) {
                 for (int32_t gi : vote_cls[c].members) vote_alone.push_back(gi);
                 vote_cls.erase(vote_cls.begin() + (long)c);
             } else {
@@ -1003,7 +1003,7 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
                 L.map_words = std::max(L.map_words, vote_map_words(groups[gi].ix));
                 most = std::max<int64_t>(most, (int64_t)groups[gi].ix->T * groups[gi].ix->max_leaf);
             }
-            L.qcap = vote_multi_qcap(L.map_words, most);
+            L.qcap = vote_multi_qcap(c.key, L.map_words, most);
             std::vector<VoteItem> items;
             std::vector<int32_t> row_item;
             int64_t row0 = 0;

@@ -324,11 +324,12 @@ __device__ __forceinline__ void append_batch(const uint32_t (&ob)[NB], const int
     }
 }
 
-// Per-slot window descriptors of wave w, one slot per lane (lanes >= S
-// unused): part = 64-id part of the window in its leaf (-1 past the last
+// Per-slot window descriptors of wave w of NW, one slot per lane (lanes >=
+// S unused): part = 64-id part of the window in its leaf (-1 past the last
 // tree) and tp = tree | 64 * part << 8.  Computed once per kernel.
+template <int NW>
 __device__ __forceinline__ void slot_table(int w, int T, int wpl, int& part64, int& tp) {
-    const int u = w + kVoteWaves * lane_id();
+    const int u = w + NW * lane_id();
     const int t = u / wpl, part = u - t * wpl;
     part64 = t < T ? part * kWave : -1;
     tp = t < T ? (t | (part * kWave) << 8) : 0;
@@ -515,12 +516,12 @@ __global__ __launch_bounds__(kVoteBlock) void vote_dir_kernel(
 // surrounds the atomics.
 constexpr int kRerunUnroll = 4;
 
-template <bool CLEARING>
+template <bool CLEARING, int NW>
 __device__ __forceinline__ void rerun(uint32_t* map, int32_t* queue, int qn, bool last, int w, int32_t n32,
                                       int* nsel, int* spare, int32_t* out, uint32_t cap) {
     constexpr int R = kRerunUnroll;
     const int lane = lane_id();
-    for (int base = w * kWave * R; base < qn; base += kVoteBlock * R) {   // wave-uniform trip count
+    for (int base = w * kWave * R; base < qn; base += NW * kWave * R) {   // wave-uniform trip count
         int32_t e[R];
         uint32_t f[R];
 #pragma unroll
@@ -554,8 +555,10 @@ __device__ __forceinline__ void rerun(uint32_t* map, int32_t* queue, int qn, boo
 // windows per leaf; row r is query r - row0 of item row_item[r], and the map
 // and queue are laid out for the largest index).  Every row's item gives its
 // index arrays, n, v and outputs; the map is clear again after every query
-// (each query clears the words its index's ids use).
-template <int S, bool QUEUE, bool MULTI>
+// (each query clears the words its index's ids use).  NW waves per
+// workgroup: 16 (one workgroup per CU), or 8 where two workgroups' maps and
+// queues fit LDS together.
+template <int S, bool QUEUE, bool MULTI, int NW>
 __device__ __forceinline__ void vote_map_body(const VoteItem& one, const VoteItem* __restrict__ items,
                                               const int32_t* __restrict__ row_item, int64_t nrows, int32_t T,
                                               int32_t wpl, int32_t map_words, int32_t qcap) {
@@ -579,9 +582,9 @@ __device__ __forceinline__ void vote_map_body(const VoteItem& one, const VoteIte
         else return one;
     };
     int part64, slot_tp;
-    slot_table(w, T, wpl, part64, slot_tp);
+    slot_table<NW>(w, T, wpl, part64, slot_tp);
 
-    for (int i = tid; i < (map_words >> 2); i += kVoteBlock)
+    for (int i = tid; i < (map_words >> 2); i += NW * kWave)
         reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
     // leaf position of tree tid in the query of row r (tid < T): perm index
     // of the leaf's first id, and its length
@@ -674,8 +677,8 @@ __device__ __forceinline__ void vote_map_body(const VoteItem& one, const VoteIte
             for (int level = 2; level <= it.v; ++level) {
                 const bool last = level == it.v;
                 // runs 2, 4, ...: the bits of the queued ids start set
-                if ((level & 1) == 0) rerun<true>(map, queue, qn, last, w, n32, nsel, spare, out, (uint32_t)cap32);
-                else rerun<false>(map, queue, qn, last, w, n32, nsel, spare, out, (uint32_t)cap32);
+                if ((level & 1) == 0) rerun<true, NW>(map, queue, qn, last, w, n32, nsel, spare, out, (uint32_t)cap32);
+                else rerun<false, NW>(map, queue, qn, last, w, n32, nsel, spare, out, (uint32_t)cap32);
                 lds_barrier();
             }
         }
@@ -687,7 +690,7 @@ __device__ __forceinline__ void vote_map_body(const VoteItem& one, const VoteIte
             *qfill = 0;
             *nsel = 0;
         }
-        for (int i = tid; i < (it.map_words >> 2); i += kVoteBlock)
+        for (int i = tid; i < (it.map_words >> 2); i += NW * kWave)
             reinterpret_cast<uint4*>(map_smem)[i] = make_uint4(0u, 0u, 0u, 0u);
         lds_barrier();
         if (q1 >= nrows) return false;
@@ -700,19 +703,19 @@ __device__ __forceinline__ void vote_map_body(const VoteItem& one, const VoteIte
     }
 }
 
-template <int S, bool QUEUE>
-__global__ __launch_bounds__(kVoteBlock) void vote_map_kernel(VoteItem one, int64_t nq, int32_t T, int32_t wpl,
+template <int S, bool QUEUE, int NW>
+__global__ __launch_bounds__(NW * kWave) void vote_map_kernel(VoteItem one, int64_t nq, int32_t T, int32_t wpl,
                                                               int32_t map_words, int32_t qcap) {
-    vote_map_body<S, QUEUE, false>(one, nullptr, nullptr, nq, T, wpl, map_words, qcap);
+    vote_map_body<S, QUEUE, false, NW>(one, nullptr, nullptr, nq, T, wpl, map_words, qcap);
 }
 
 // several query calls of one geometry in one persistent launch
-template <int S, bool QUEUE>
-__global__ __launch_bounds__(kVoteBlock) void vote_map_multi_kernel(const VoteItem* __restrict__ items,
+template <int S, bool QUEUE, int NW>
+__global__ __launch_bounds__(NW * kWave) void vote_map_multi_kernel(const VoteItem* __restrict__ items,
                                                                     const int32_t* __restrict__ row_item,
                                                                     int64_t nrows, int32_t T, int32_t wpl,
                                                                     int32_t map_words, int32_t qcap) {
-    vote_map_body<S, QUEUE, true>(VoteItem(), items, row_item, nrows, T, wpl, map_words, qcap);
+    vote_map_body<S, QUEUE, true, NW>(VoteItem(), items, row_item, nrows, T, wpl, map_words, qcap);
 }
 
 // debug: F(x; q) of every listed candidate, by binary search of x in each of
@@ -772,11 +775,15 @@ struct SingleGeometry {
 
 constexpr size_t kMapTail = sizeof(int2) * kPosBufs * kMaxT + 16 + 4 * kWave;   // positions, flags, spare
 
-SingleGeometry single_geometry(const mrpt_index* ix, bool queued) {
+// the LDS one workgroup of nw waves may take: all of it at 16 waves, half at
+// 8 (two workgroups per CU)
+size_t vote_lds_budget(int nw) { return nw == kVoteWaves ? vote_lds_limit() : vote_lds_limit() / 2; }
+
+SingleGeometry single_geometry(const mrpt_index* ix, bool queued, int nw = kVoteWaves) {
     SingleGeometry g;
-    const size_t limit = vote_lds_limit();
+    const size_t limit = vote_lds_budget(nw);
     g.wpl = (ix->max_leaf + kWave - 1) / kWave;
-    g.slots = ((int64_t)ix->T * g.wpl + kVoteWaves - 1) / kVoteWaves;
+    g.slots = ((int64_t)ix->T * g.wpl + nw - 1) / nw;
     g.map_words = ((ix->n + kVoteSlots * kWave) / 32 + 1 + 3) / 4 * 4;
     const int64_t room = ((int64_t)limit - (int64_t)kMapTail - g.map_words * 4) / 4;
     g.qcap = queued ? std::min<int64_t>(room, (int64_t)ix->T * ix->max_leaf) / 4 * 4 : 0;
@@ -789,6 +796,16 @@ SingleGeometry single_geometry(const mrpt_index* ix, bool queued) {
            (int64_t)ix->T * ix->perm_ld < (int64_t(1) << 30) && room >= 0 && (!queued || g.qcap >= 1024);
     g.lds = (size_t)(g.map_words + g.qcap) * 4 + kMapTail;
     return g;
+}
+
+// waves per workgroup of the single-pass kernel for this index: 8 (two
+// workgroups per CU, whose fixed per-query costs overlap) when the map, the
+// windows and a queue that holds every repeat of a query, or 4,096 of them,
+// fit half of LDS; else 16
+int single_waves(const mrpt_index* ix, bool queued) {
+    const SingleGeometry g8 = single_geometry(ix, queued, 8);
+    const int64_t most = (int64_t)ix->T * ix->max_leaf - ix->n / ((int64_t)1 << ix->depth);
+    return g8.ok && (!queued || g8.qcap >= std::min<int64_t>(most, 4096)) ? 8 : kVoteWaves;
 }
 
 int device_cus() {
@@ -814,13 +831,14 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     // one), else the environment override, else automatic
     const int mode = recount_only ? -1 : cfg.vote_kernel == 2 ? 0 : cfg.vote_kernel == 1 ? -1 : vote_kernel_override();
     const bool queued = v >= 2;   // repeats are queued and rerun
-    const SingleGeometry sg = single_geometry(ix, queued);
+    const int nw = single_waves(ix, queued);
+    const SingleGeometry sg = single_geometry(ix, queued, nw);
     const bool single = recount_only || (mode < 0 && sg.ok);
     if (single && !recount_only) {
         const int wpl = sg.wpl;
         const int64_t slots = sg.slots, map_words = sg.map_words, qcap = sg.qcap;
         const size_t lds = sg.lds;
-        const int64_t grid = std::min<int64_t>(nq, device_cus());
+        const int64_t grid = std::min<int64_t>(nq, (int64_t)device_cus() * (kVoteWaves / nw));
         VoteItem one;
         one.leaf = leaf;
         one.perm = ix->perm;
@@ -833,12 +851,17 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         one.n = (int32_t)ix->n;
         one.v = v;
         one.map_words = (int32_t)map_words;
-#define MRPT_MAP(SS, H)                                                                                          \
+#define MRPT_MAP_W(SS, H, NW)                                                                                    \
     do {                                                                                                         \
-        (void)hipFuncSetAttribute((const void*)vote_map_kernel<SS, H>,                                           \
+        (void)hipFuncSetAttribute((const void*)vote_map_kernel<SS, H, NW>,                                       \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                         \
-        hipLaunchKernelGGL((vote_map_kernel<SS, H>), dim3((unsigned)grid), dim3(kVoteBlock), lds, s, one, nq,     \
-                           ix->T, wpl, (int32_t)map_words, (int32_t)qcap);                                       \
+        hipLaunchKernelGGL((vote_map_kernel<SS, H, NW>), dim3((unsigned)grid), dim3((NW) * kWave), lds, s, one,   \
+                           nq, ix->T, wpl, (int32_t)map_words, (int32_t)qcap);                                   \
+    } while (0)
+#define MRPT_MAP(SS, H)                      \
+    do {                                     \
+        if (nw == 8) MRPT_MAP_W(SS, H, 8);   \
+        else MRPT_MAP_W(SS, H, kVoteWaves);  \
     } while (0)
         // the smallest instantiated slot count that holds the windows: every
         // slot costs its loads and map updates even when it is empty
@@ -853,6 +876,7 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
         }
 #undef MRPT_MAP_S
 #undef MRPT_MAP
+#undef MRPT_MAP_W
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !queued) return e;
         // a query queues sum(F - 1) <= T * max_leaf - (its first leaf's size)
@@ -905,15 +929,23 @@ constexpr int kSlotClasses[] = {4, 8, 13, 16, 20, 25, 28, kVoteSlots};
 
 }  // namespace
 
+// ((((slot class * 2 + queued) * 2 + eight waves) * 256 + T) * 65536 + windows per leaf
 int64_t vote_form(const mrpt_index* ix, int32_t v, const LaunchCfg& cfg) {
     const int mode = cfg.vote_kernel == 2 ? 0 : cfg.vote_kernel == 1 ? -1 : vote_kernel_override();
     const bool queued = v >= 2;
-    const SingleGeometry sg = single_geometry(ix, queued);
+    const int nw = single_waves(ix, queued);
+    const SingleGeometry sg = single_geometry(ix, queued, nw);
     if (mode >= 0 || !sg.ok) return -1;
     int c = 0;
     while (kSlotClasses[c] < sg.slots) ++c;
-    return (((int64_t)c * 2 + (queued ? 1 : 0)) * 256 + ix->T) * 65536 + sg.wpl;
+    return ((((int64_t)c * 2 + (queued ? 1 : 0)) * 2 + (nw == 8 ? 1 : 0)) * 256 + ix->T) * 65536 + sg.wpl;
 }
+
+namespace {
+int form_waves(int64_t form) { return ((form / 65536 / 256) & 1) != 0 ? 8 : kVoteWaves; }
+bool form_queued(int64_t form) { return ((form / 65536 / 256 / 2) & 1) != 0; }
+int form_slot_class(int64_t form) { return (int)(form / 65536 / 256 / 4); }
+}  // namespace
 
 int32_t vote_map_words(const mrpt_index* ix) { return (int32_t)single_geometry(ix, false).map_words; }
 
@@ -921,8 +953,8 @@ int64_t vote_most_queued(const mrpt_index* ix) {
     return (int64_t)ix->T * ix->max_leaf - ix->n / ((int64_t)1 << ix->depth);
 }
 
-int64_t vote_multi_qcap(int32_t map_words, int64_t most_occurrences) {
-    const int64_t room = ((int64_t)vote_lds_limit() - (int64_t)kMapTail - (int64_t)map_words * 4) / 4;
+int64_t vote_multi_qcap(int64_t form, int32_t map_words, int64_t most_occurrences) {
+    const int64_t room = ((int64_t)vote_lds_budget(form_waves(form)) - (int64_t)kMapTail - (int64_t)map_words * 4) / 4;
     int64_t qcap = std::min<int64_t>(room, most_occurrences) / 4 * 4;
     const char* cap_env = std::getenv("MRPT_VOTE_QUEUE_CAP");
     if (cap_env && *cap_env && std::atoll(cap_env) > 0) qcap = std::min<int64_t>(qcap, std::atoll(cap_env) / 4 * 4);
@@ -934,16 +966,22 @@ hipError_t launch_vote_multi(int64_t form, int32_t map_words, int64_t qcap, cons
     if (nrows == 0) return hipSuccess;
     const int32_t wpl = (int32_t)(form % 65536);
     const int32_t T = (int32_t)((form / 65536) % 256);
-    const bool queued = ((form / 65536 / 256) & 1) != 0;
-    const int c = (int)(form / 65536 / 256 / 2);
+    const int nw = form_waves(form);
+    const bool queued = form_queued(form);
+    const int c = form_slot_class(form);
     const size_t lds = (size_t)(map_words + qcap) * 4 + kMapTail;
-    const int64_t grid = std::min<int64_t>(nrows, device_cus());
-#define MRPT_MAPM(SS, H)                                                                                     \
+    const int64_t grid = std::min<int64_t>(nrows, (int64_t)device_cus() * (kVoteWaves / nw));
+#define MRPT_MAPM_W(SS, H, NW)                                                                               \
     do {                                                                                                     \
-        (void)hipFuncSetAttribute((const void*)vote_map_multi_kernel<SS, H>,                                 \
+        (void)hipFuncSetAttribute((const void*)vote_map_multi_kernel<SS, H, NW>,                             \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                     \
-        hipLaunchKernelGGL((vote_map_multi_kernel<SS, H>), dim3((unsigned)grid), dim3(kVoteBlock), lds, s,     \
-                           items, row_item, nrows, T, wpl, map_words, (int32_t)qcap);                        \
+        hipLaunchKernelGGL((vote_map_multi_kernel<SS, H, NW>), dim3((unsigned)grid), dim3((NW) * kWave), lds, \
+                           s, items, row_item, nrows, T, wpl, map_words, (int32_t)qcap);                     \
+    } while (0)
+#define MRPT_MAPM(SS, H)                      \
+    do {                                      \
+        if (nw == 8) MRPT_MAPM_W(SS, H, 8);   \
+        else MRPT_MAPM_W(SS, H, kVoteWaves);  \
     } while (0)
 #define MRPT_MAPM_C(CI, SS)                       \
     case CI:                                      \
@@ -958,6 +996,7 @@ hipError_t launch_vote_multi(int64_t form, int32_t map_words, int64_t qcap, cons
     }
 #undef MRPT_MAPM_C
 #undef MRPT_MAPM
+#undef MRPT_MAPM_W
     return hipGetLastError();
 }
 

@@ -198,15 +198,16 @@ struct VoteItem {
 };
 
 // the single-pass vote form of a call (equal forms share a launch: slot
-// class, queueing, T, windows per leaf), -1 when the call needs the
-// multi-pass kernel; map words of an index; the most repeats one query can
-// queue; the queue capacity of a multi-index launch whose map holds
-// map_words (-1 when too small); the launch itself (rows whose queue
-// overflows get count -1, counted again by launch_vote_recount)
+// class, queueing, waves per workgroup, T, windows per leaf), -1 when the
+// call needs the multi-pass kernel; map words of an index; the most repeats
+// one query can queue; the queue capacity of a multi-index launch of that
+// form whose map holds map_words (-1 when too small); the launch itself
+// (rows whose queue overflows get count -1, counted again by
+// launch_vote_recount)
 int64_t vote_form(const mrpt_index* ix, int32_t v, const LaunchCfg& cfg);
 int32_t vote_map_words(const mrpt_index* ix);
 int64_t vote_most_queued(const mrpt_index* ix);
-int64_t vote_multi_qcap(int32_t map_words, int64_t most_occurrences);
+int64_t vote_multi_qcap(int64_t form, int32_t map_words, int64_t most_occurrences);
 hipError_t launch_vote_multi(int64_t form, int32_t map_words, int64_t qcap, const VoteItem* items,
                              const int32_t* row_item, int64_t nrows, hipStream_t s);
 hipError_t launch_vote_recount(const mrpt_index* ix, const int32_t* leaf, int64_t nq, int32_t v, int32_t* s_ids,
