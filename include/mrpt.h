@@ -229,6 +229,11 @@ typedef struct mrpt_plan_opts {
                                a stage starts when the previous one has ended; 0: every group its
                                own chain of launches, dealt over `branches`.  None of these knobs
                                changes a result; they are there for tuning the launches. */
+    int32_t vote_waves;     /* waves per workgroup of the single-pass vote kernel: 0 (default)
+                               automatic (8, two workgroups per CU, where half of LDS holds the
+                               index's map and a queue for every repeat of a query or 4,096 of
+                               them, else 16); 16; or 8 wherever the map fits half of LDS (a
+                               smaller repeat queue: overflowing queries are recounted). */
 } mrpt_plan_opts;
 
 typedef struct mrpt_plan mrpt_plan;

@@ -37,6 +37,7 @@ def main():
     p.add_argument("--branches", default="1,2,4,8,16")
     p.add_argument("--proj-rows", default="0,16", help="projection vectors per wave to try (0: automatic)")
     p.add_argument("--vote-kernels", default="0,2", help="vote kernels to try (0 automatic, 1 single-pass, 2 multi-pass)")
+    p.add_argument("--vote-waves", default="0,16", help="single-pass vote workgroups to try (0 automatic, 8, 16 waves)")
     p.add_argument("--recall-sample", type=int, default=2000)
     p.add_argument("--retune", action="store_true", help="time every candidate even if the cache holds a choice")
     args = p.parse_args()
@@ -77,13 +78,14 @@ def main():
         return (time.perf_counter() - t0) / steps * 1e3
 
     # autotuner over the recorded graph's launch choices (tuning.py): plan
-    # form, streams or chains, projection rows per wave, vote kernel; the
-    # choice is cached as JSON under the batches' signature
+    # form, streams or chains, projection rows per wave, vote kernel and its
+    # workgroup size; the choice is cached as JSON under the batches' signature
     from paper_1509_06957_amd import tuning
     grid = {"fused": [int(x) for x in args.fused.split(",")],
             "branches": [int(x) for x in args.branches.split(",")],
             "proj_rows": [int(x) for x in args.proj_rows.split(",")],
-            "vote_kernel": [int(x) for x in args.vote_kernels.split(",")]}
+            "vote_kernel": [int(x) for x in args.vote_kernels.split(",")],
+            "vote_waves": [int(x) for x in args.vote_waves.split(",")]}
     choice, tuning_ms, cached = tuning.tune(batches, prec, lambda pl: time_launches(pl.launch, max(2, args.steps // 2)),
                                             grid=grid, retune=args.retune, log=log)
     b_best = ",".join(f"{k}={v}" for k, v in choice.items())

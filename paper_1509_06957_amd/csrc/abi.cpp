@@ -728,6 +728,7 @@ void mrpt_default_plan_opts(mrpt_plan_opts* o) {
     o->proj_rows = 0;
     o->vote_kernel = 0;
     o->fused = 1;
+    o->vote_waves = 0;
 }
 
 mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mrpt_plan_opts* opts,
@@ -743,9 +744,12 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
         return fail(MRPT_EINVAL, "proj_rows = %d is not 0, 4 or 16", po.proj_rows);
     if (po.vote_kernel < 0 || po.vote_kernel > 2) return fail(MRPT_EINVAL, "vote_kernel = %d outside [0, 2]", po.vote_kernel);
     if (po.fused != 0 && po.fused != 1) return fail(MRPT_EINVAL, "fused = %d is not 0 or 1", po.fused);
+    if (po.vote_waves != 0 && po.vote_waves != 8 && po.vote_waves != 16)
+        return fail(MRPT_EINVAL, "vote_waves = %d is not 0, 8 or 16", po.vote_waves);
     LaunchCfg cfg;
     cfg.proj_rows = po.proj_rows;
     cfg.vote_kernel = po.vote_kernel;
+    cfg.vote_waves = po.vote_waves;
     mrpt_query_opts o;
     mrpt_default_opts(&o);
     o.precision = (mrpt_precision)po.precision;

@@ -801,9 +801,12 @@ SingleGeometry single_geometry(const mrpt_index* ix, bool queued, int nw = kVote
 // waves per workgroup of the single-pass kernel for this index: 8 (two
 // workgroups per CU, whose fixed per-query costs overlap) when the map, the
 // windows and a queue that holds every repeat of a query, or 4,096 of them,
-// fit half of LDS; else 16
-int single_waves(const mrpt_index* ix, bool queued) {
+// fit half of LDS; else 16.  pinned: 16, or 8 wherever the 8-wave geometry
+// fits at all (its smaller queue may overflow: those queries are recounted)
+int single_waves(const mrpt_index* ix, bool queued, int32_t pinned = 0) {
+    if (pinned == kVoteWaves) return kVoteWaves;
     const SingleGeometry g8 = single_geometry(ix, queued, 8);
+    if (pinned == 8) return g8.ok ? 8 : kVoteWaves;
     const int64_t most = (int64_t)ix->T * ix->max_leaf - ix->n / ((int64_t)1 << ix->depth);
     return g8.ok && (!queued || g8.qcap >= std::min<int64_t>(most, 4096)) ? 8 : kVoteWaves;
 }
@@ -831,7 +834,7 @@ hipError_t launch_vote_b(const mrpt_index* ix, const int32_t* leaf, int64_t nq, 
     // one), else the environment override, else automatic
     const int mode = recount_only ? -1 : cfg.vote_kernel == 2 ? 0 : cfg.vote_kernel == 1 ? -1 : vote_kernel_override();
     const bool queued = v >= 2;   // repeats are queued and rerun
-    const int nw = single_waves(ix, queued);
+    const int nw = single_waves(ix, queued, cfg.vote_waves);
     const SingleGeometry sg = single_geometry(ix, queued, nw);
     const bool single = recount_only || (mode < 0 && sg.ok);
     if (single && !recount_only) {
@@ -933,7 +936,7 @@ constexpr int kSlotClasses[] = {4, 8, 13, 16, 20, 25, 28, kVoteSlots};
 int64_t vote_form(const mrpt_index* ix, int32_t v, const LaunchCfg& cfg) {
     const int mode = cfg.vote_kernel == 2 ? 0 : cfg.vote_kernel == 1 ? -1 : vote_kernel_override();
     const bool queued = v >= 2;
-    const int nw = single_waves(ix, queued);
+    const int nw = single_waves(ix, queued, cfg.vote_waves);
     const SingleGeometry sg = single_geometry(ix, queued, nw);
     if (mode >= 0 || !sg.ok) return -1;
     int c = 0;

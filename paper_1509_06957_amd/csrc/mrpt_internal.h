@@ -134,6 +134,7 @@ hipError_t grow_trees_device(mrpt_index* ix, int32_t t0, int32_t g,
 struct LaunchCfg {
     int32_t proj_rows = 0;     // projection vectors per wave: 4 or 16
     int32_t vote_kernel = 0;   // 1: single-pass where it fits, 2: multi-pass
+    int32_t vote_waves = 0;    // single-pass workgroup: 0 automatic, 8 or 16 waves
 };
 
 // projections of the m rows of A onto vectors row0 .. row0 + nrows - 1:

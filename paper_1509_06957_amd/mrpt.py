@@ -51,7 +51,7 @@ class mrpt_batch(ctypes.Structure):
 class mrpt_plan_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rerank_factor", ctypes.c_int32), ("recheck_rel", ctypes.c_float),
                 ("branches", ctypes.c_int32), ("proj_rows", ctypes.c_int32), ("vote_kernel", ctypes.c_int32),
-                ("fused", ctypes.c_int32)]
+                ("fused", ctypes.c_int32), ("vote_waves", ctypes.c_int32)]
 
 
 _lib = None
@@ -336,7 +336,7 @@ class Plan:
     land in self.out[i] = (idx, dist) at every launch()."""
 
     def __init__(self, batches, precision: int = MRPT_FP32, rerank_factor: int = 4, recheck_rel: float = 1e-6,
-                 branches: int = 4, proj_rows: int = 0, vote_kernel: int = 0, fused: int = 1):
+                 branches: int = 4, proj_rows: int = 0, vote_kernel: int = 0, fused: int = 1, vote_waves: int = 0):
         import torch
         self.handle = None
         self.batches = list(batches)
@@ -345,7 +345,7 @@ class Plan:
                     for (_, Q, k, _) in self.batches]
         o = mrpt_default_plan_opts()
         o.precision, o.rerank_factor, o.recheck_rel, o.branches = precision, rerank_factor, recheck_rel, branches
-        o.proj_rows, o.vote_kernel, o.fused = proj_rows, vote_kernel, fused
+        o.proj_rows, o.vote_kernel, o.fused, o.vote_waves = proj_rows, vote_kernel, fused, vote_waves
         self.handle = mrpt_plan_create([(ix.handle, Q, k, v, oi, od) for (ix, Q, k, v), (oi, od)
                                         in zip(self.batches, self.out)], o)
 

@@ -3,8 +3,10 @@
 A plan's launch choices change no result (tested): the plan form (one
 launch per stage across indexes, or one chain per group), the stream or
 chain count, the projection kernel's vectors per wave (its tile height: 4 or
-16; 0 lets the launcher pick by launch size) and the vote kernel (single- or
-multi-pass).  tune() times a plan for every candidate on the caller's
+16; 0 lets the launcher pick by launch size), the vote kernel (single- or
+multi-pass) and the single-pass vote kernel's workgroup (8 or 16 waves,
+which sets how much LDS its repeat queue, the candidate buffer of the
+reruns, gets).  tune() times a plan for every candidate on the caller's
 batches and keeps the fastest.  The choice is stored under a key made of the
 GPU architecture, the precision arm and, for every group of batches with one
 (index, k, v), the tuple (d, T, depth, k, v, nq bucket) with nq rounded up
@@ -24,6 +26,7 @@ DEFAULT_CANDIDATES = {
     "branches": (1, 2, 4, 8),
     "proj_rows": (0, 16),
     "vote_kernel": (0, 2),
+    "vote_waves": (0, 16),
 }
 
 
@@ -88,7 +91,9 @@ def candidates(grid: Optional[Dict[str, Iterable[int]]] = None) -> List[Dict[str
         for b in g["branches"]:
             for pr in g["proj_rows"]:
                 for vk in g["vote_kernel"]:
-                    out.append({"fused": f, "branches": b, "proj_rows": pr, "vote_kernel": vk})
+                    for vw in g["vote_waves"]:
+                        out.append({"fused": f, "branches": b, "proj_rows": pr, "vote_kernel": vk,
+                                    "vote_waves": vw})
     return out
 
 

@@ -58,7 +58,8 @@ def test_plan_structs_match_header_layout():
     # mrpt_batch: index, Q pointers; int64 nq; int32 k, v; two pointers
     assert ctypes.sizeof(mrpt.mrpt_batch) == 8 + 8 + 8 + 4 + 4 + 8 + 8
     assert mrpt.mrpt_batch.k.offset == 24 and mrpt.mrpt_batch.out_idx.offset == 32
-    assert ctypes.sizeof(mrpt.mrpt_plan_opts) == 28 and mrpt.mrpt_plan_opts.fused.offset == 24
+    assert ctypes.sizeof(mrpt.mrpt_plan_opts) == 32 and mrpt.mrpt_plan_opts.fused.offset == 24
+    assert mrpt.mrpt_plan_opts.vote_waves.offset == 28
 
 
 def test_plan_error_paths_without_gpu():
@@ -66,8 +67,8 @@ def test_plan_error_paths_without_gpu():
     lib = mrpt.load()
     o = mrpt.mrpt_plan_opts()
     lib.mrpt_default_plan_opts(ctypes.byref(o))
-    assert (o.precision, o.rerank_factor, o.branches, o.proj_rows, o.vote_kernel, o.fused) == \
-        (mrpt.MRPT_FP32, 4, 4, 0, 0, 1)
+    assert (o.precision, o.rerank_factor, o.branches, o.proj_rows, o.vote_kernel, o.fused, o.vote_waves) == \
+        (mrpt.MRPT_FP32, 4, 4, 0, 0, 1, 0)
     h = ctypes.c_void_p()
     assert lib.mrpt_plan_create(None, 0, None, ctypes.byref(h)) == mrpt.MRPT_EINVAL
     assert "nbatch" in mrpt.mrpt_last_error()
@@ -82,6 +83,9 @@ def test_plan_error_paths_without_gpu():
     o.proj_rows, o.vote_kernel = 0, 3
     assert lib.mrpt_plan_create(arr, 1, ctypes.byref(o), ctypes.byref(h)) == mrpt.MRPT_EINVAL
     assert "vote_kernel" in mrpt.mrpt_last_error()
+    o.vote_kernel, o.vote_waves = 0, 4
+    assert lib.mrpt_plan_create(arr, 1, ctypes.byref(o), ctypes.byref(h)) == mrpt.MRPT_EINVAL
+    assert "vote_waves" in mrpt.mrpt_last_error()
     assert lib.mrpt_plan_launch(None, None) == mrpt.MRPT_EINVAL
     assert lib.mrpt_plan_device_bytes(None) == 0
     lib.mrpt_plan_free(None)

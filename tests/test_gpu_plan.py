@@ -129,19 +129,22 @@ def test_plan_rejects_bad_batch(setup):
 
 
 @pytest.mark.parametrize("fused", [1, 0])
-@pytest.mark.parametrize("proj_rows,vote_kernel", [(4, 0), (16, 0), (0, 1), (0, 2)])
-def test_plan_launch_choices_keep_results(setup, proj_rows, vote_kernel, fused):
+@pytest.mark.parametrize("proj_rows,vote_kernel,vote_waves", [(4, 0, 0), (16, 0, 0), (0, 1, 0), (0, 2, 0),
+                                                              (0, 0, 16), (0, 1, 8)])
+def test_plan_launch_choices_keep_results(setup, proj_rows, vote_kernel, vote_waves, fused):
     # the tunable launch choices (projection vectors per wave, single- or
-    # multi-pass voting, per-stage or per-group launches) change no result
+    # multi-pass voting, the single-pass workgroup's waves, per-stage or
+    # per-group launches) change no result
     _, _, ixs, stream, _, Qs = setup
-    print(f"[case] plan proj_rows={proj_rows} vote_kernel={vote_kernel} fused={fused}", flush=True)
+    print(f"[case] plan proj_rows={proj_rows} vote_kernel={vote_kernel} vote_waves={vote_waves} fused={fused}",
+          flush=True)
     ref = eager(ixs, stream, Qs, mrpt.MRPT_BF16_RERANK)
     plan = mrpt.Plan([(ixs[ix], Q, k, SMALL.v) for (_, ix, _, k), Q in zip(stream, Qs)],
                      precision=mrpt.MRPT_BF16_RERANK, branches=3, proj_rows=proj_rows, vote_kernel=vote_kernel,
-                     fused=fused)
+                     fused=fused, vote_waves=vote_waves)
     out = plan.launch()
     torch.cuda.synchronize()
-    same(out, ref, f"proj_rows={proj_rows} vote_kernel={vote_kernel} fused={fused}")
+    same(out, ref, f"proj_rows={proj_rows} vote_kernel={vote_kernel} vote_waves={vote_waves} fused={fused}")
     plan.close()
 
 
@@ -213,9 +216,10 @@ def test_tuner_times_candidates_and_caches_the_choice(setup, tmp_path):
         ev[1].synchronize()
         return ev[0].elapsed_time(ev[1]) / 3
 
-    grid = {"fused": [1, 0], "branches": [1, 3], "proj_rows": [0], "vote_kernel": [0]}
+    grid = {"fused": [1, 0], "branches": [1, 3], "proj_rows": [0], "vote_kernel": [0], "vote_waves": [0, 16]}
     choice, timings, cached = tuning.tune(batches, mrpt.MRPT_FP32, time_plan, grid=grid, path=path)
-    assert not cached and len(timings) == 4 and set(choice) == {"fused", "branches", "proj_rows", "vote_kernel"}
+    assert not cached and len(timings) == 8
+    assert set(choice) == {"fused", "branches", "proj_rows", "vote_kernel", "vote_waves"}
     again, t2, cached2 = tuning.tune(batches, mrpt.MRPT_FP32, time_plan, grid=grid, path=path)
     assert cached2 and again == choice and t2 == {}
     ref = eager(ixs, stream, Qs, mrpt.MRPT_FP32)

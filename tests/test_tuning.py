@@ -19,9 +19,11 @@ def test_nq_bucket():
 
 
 def test_candidates_cover_the_grid():
-    c = tuning.candidates({"fused": [1], "branches": [1, 4], "proj_rows": [0], "vote_kernel": [0, 2]})
+    c = tuning.candidates({"fused": [1], "branches": [1, 4], "proj_rows": [0], "vote_kernel": [0, 2],
+                           "vote_waves": [0]})
     assert len(c) == 4 and {x["branches"] for x in c} == {1, 4} and all(x["fused"] == 1 for x in c)
-    assert len(tuning.candidates()) == 2 * 4 * 2 * 2
+    assert len(tuning.candidates()) == 2 * 4 * 2 * 2 * 2
+    assert {x["vote_waves"] for x in tuning.candidates()} == {0, 16}
 
 
 def test_signature_groups_batches_by_index_k_v(monkeypatch):
