@@ -248,6 +248,9 @@ def main():
             "bytes_per_launch": stage["bytes"], "launch_ms": stage["ms"],
             "profiled_launch_us": float(row["avg_us"]) if row else None,
             "copy_GBps": round(copy_gbps, 1),
+            "basis": "frac = algorithmic bytes / launch time / 8 TB/s; traffic = bytes leaving L2 "
+                     "(TCC_EA0 read/write requests by size), which include Infinity-Cache hits: no "
+                     "counter on this part separates those from DRAM reads",
         }
 
     roofline = roofline_of(stages32[dom], STAGE_KERNEL[dom])
