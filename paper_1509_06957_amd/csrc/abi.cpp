@@ -987,7 +987,7 @@ mrpt_status mrpt_plan_create(const mrpt_batch* batches, int32_t nbatch, const mr
                 it.d = g.ix->d;
                 it.T = g.ix->T;
                 it.depth = g.ix->depth;
-                it.pad_ = 0;
+                it.nby = (int32_t)rg.nby;
                 items.push_back(it);
                 L.blocks += rg.nbx * rg.nby;
                 L.max_d = std::max(L.max_d, g.ix->d);

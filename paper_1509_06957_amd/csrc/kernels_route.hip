@@ -63,6 +63,30 @@ __device__ __forceinline__ void stage_query_chunk(const float* __restrict__ Q, i
 // ---------------------------------------------------------------------------
 constexpr int kProjWaves = 8;
 
+// Workgroup order of the (query tile, row or tree group) grids, launched as
+// one dimension.  Consecutive workgroups go to the eight XCDs in turn, each
+// with its own L2, so workgroup r runs on XCD r mod 8.  The grid's nbx * nby
+// workgroups in tile-major order (the groups of one tile consecutive) are cut
+// into eight contiguous runs, one per XCD, taken in order: every group of a
+// query tile runs on one XCD (two at a run's edge), one after another, and
+// stages the tile from that XCD's L2 after the first.  With the tile's groups
+// spread over all XCDs, each read it from memory again.  The map is a
+// bijection of [0, nbx * nby) for any XCD count; eight is the one it is
+// tuned for.  An offset to r that is the same for the whole grid (a
+// multi-index launch's item) keeps the property.
+constexpr int kXcds = 8;
+// most workgroups of a one-dimensional launch: the dispatch counts the grid
+// in work-items, fewer than 2^32 per dimension
+constexpr int64_t kMaxGrid = ((int64_t(1) << 32) - 1) / (kProjWaves * kWave);
+__device__ __forceinline__ void xcd_tile_group(int64_t r, int64_t nbx, int32_t nby, int64_t& tile, int32_t& grp) {
+    const int64_t n = nbx * nby;
+    const int64_t per = n / kXcds, extra = n - per * kXcds;
+    const int64_t x = r % kXcds, k = r / kXcds;
+    const int64_t m = x * per + (x < extra ? x : extra) + k;
+    tile = m / nby;
+    grp = (int32_t)(m - tile * nby);
+}
+
 // The workgroup's 64-query tile is staged in LDS as [feature][query], in
 // chunks of at most kProjChunk features when d is wider.  A vector's
 // nonzeros are in ascending feature order, so those of one chunk are a
@@ -415,10 +439,13 @@ template <int RPW, bool CHUNKED, int QPL, int MAXL, bool LONG>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_route_kernel(
     const float* __restrict__ Q, int64_t nq, int32_t d, const int32_t* __restrict__ rowptr,
     const int32_t* __restrict__ col, const float* __restrict__ val, const float* __restrict__ splits, int32_t T,
-    int32_t depth, int32_t* __restrict__ leaf) {
+    int32_t depth, int32_t* __restrict__ leaf, int64_t nbx, int32_t nby) {
     extern __shared__ float proj_smem[];   // query tile, then [G * depth][64 * QPL] projections
+    int64_t tile;
+    int32_t grp;
+    xcd_tile_group(blockIdx.x, nbx, nby, tile, grp);
     project_route_body<RPW, CHUNKED, QPL, MAXL, LONG>(Q, nq, d, rowptr, col, val, splits, T, depth, leaf, proj_smem,
-                                                      blockIdx.x, (int32_t)blockIdx.y);
+                                                      tile, grp);
 }
 
 template <int RPW, bool CHUNKED, int QPL, bool LONG>
@@ -426,9 +453,12 @@ __global__ __launch_bounds__(kProjWaves * kWave) void project_kernel(const float
                                                                      int32_t d, const int32_t* __restrict__ rowptr,
                                                                      const int32_t* __restrict__ col,
                                                                      const float* __restrict__ val, int32_t nrows,
-                                                                     float* __restrict__ Pq) {
+                                                                     float* __restrict__ Pq, int64_t nbx, int32_t nby) {
     extern __shared__ float proj_smem[];   // [min(d, kProjChunk)][QPL][65]
-    project_body<RPW, CHUNKED, QPL, LONG>(Q, nq, d, rowptr, col, val, nrows, Pq, proj_smem, blockIdx.x, blockIdx.y);
+    int64_t tile;
+    int32_t grp;
+    xcd_tile_group(blockIdx.x, nbx, nby, tile, grp);
+    project_body<RPW, CHUNKED, QPL, LONG>(Q, nq, d, rowptr, col, val, nrows, Pq, proj_smem, tile, grp);
 }
 
 // the item of a multi-index launch that holds workgroup b (items ascending
@@ -444,16 +474,18 @@ __device__ __forceinline__ int32_t find_route_item(const RouteItem* __restrict__
 }
 
 // projection and descent of several query calls in one launch: workgroup b
-// is (query tile, tree group) (x, y) of its item's own grid
+// is workgroup b - blk0 of its item's own grid, in the XCD order above
 template <int RPW, bool CHUNKED, int QPL, int MAXL>
 __global__ __launch_bounds__(kProjWaves * kWave) void project_route_multi_kernel(const RouteItem* __restrict__ items,
                                                                                  int32_t nitems) {
     extern __shared__ float proj_smem[];
     const int32_t i = find_route_item(items, nitems, blockIdx.x);
     const RouteItem& it = items[i];
-    const int64_t r = (int64_t)blockIdx.x - it.blk0;
+    int64_t tile;
+    int32_t grp;
+    xcd_tile_group((int64_t)blockIdx.x - it.blk0, it.nbx, it.nby, tile, grp);
     project_route_body<RPW, CHUNKED, QPL, MAXL, false>(it.Q, it.nq, it.d, it.rowptr, it.col, it.val, it.splits, it.T,
-                                                it.depth, it.leaf, proj_smem, r % it.nbx, (int32_t)(r / it.nbx));
+                                                it.depth, it.leaf, proj_smem, tile, grp);
 }
 
 }  // namespace
@@ -493,12 +525,20 @@ hipError_t launch_project(const mrpt_index* ix, const float* A, int64_t m, int32
 #define MRPT_PROJ_K(RPW, CH, QPL, LG)                                                                          \
     do {                                                                                                      \
         const size_t lds = (size_t)std::min(d, kProjChunk) * kQStride * 4 * (QPL);                           \
-        dim3 grid((unsigned)((m + kWave * (QPL) - 1) / (kWave * (QPL))),                                      \
-                  (unsigned)((nrows + kProjWaves * (RPW) - 1) / (kProjWaves * (RPW))));                       \
+        const int64_t nbx = (m + kWave * (QPL) - 1) / (kWave * (QPL));                                        \
+        if (nbx > kMaxGrid) return hipErrorInvalidConfiguration;                                              \
+        /* row groups per launch: the one-dimensional grid within the dispatch limit */                       \
+        const int32_t step = (int32_t)std::min<int64_t>(kMaxGrid / nbx, INT32_MAX / (kProjWaves * (RPW))) *   \
+                             (kProjWaves * (RPW));                                                            \
         (void)hipFuncSetAttribute((const void*)project_kernel<RPW, CH, QPL, LG>,                              \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                      \
-        hipLaunchKernelGGL((project_kernel<RPW, CH, QPL, LG>), grid, dim3(kProjWaves * kWave), lds, s, A, m,   \
-                           d, ix->rowptr + row0, ix->col, ix->val, nrows, P);                                 \
+        for (int32_t c0 = 0; c0 < nrows; c0 += step) {                                                        \
+            const int32_t rows_c = std::min(step, nrows - c0);                                                \
+            const int32_t nby = (rows_c + kProjWaves * (RPW) - 1) / (kProjWaves * (RPW));                     \
+            hipLaunchKernelGGL((project_kernel<RPW, CH, QPL, LG>), dim3((unsigned)(nbx * nby)),                \
+                               dim3(kProjWaves * kWave), lds, s, A, m, d, ix->rowptr + row0 + c0, ix->col,     \
+                               ix->val, rows_c, P + (int64_t)c0 * m, nbx, nby);                               \
+        }                                                                                                     \
     } while (0)
 #define MRPT_PROJ(RPW, CH, QPL)                     \
     do {                                            \
@@ -543,11 +583,18 @@ hipError_t launch_route_fused(const mrpt_index* ix, const float* Q, int64_t nq, 
         const size_t tile_b = (size_t)std::min(d, kProjChunk) * kQStride * 4 * (QPL);                           \
         const size_t proj_b = (size_t)G * depth * kWave * (QPL) * 4;                                            \
         const size_t lds = std::max(tile_b, proj_b);                                                            \
-        dim3 grid((unsigned)((nq + kWave * (QPL) - 1) / (kWave * (QPL))), (unsigned)((ix->T + G - 1) / G));   \
+        const int32_t nby = (ix->T + G - 1) / G;                                                                \
+        /* queries per launch: the one-dimensional grid within the dispatch limit */                            \
+        const int64_t step = (kMaxGrid / nby) * kWave * (QPL);                                                  \
         (void)hipFuncSetAttribute((const void*)project_route_kernel<RPW, CH, QPL, ML, LG>,                      \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                        \
-        hipLaunchKernelGGL((project_route_kernel<RPW, CH, QPL, ML, LG>), grid, dim3(kProjWaves * kWave), lds, s, Q, \
-                           nq, d, ix->rowptr, ix->col, ix->val, ix->splits, ix->T, depth, leaf);                \
+        for (int64_t q0 = 0; q0 < nq; q0 += step) {                                                             \
+            const int64_t nq_c = std::min(step, nq - q0);                                                       \
+            const int64_t nbx = (nq_c + kWave * (QPL) - 1) / (kWave * (QPL));                                   \
+            hipLaunchKernelGGL((project_route_kernel<RPW, CH, QPL, ML, LG>), dim3((unsigned)(nbx * nby)),        \
+                               dim3(kProjWaves * kWave), lds, s, Q + q0 * d, nq_c, d, ix->rowptr, ix->col,       \
+                               ix->val, ix->splits, ix->T, depth, leaf + q0 * ix->T, nbx, nby);                 \
+        }                                                                                                       \
     } while (0)
 #define MRPT_PR_D(RPW, CH, QPL, LG)                         \
     do {                                                    \
@@ -636,6 +683,7 @@ RouteGrid route_grid(const mrpt_index* ix, int64_t nq, int32_t rpw, int32_t qpl)
 hipError_t launch_route_multi(int32_t form, int32_t rpw, int32_t qpl, int32_t max_d, const RouteItem* items,
                               int32_t nitems, int64_t blocks, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
+    if (blocks > kMaxGrid) return hipErrorInvalidConfiguration;
     const int pc = form / 100, dc = form % 100;
     if (pc > 2 || dc > 3) return hipErrorInvalidValue;
     const bool chunked = pc == 2;

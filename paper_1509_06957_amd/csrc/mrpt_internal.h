@@ -226,7 +226,8 @@ struct RouteItem {
     int64_t nq;
     int64_t blk0;                // first workgroup of the call in the launch
     int64_t nbx;                 // workgroups along the queries
-    int32_t d, T, depth, pad_;
+    int32_t d, T, depth;
+    int32_t nby;                 // workgroups along the trees (tree groups)
 };
 // the routing form of a call's index (equal forms can share the launch),
 // -1 without a multi-index form (vectors over 64 nonzeros)
