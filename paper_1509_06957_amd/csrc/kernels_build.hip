@@ -7,8 +7,9 @@
 // every node of every tree of the group is cut by rank: the node's keys
 // (projection, id) are sorted within the node and its first ceil(m/2) keys
 // form the left child.  A key is a 64-bit word, the projection's order bits
-// above the id, so one segmented radix sort over all nodes of the group does
-// the cut of a whole level, ties broken by id.  The split stored for queries
+// above the id (idb = bits of n - 1 of them), so one segmented radix sort of
+// its 32 + idb low bits over all nodes of the group does the cut of a whole
+// level, ties broken by id.  The split stored for queries
 // is the largest left value for odd m and the float32 midpoint of the two
 // middle values for even m.  Finally each leaf is sorted by id.
 #include <rocprim/device/device_segmented_radix_sort.hpp>
@@ -32,20 +33,20 @@ __device__ __forceinline__ float from_order_bits(uint32_t o) {
 
 // keys of level lv: tree tl = blockIdx.y of the group, position i (the id at
 // that position after the previous level's sort, or i itself at level 0)
-__global__ void level_keys_kernel(const float* __restrict__ P, int32_t depth, int32_t lv, int64_t n,
+__global__ void level_keys_kernel(const float* __restrict__ P, int32_t depth, int32_t lv, int64_t n, int32_t idb,
                                   const uint64_t* __restrict__ prev, uint64_t* __restrict__ keys) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t tl = blockIdx.y;
     const int64_t at = tl * n + i;
-    const uint32_t id = prev ? (uint32_t)prev[at] : (uint32_t)i;
+    const uint32_t id = prev ? (uint32_t)(prev[at] & ((uint64_t(1) << idb) - 1)) : (uint32_t)i;
     const float p = P[(tl * depth + lv) * n + id];
-    keys[at] = ((uint64_t)order_bits(p) << 32) | id;
+    keys[at] = ((uint64_t)order_bits(p) << idb) | id;
 }
 
 // split of node s of level lv in tree tl = blockIdx.y, from its sorted keys
 __global__ void level_splits_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__ node_off,
-                                    int32_t lv, int64_t n, int64_t nsplit, float* __restrict__ splits) {
+                                    int32_t lv, int64_t n, int32_t idb, int64_t nsplit, float* __restrict__ splits) {
     const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     const int nodes = 1 << lv;
     if (s >= nodes) return;
@@ -53,10 +54,10 @@ __global__ void level_splits_kernel(const uint64_t* __restrict__ keys, const int
     const int64_t b = node_off[s], m = node_off[s + 1] - b;
     const int64_t nl = (m + 1) / 2;
     const uint64_t* k = keys + tl * n + b;
-    const float left_max = from_order_bits((uint32_t)(k[nl - 1] >> 32));
+    const float left_max = from_order_bits((uint32_t)(k[nl - 1] >> idb));
     float split = left_max;
     if ((m & 1) == 0) {
-        const float right_min = from_order_bits((uint32_t)(k[nl] >> 32));
+        const float right_min = from_order_bits((uint32_t)(k[nl] >> idb));
         const float sum = left_max + right_min;
         split = sum * 0.5f;
     }
@@ -64,12 +65,12 @@ __global__ void level_splits_kernel(const uint64_t* __restrict__ keys, const int
 }
 
 // ids of the sorted keys into the perm rows of the group (row stride ld)
-__global__ void perm_rows_kernel(const uint64_t* __restrict__ keys, int64_t n, int64_t ld,
+__global__ void perm_rows_kernel(const uint64_t* __restrict__ keys, int64_t n, int32_t idb, int64_t ld,
                                  int32_t* __restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t tl = blockIdx.y;
-    perm[tl * ld + i] = (int32_t)(uint32_t)keys[tl * n + i];
+    perm[tl * ld + i] = (int32_t)(keys[tl * n + i] & ((uint64_t(1) << idb) - 1));
 }
 
 // identity ids (depth 0: one leaf holding every point, ascending)
@@ -93,6 +94,9 @@ hipError_t grow_trees_device(mrpt_index* ix, int32_t t0, int32_t g, const std::v
     const int64_t nsplit = ((int64_t)1 << depth) - 1;
     const unsigned threads = 256;
     const dim3 rows((unsigned)((n + threads - 1) / threads), (unsigned)g);
+    // bits of the largest id (at least 1): the keys' low field
+    int32_t idb = 1;
+    while (idb < 31 && ((n - 1) >> idb) != 0) ++idb;
     hipError_t e;
     if ((e = launch_project(ix, ix->X, n, t0 * depth, g * depth, P, s)) != hipSuccess) return e;
 
@@ -127,17 +131,18 @@ hipError_t grow_trees_device(mrpt_index* ix, int32_t t0, int32_t g, const std::v
     // each level: keys from the previous level's sorted keys (in keys_b) into
     // keys_a, then the sort of keys_a back into keys_b
     for (int32_t lv = 0; lv < depth; ++lv) {
-        hipLaunchKernelGGL(level_keys_kernel, rows, dim3(threads), 0, s, P, depth, lv, n,
+        hipLaunchKernelGGL(level_keys_kernel, rows, dim3(threads), 0, s, P, depth, lv, n, idb,
                            lv == 0 ? (const uint64_t*)nullptr : keys_b, keys_a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = sort_level(lv, keys_a, keys_b, 0, 64)) != hipSuccess) return e;
+        if ((e = sort_level(lv, keys_a, keys_b, 0, 32 + (unsigned)idb)) != hipSuccess) return e;
         const std::vector<int64_t>& lo = level_off[lv];
         if ((e = hipMemcpy(node_off, lo.data(), lo.size() * sizeof(int64_t), hipMemcpyHostToDevice)) !=
             hipSuccess)
             return e;
         const int nodes = 1 << lv;
         hipLaunchKernelGGL(level_splits_kernel, dim3((unsigned)((nodes + threads - 1) / threads), (unsigned)g),
-                           dim3(threads), 0, s, keys_b, node_off, lv, n, nsplit, ix->splits + (int64_t)t0 * nsplit);
+                           dim3(threads), 0, s, keys_b, node_off, lv, n, idb, nsplit,
+                           ix->splits + (int64_t)t0 * nsplit);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const uint64_t* ids = keys_a;
@@ -145,10 +150,10 @@ hipError_t grow_trees_device(mrpt_index* ix, int32_t t0, int32_t g, const std::v
         hipLaunchKernelGGL(iota_keys_kernel, rows, dim3(threads), 0, s, n, keys_a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
-        // leaves: ids ascending (the low 32 bits of the key)
-        if ((e = sort_level(depth, keys_b, keys_a, 0, 32)) != hipSuccess) return e;
+        // leaves: ids ascending (the key's low idb bits)
+        if ((e = sort_level(depth, keys_b, keys_a, 0, (unsigned)idb)) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(perm_rows_kernel, rows, dim3(threads), 0, s, ids, n, ix->perm_ld,
+    hipLaunchKernelGGL(perm_rows_kernel, rows, dim3(threads), 0, s, ids, n, idb, ix->perm_ld,
                        ix->perm + (int64_t)t0 * ix->perm_ld);
     return hipGetLastError();
 }
