@@ -387,7 +387,7 @@ def main():
                   "built_on_device": bool(ix.info.built_on_device), "max_row_nnz": int(ix.info.max_row_nnz),
                   # projection work of the build: n * (nonzeros of all T*depth vectors) multiply-adds
                   "projection_fma": int(w.n) * nnz,
-                  "note": "device: projection kernel + per-level segmented sort; host: threads over trees"},
+                  "note": "device: projection kernel + per-level cut by rank (radix select of each node's middle key, partition); host: threads over trees"},
         "recall_sample": len(rs),
         "recall_truth": truth,
         "latency": latency,

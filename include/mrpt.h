@@ -108,8 +108,10 @@ mrpt_status mrpt_build(const float* data, int64_t n, int32_t d, int32_t T, int32
 /* Index build options. */
 typedef struct {
     int32_t on_device;     /* 1 (default): grow the trees on the GPU (data projected by the
-                              query path's projection kernel, every level cut by a segmented
-                              sort of (projection, id) keys); 0: on host threads.  Both give
+                              query path's projection kernel, every node of a level cut by
+                              rank: a radix select of its middle (projection, id) key and a
+                              partition; MRPT_BUILD_SORT=1 sorts each level instead); 0: on
+                              host threads.  All give
                               bit-identical trees.  The GPU build takes scratch device memory
                               of about n*(4*depth + 16) bytes per tree of a group (groups
                               sized to MRPT_BUILD_LIMIT bytes, default 8 GiB). */

@@ -457,22 +457,28 @@ def test_vote_kernel_variants_agree(kernel, monkeypatch):
                                                  (3000, 24, 3, 0, False), (777, 4, 9, 9, True),
                                                  (20000, 3, 2, 11, True), (65537, 12, 3, 12, False)])
 def test_device_build_matches_host_and_oracle(n, d, T, depth, integer, monkeypatch):
-    # the GPU build (projection kernel + per-level segmented sort of
-    # (projection, id) keys) and the host build give the oracle's trees bit
-    # for bit; integer data in {0..3} ties projections often, depth 0 is one
-    # leaf, and the scratch limit forces groups of two trees
+    # the GPU build (projection kernel, then each level cut by rank: a radix
+    # select of every node's middle (projection, id) key and a partition,
+    # with nodes over 8192 keys cut by many workgroups and smaller ones by one
+    # in LDS; or, with MRPT_BUILD_SORT=1, a segmented sort of every level)
+    # and the host build give the oracle's trees bit for bit; integer data in
+    # {0..3} ties projections often, depth 0 is one leaf, and the scratch
+    # limit forces groups of two trees.  n = 20000 and 65537 reach the
+    # many-workgroup cut (levels 0-1 and 0-3; 65537 / 8 = 8192.1 keys per
+    # node at level 3)
     _print_case(f"device build n={n} d={d} T={T} depth={depth} integer={integer}")
     monkeypatch.setenv("MRPT_BUILD_LIMIT", str(2 * n * (4 * max(depth, 1) + 16)))
     X, _ = _small(n, d, T, depth, seed=n + depth, integer=integer)
     orc = oracle.build_index(X, T, depth, 0.5, 11)
-    for on_device in (True, False):
+    for on_device, sort in ((True, "0"), (True, "1"), (False, "0")):
+        monkeypatch.setenv("MRPT_BUILD_SORT", sort)
         g = mrpt.Index(dev(X), T, depth, 0.5, 11, on_device=on_device)
         assert np.array_equal(mrpt.mrpt_export_leaf_offsets(g.handle), orc.off)
         for t in range(T):
             splits, perm = mrpt.mrpt_export_tree(g.handle, t)
             assert np.array_equal(splits.view(np.uint32), orc.splits[t].view(np.uint32)), \
-                f"on_device={on_device} tree {t} splits"
-            assert np.array_equal(perm, orc.perm[t]), f"on_device={on_device} tree {t} perm"
+                f"on_device={on_device} sort={sort} tree {t} splits"
+            assert np.array_equal(perm, orc.perm[t]), f"on_device={on_device} sort={sort} tree {t} perm"
         g.close()
 
 
