@@ -4,9 +4,9 @@
 // Trees are grown in groups.  For a group the data are projected onto all of
 // its vectors at once (project_kernel, the float32 fused multiply-add chain
 // in ascending feature order that the queries use), then level by level
-// every node of every tree of the group is cut by rank: the node's keys
-// (projection, id) are sorted within the node and its first ceil(m/2) keys
-// form the left child.  A key is a 64-bit word, the projection's order bits
+// every node of every tree of the group is cut by rank: the ceil(m/2)
+// smallest of the node's keys (projection, id) form the left child, the rest
+// the right one.  A key is a 64-bit word, the projection's order bits
 // above the id (idb = bits of n - 1 of them), so the order of keys is the
 // order (projection, id), and all keys of a tree are distinct.  The split
 // stored for queries is the largest left value for odd m and the float32
