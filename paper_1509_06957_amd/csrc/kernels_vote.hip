@@ -268,7 +268,10 @@ __global__ void vote_dir_build_kernel(const int32_t* __restrict__ perm, const in
 // lie in spare words past the ids, a different word for every lane.  Loads address perm by a 32-bit byte offset
 // from its base.  Two queries are counted per loop turn, so the windows in
 // flight and the windows counted swap register arrays instead of moving.
-constexpr int kMapBatch = 5;         // slots whose map updates are issued together
+// slots whose map updates are issued together (13: the two batches of a
+// 25-slot wave, the sift-like shape, without spilling the batch's lane masks
+// out of scalar registers; 5 took 4 % longer there)
+constexpr int kMapBatch = 13;
 constexpr int kPosBufs = 3;          // leaf position buffers of the pipeline
 
 // number of set bits of m below this lane, plus base
