@@ -28,7 +28,7 @@ CSRC = os.path.join(ROOT, "paper_1509_06957_amd", "csrc")
 KERNEL_FILE = {"project_route_kernel": "kernels_route.hip",
                "vote_map_kernel": "kernels_vote.hip", "vote_dir_kernel": "kernels_vote.hip",
                "dist_fp32_kernel": "kernels_search.hip", "dist_prefilter_kernel": "kernels_search.hip",
-               "dist_prefilter_w7_kernel": "kernels_search.hip", "dist_prefilter_w5_kernel": "kernels_search.hip"}
+               "dist_prefilter_w7_kernel": "kernels_search.hip", "dist_prefilter_w6_kernel": "kernels_search.hip"}
 # the kernel that dominates each stage on this workload (rocprofv3 names)
 STAGE_KERNEL = {"route": "project_route_kernel", "vote": "vote_map_kernel", "search": "dist_fp32_kernel"}
 COPY_BYTES = 1 << 30
@@ -256,7 +256,7 @@ def main():
     roofline = roofline_of(stages32[dom], STAGE_KERNEL[dom])
     bf16_kernel = "dist_prefilter_w7_kernel" if w.d <= 128 else "dist_prefilter_kernel<0"
     roofline16 = roofline_of(stages16["search"], bf16_kernel)
-    roofline8 = roofline_of(stages8["search"], "dist_prefilter_w5_kernel<1" if w.d <= 128 else "dist_prefilter_kernel<1")
+    roofline8 = roofline_of(stages8["search"], "dist_prefilter_w6_kernel<1" if w.d <= 128 else "dist_prefilter_kernel<1")
     roofline_vote = roofline_of(stages32["vote"], "vote_map_kernel" if w.d <= 128 else "vote_dir_kernel")
 
     # latency of one query call (fp32 arm, all five steps) per batch size:

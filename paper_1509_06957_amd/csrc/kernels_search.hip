@@ -393,13 +393,16 @@ __device__ __forceinline__ void dist_prefilter_body(const float* __restrict__ X,
                                                     float* __restrict__ out_dist, const int64_t q,
                                                     int32_t* __restrict__ keep_out = nullptr) {
     constexpr int GPW = kWave / GB;
-    constexpr int U = 8 / NVB;
+    // rows per group in flight: 8 / NVB, but 4 for the fp8 rows of d <= 128
+    // (eight lanes per row), whose kernel then runs at six waves per SIMD
+    // (8 rows at five waves: 3 % slower)
+    constexpr int U = (FMT == kFmtFp8 && GB == 8 && NVB == 1) ? 4 : 8 / NVB;
     constexpr int EPU = FMT == kFmtBf16 ? 8 : 16;      // row values per 16-byte load
     constexpr int ROWB = FMT == kFmtBf16 ? 2 : 1;       // bytes per row value
     // phase 2 reads float32 rows as the fp32 kernel does: G2 lanes x NV2 float4
     constexpr int GPW2 = kWave / G2;
     constexpr int U2 = 8 / NV2;
-    static_assert(kPfChunk % (kDistWaves * (kWave / GB) * (8 / NVB)) == 0, "a round covers whole steps");
+    static_assert(kPfChunk % (kDistWaves * (kWave / GB) * U) == 0, "a round covers whole steps");
     // phase 1 (round scores and the kept list) and phases 2-3 (distances,
     // order, final slots) use the same LDS
     __shared__ __align__(16) unsigned char pf_smem[kPfBuf * 8];
@@ -736,10 +739,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void d
     dist_prefilter_body<FMT, GB, NVB, G2, NV2>(MRPT_PF_ARGS);
 }
 
-// The fp8 forms of d <= 128 held to 96 registers, five waves per SIMD
-// instead of four (two registers spill; seven waves would spill 37).
+// The fp8 forms of d <= 128 (four rows in flight per group) held to 80
+// registers, six waves per SIMD instead of four, with no spill.
 template <int FMT, int GB, int NVB, int G2, int NV2>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void dist_prefilter_w5_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void dist_prefilter_w6_kernel(
     MRPT_PF_PARAMS) {
     dist_prefilter_body<FMT, GB, NVB, G2, NV2>(MRPT_PF_ARGS);
 }
@@ -773,7 +776,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void d
 }
 
 template <int FMT, int GB, int NVB, int G2, int NV2>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void dist_prefilter_multi_w5_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void dist_prefilter_multi_w6_kernel(
     const SearchItem* __restrict__ items, int32_t nitems, int32_t d, float recheck_rel) {
     const int32_t i = find_item(items, nitems, blockIdx.x);
     const SearchItem& it = items[i];
@@ -796,7 +799,7 @@ void launch_prefilter_form(dim3 grid, hipStream_t s, const float* X, const uint8
         hipLaunchKernelGGL((dist_prefilter_w7_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
                            Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
     else if constexpr (F == kFmtFp8 && GB == 8 && NVB == 1)
-        hipLaunchKernelGGL((dist_prefilter_w5_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
+        hipLaunchKernelGGL((dist_prefilter_w6_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d,
                            Q, s_ids, cap, s_count, k, kp, recheck_rel, out_idx, out_dist);
     else
         hipLaunchKernelGGL((dist_prefilter_kernel<F, GB, NVB, G2, NV2>), grid, dim3(256), 0, s, X, Xq, sn8, d, Q,
@@ -951,11 +954,11 @@ hipError_t launch_search_multi(int32_t form, int32_t d, const SearchItem* items,
     } else if (form >= 300 && form < 400) {
         switch (form - 300) {
             case 0:
-                hipLaunchKernelGGL((dist_prefilter_multi_w5_kernel<kFmtFp8, 8, 1, 16, 1>), grid, block, 0, s,
+                hipLaunchKernelGGL((dist_prefilter_multi_w6_kernel<kFmtFp8, 8, 1, 16, 1>), grid, block, 0, s,
                                    items, nitems, d, recheck_rel);
                 break;
             case 1:
-                hipLaunchKernelGGL((dist_prefilter_multi_w5_kernel<kFmtFp8, 8, 1, 32, 1>), grid, block, 0, s,
+                hipLaunchKernelGGL((dist_prefilter_multi_w6_kernel<kFmtFp8, 8, 1, 32, 1>), grid, block, 0, s,
                                    items, nitems, d, recheck_rel);
                 break;
             case 2: MRPT_PFM(kFmtFp8, 16, 1, 64, 1); break;
