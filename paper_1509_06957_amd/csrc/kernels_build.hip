@@ -18,6 +18,8 @@
 // pass, from the top: a histogram of the current digit over the keys that
 // match the digits found so far, then the bin that holds the wanted rank),
 // and one partition pass moves the keys at or below it to the node's front.
+// A node stops early when the wanted rank is the last key of its bin: the
+// bin then goes left whole, and its lower digits need no pass.
 // Nodes of more than kCutSmallMax keys are cut by many workgroups each
 // (global histograms, one pass per digit); smaller ones by one workgroup
 // per node with its keys in LDS.  The order inside a child is left to the
@@ -117,7 +119,33 @@ struct CutNode {
     unsigned long long krem;
     unsigned long long fill_l, fill_r;
     unsigned long long right_min;
+    unsigned long long left_max;
+    int32_t shift;               // digits at and above it decide the cut; -1 while open
+    int32_t pad_;
 };
+
+// the largest / smallest value over the wave's lanes
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int o) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const unsigned long long t = shfl_xor_u64(v, o);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const unsigned long long t = shfl_xor_u64(v, o);
+        v = t < v ? t : v;
+    }
+    return v;
+}
 
 __global__ void cut_init_kernel(CutNode* __restrict__ st, int64_t gnodes, const int64_t* __restrict__ node_off,
                                 int32_t nodes) {
@@ -130,6 +158,8 @@ __global__ void cut_init_kernel(CutNode* __restrict__ st, int64_t gnodes, const 
     st[g].fill_l = 0ull;
     st[g].fill_r = 0ull;
     st[g].right_min = ~0ull;
+    st[g].left_max = 0ull;
+    st[g].shift = -1;
 }
 
 // the first node of the chunk starting at position p0 of the key array, and
@@ -169,12 +199,19 @@ __global__ __launch_bounds__(kCutThreads) void cut_hist_kernel(const uint64_t* _
     __syncthreads();
     const int64_t g0 = s_g0, b1 = s_b1;
     const bool two = b1 < total && b1 < p0 + kCutChunk;
+    // a decided node takes no more histograms: its keys are not read
+    const bool open0 = st[g0].shift < 0;
+    const bool open1 = two && st[g0 + 1].shift < 0;
+    if (!open0 && !open1) return;
     const uint64_t pre0 = st[g0].prefix;
     const uint64_t pre1 = two ? st[g0 + 1].prefix : 0ull;
     const uint32_t mask = (1u << (top - shift)) - 1u;
+    const int64_t pbeg = open0 ? p0 : b1;                       // the open nodes' positions
+    const int64_t pend = open1 ? p0 + kCutChunk : (b1 < p0 + kCutChunk ? b1 : p0 + kCutChunk);
     for (int e = 0; e < kCutChunk / kCutThreads; ++e) {
         const int64_t p = p0 + e * kCutThreads + tid;
         if (p >= total) break;
+        if (p < pbeg || p >= pend) continue;
         const uint64_t k = keys[p];
         const int slot = p >= b1 ? 1 : 0;
         if (((k ^ (slot ? pre1 : pre0)) >> top) == 0) atomicAdd(&h[slot][(uint32_t)(k >> shift) & mask], 1u);
@@ -189,9 +226,12 @@ __global__ __launch_bounds__(kCutThreads) void cut_hist_kernel(const uint64_t* _
 
 // one wave picks a digit: the bin of h (kCutBins counts) that holds rank
 // *krem, whose count below is taken off *krem and whose value goes into
-// *prefix at `shift`; h is cleared for the next pass
+// *prefix at `shift`; h is cleared for the next pass.  When the wanted rank
+// is the bin's last key, every key of the bin goes left and the cut is
+// decided: *done = shift (the node's keys compare with the prefix from
+// that bit up; the lower digits need no more passes)
 __device__ __forceinline__ void pick_digit(uint32_t* h, unsigned long long* prefix, unsigned long long* krem,
-                                           int32_t shift) {
+                                           int32_t shift, int32_t* done) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
     constexpr int per = kCutBins / kWave;
     uint32_t c[per];
@@ -222,6 +262,7 @@ __device__ __forceinline__ void pick_digit(uint32_t* h, unsigned long long* pref
         }
         *krem = want - below;
         *prefix |= (unsigned long long)(lane * per + b) << shift;
+        if (c[b] == want - below) *done = shift;
     }
 #pragma unroll
     for (int j = 0; j < per; ++j) h[lane * per + j] = 0u;
@@ -230,7 +271,8 @@ __device__ __forceinline__ void pick_digit(uint32_t* h, unsigned long long* pref
 __global__ __launch_bounds__(kWave) void cut_pick_kernel(uint32_t* __restrict__ hist, CutNode* __restrict__ st,
                                                           int32_t shift) {
     const int64_t g = blockIdx.x;
-    pick_digit(hist + g * kCutBins, &st[g].prefix, &st[g].krem, shift);
+    if (st[g].shift >= 0) return;   // decided: its bins stay zero
+    pick_digit(hist + g * kCutBins, &st[g].prefix, &st[g].krem, shift, &st[g].shift);
 }
 
 // the partition of large nodes: keys at or below the node's selected key
@@ -242,7 +284,7 @@ __global__ __launch_bounds__(kCutThreads) void cut_partition_kernel(const uint64
                                                                      uint64_t* __restrict__ out) {
     constexpr int E = kCutChunk / kCutThreads;
     __shared__ uint32_t cnt[2][2];
-    __shared__ unsigned long long base[2][2], rmin[2];
+    __shared__ unsigned long long base[2][2], rmin[2], lmax[2];
     __shared__ int64_t s_g0, s_b1;
     const int tid = (int)threadIdx.x;
     const int64_t p0 = (int64_t)blockIdx.x * kCutChunk;
@@ -253,14 +295,20 @@ __global__ __launch_bounds__(kCutThreads) void cut_partition_kernel(const uint64
         s_b1 = b1;
         cnt[0][0] = cnt[0][1] = cnt[1][0] = cnt[1][1] = 0u;
         rmin[0] = rmin[1] = ~0ull;
+        lmax[0] = lmax[1] = 0ull;
     }
     __syncthreads();
     const int64_t g0 = s_g0, b1 = s_b1;
     const bool two = b1 < total && b1 < p0 + kCutChunk;
-    const uint64_t t0 = st[g0].prefix;
-    const uint64_t t1 = two ? st[g0 + 1].prefix : 0ull;
+    // a key goes right when its bits from the node's deciding digit up
+    // exceed the selected prefix's
+    const int r0 = st[g0].shift < 0 ? 0 : st[g0].shift;
+    const int r1 = two ? (st[g0 + 1].shift < 0 ? 0 : st[g0 + 1].shift) : 0;
+    const uint64_t t0 = st[g0].prefix >> r0;
+    const uint64_t t1 = two ? st[g0 + 1].prefix >> r1 : 0ull;
     uint64_t k[E];
     uint32_t at[E];
+    unsigned long long mn[2] = {~0ull, ~0ull}, mx[2] = {0ull, 0ull};   // per slot, this thread's keys
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int64_t p = p0 + e * kCutThreads + tid;
@@ -269,9 +317,18 @@ __global__ __launch_bounds__(kCutThreads) void cut_partition_kernel(const uint64
         if (p < total) {
             k[e] = keys[p];
             const int slot = p >= b1 ? 1 : 0;
-            const bool right = k[e] > (slot ? t1 : t0);
+            const bool right = (k[e] >> (slot ? r1 : r0)) > (slot ? t1 : t0);
             at[e] = atomicAdd(&cnt[slot][right ? 1 : 0], 1u);
-            if (right) atomicMin(&rmin[slot], (unsigned long long)k[e]);
+            if (right) mn[slot] = k[e] < mn[slot] ? k[e] : mn[slot];
+            else mx[slot] = k[e] > mx[slot] ? k[e] : mx[slot];
+        }
+    }
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+        const unsigned long long wmn = wave_min_u64(mn[slot]), wmx = wave_max_u64(mx[slot]);
+        if ((tid & (kWave - 1)) == 0) {
+            if (wmn != ~0ull) atomicMin(&rmin[slot], wmn);
+            if (wmx != 0ull) atomicMax(&lmax[slot], wmx);
         }
     }
     __syncthreads();
@@ -285,6 +342,9 @@ __global__ __launch_bounds__(kCutThreads) void cut_partition_kernel(const uint64
     } else if (tid < 6) {
         const int slot = tid - 4;
         if ((slot == 0 || two) && rmin[slot] != ~0ull) atomicMin(&st[g0 + slot].right_min, rmin[slot]);
+    } else if (tid < 8) {
+        const int slot = tid - 6;
+        if ((slot == 0 || two) && cnt[slot][0] != 0u) atomicMax(&st[g0 + slot].left_max, lmax[slot]);
     }
     __syncthreads();
 #pragma unroll
@@ -296,7 +356,7 @@ __global__ __launch_bounds__(kCutThreads) void cut_partition_kernel(const uint64
             const int64_t tl = g / nodes;
             const int j = (int)(g - tl * nodes);
             const int64_t lo = node_off[j], m = node_off[j + 1] - lo;
-            const bool right = k[e] > (slot ? t1 : t0);
+            const bool right = (k[e] >> (slot ? r1 : r0)) > (slot ? t1 : t0);
             const int64_t place = (right ? (m + 1) / 2 + (int64_t)base[slot][1] : (int64_t)base[slot][0]) + at[e];
             // exactly ceil(m/2) keys are at or below the selected one (the
             // keys of a tree are distinct), so every place is inside the
@@ -316,7 +376,7 @@ __global__ void cut_splits_kernel(const CutNode* __restrict__ st, int64_t gnodes
     const int64_t tl = g / nodes;
     const int j = (int)(g - tl * nodes);
     const int64_t m = node_off[j + 1] - node_off[j];
-    const float left_max = from_order_bits((uint32_t)(st[g].prefix >> idb));
+    const float left_max = from_order_bits((uint32_t)(st[g].left_max >> idb));
     float split = left_max;
     if ((m & 1) == 0) {
         const float right_min = from_order_bits((uint32_t)(st[g].right_min >> idb));
@@ -336,8 +396,9 @@ __global__ __launch_bounds__(NT) void cut_small_kernel(const uint64_t* __restric
                                                        uint64_t* __restrict__ out, float* __restrict__ splits) {
     extern __shared__ unsigned long long kv[];
     __shared__ uint32_t h[kCutBins];
-    __shared__ unsigned long long s_prefix, s_krem, s_rmin;
+    __shared__ unsigned long long s_prefix, s_krem, s_rmin, s_lmax;
     __shared__ uint32_t s_cnt[2];
+    __shared__ int32_t s_shift;
     const int tid = (int)threadIdx.x;
     const int64_t g = blockIdx.x;
     const int64_t tl = g / nodes;
@@ -351,10 +412,12 @@ __global__ __launch_bounds__(NT) void cut_small_kernel(const uint64_t* __restric
         s_prefix = 0ull;
         s_krem = (unsigned long long)((m + 1) / 2);
         s_rmin = ~0ull;
+        s_lmax = 0ull;
         s_cnt[0] = s_cnt[1] = 0u;
+        s_shift = -1;
     }
     __syncthreads();
-    for (int top = top_bits; top > 0; top -= kCutDigit) {
+    for (int top = top_bits; top > 0 && s_shift < 0; top -= kCutDigit) {
         const int shift = top > kCutDigit ? top - kCutDigit : 0;
         const uint32_t mask = (1u << (top - shift)) - 1u;
         const uint64_t pre = s_prefix;
@@ -363,27 +426,38 @@ __global__ __launch_bounds__(NT) void cut_small_kernel(const uint64_t* __restric
             if (((k ^ pre) >> top) == 0) atomicAdd(&h[(uint32_t)(k >> shift) & mask], 1u);
         }
         __syncthreads();
-        if (tid < kWave) pick_digit(h, &s_prefix, &s_krem, shift);
+        if (tid < kWave) pick_digit(h, &s_prefix, &s_krem, shift, &s_shift);
         __syncthreads();
     }
-    const uint64_t sel = s_prefix;
+    // a key goes left when its bits from the deciding digit up are at most
+    // the selected prefix's (all bits when every pass ran)
+    const int rs = s_shift < 0 ? 0 : s_shift;
+    const uint64_t sel = s_prefix >> rs;
     const int nl = (m + 1) / 2;
     uint64_t* dst = out + tl * n + lo;
+    unsigned long long mn = ~0ull, mx = 0ull;   // this thread's keys: smallest right, largest left
     for (int i = tid; i < m; i += NT) {
         const uint64_t k = kv[i];
         // (places stay inside the node even for a wrong selection)
-        if (k <= sel) {
+        if ((k >> rs) <= sel) {
             const uint32_t at = atomicAdd(&s_cnt[0], 1u);
             if ((int)at < nl) dst[at] = k;
+            mx = k > mx ? k : mx;
         } else {
             const uint32_t at = atomicAdd(&s_cnt[1], 1u);
             if ((int)at < m - nl) dst[nl + at] = k;
-            atomicMin(&s_rmin, (unsigned long long)k);
+            mn = k < mn ? k : mn;
         }
+    }
+    mn = wave_min_u64(mn);
+    mx = wave_max_u64(mx);
+    if ((tid & (kWave - 1)) == 0) {
+        if (mn != ~0ull) atomicMin(&s_rmin, mn);
+        if (mx != 0ull) atomicMax(&s_lmax, mx);
     }
     __syncthreads();
     if (tid == 0) {
-        const float left_max = from_order_bits((uint32_t)(sel >> idb));
+        const float left_max = from_order_bits((uint32_t)(s_lmax >> idb));
         float split = left_max;
         if ((m & 1) == 0) {
             const float right_min = from_order_bits((uint32_t)(s_rmin >> idb));
